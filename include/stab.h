@@ -1,0 +1,138 @@
+/*
+ * stab.h -- C ABI of the MI355X stabilizer-tableau library (libstab.so).
+ *
+ * The library simulates Clifford circuits with single-qubit Z measurements on the
+ * Aaronson-Gottesman (CHP) tableau that the STABSim paper builds on (Sec. 2.3-2.4): 2n rows
+ * (n destabilizers, n stabilizers) of x|z bits plus a sign bit, Clifford gates as per-row bit
+ * rules (Table 1), and measurements that either run rowsum from the first anticommuting
+ * stabilizer (random outcome) or reduce a product of stabilizers into a scratch row
+ * (deterministic outcome; rowsum of Appendix A.2, Alg. 2).  Every kernel is HIP for gfx950.
+ *
+ * Conventions for every call:
+ *   - Return 0 on success or a negative STAB_E* code; stab_last_error() then gives a message
+ *     (thread-local).  Arguments are validated before anything is enqueued, so a call that
+ *     fails validation has no side effect.
+ *   - Device pointers are HIP device memory the caller owns (typically a torch uint8 tensor);
+ *     the library never frees them.  Host pointers are ordinary host memory, written only on
+ *     success.  hip_stream is a hipStream_t (NULL = default stream); every call is synchronous
+ *     with respect to the host unless it says otherwise.
+ *   - A context is not thread-safe.  Distinct contexts are independent.
+ *   - A device error leaves the context unusable (every later call returns STAB_EDEVICE).
+ *
+ * Op-stream format (the input of stab_run / stab_sample):
+ *   An array of stab_instr plus one flat int32 target array.  Instruction k consumes the next
+ *   instr[k].ntargets targets.  Two-qubit kinds (CX, DEP2) consume (a, b) pairs.  Targets of
+ *   one instruction act in order, as if each were its own instruction.
+ *   Randomness: Philox4x64-10 (Salmon et al., SC'11), key = (seed, shot), counter =
+ *   (instruction index, target position, 0, 0), outputs u0..u3.  The instruction index counts
+ *   every instruction a context has executed, TICK included.
+ *     DEP1:   error iff u0 < t0; Pauli 1 + mulhi64(u1, 3) (1=X, 2=Y, 3=Z)
+ *     DEP2:   error iff u0 < t0; k = 1 + mulhi64(u1, 15); Pauli on a = k >> 2, on b = k & 3
+ *     PAULI1: X iff u0 < t0, else Y iff u0 < t1, else Z iff u0 < t2 (cumulative thresholds)
+ *     M/MR/R: a random outcome is u0 >> 63; MR and R then apply X if the outcome is 1 and R
+ *             records nothing.  Records hold 1 bit per M/MR target (1 = eigenvalue -1).
+ */
+#ifndef STAB_H
+#define STAB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define STAB_OK         0
+#define STAB_EINVAL    -1   /* bad argument or malformed op stream */
+#define STAB_ENOMEM    -2   /* buffer too small or device allocation failed */
+#define STAB_EDEVICE   -3   /* HIP runtime error (context poisoned) */
+#define STAB_ERANGE    -4   /* size outside what this build supports */
+#define STAB_EINTERNAL -5   /* an internal consistency check failed on the device */
+
+/* instruction kinds */
+enum {
+    STAB_TICK = 0, STAB_H = 1, STAB_S = 2, STAB_X = 3, STAB_Y = 4, STAB_Z = 5, STAB_CX = 6,
+    STAB_M = 7, STAB_MR = 8, STAB_R = 9, STAB_DEP1 = 10, STAB_DEP2 = 11, STAB_PAULI1 = 12
+};
+
+/* One instruction (32 bytes, no implicit padding). */
+typedef struct stab_instr {
+    uint32_t kind;      /* STAB_* kind */
+    uint32_t ntargets;  /* int32 targets consumed (even for CX and DEP2) */
+    uint64_t t0, t1, t2;/* noise thresholds (see the format above); 0 otherwise */
+} stab_instr;
+
+/* Storage modes.  SHARED keeps one x|z tableau and one sign vector per shot: exact because
+ * x|z never depends on signs, outcomes or Pauli noise (only signs do).  FULL keeps one
+ * complete tableau per shot. */
+#define STAB_MODE_SHARED 0
+#define STAB_MODE_FULL   1
+
+typedef struct stab_ctx stab_ctx;
+
+/* Largest qubit count this build supports (one 64-row band of the tableau must fit in the
+ * 160 KB of LDS of one compute unit). */
+int32_t stab_max_qubits(void);
+
+/* Bytes of device memory a context needs in dev_buf for n qubits and `shots` shots in the
+ * given mode.  Writes *bytes_out.  Errors: STAB_EINVAL (n < 1, shots < 1, bad mode),
+ * STAB_ERANGE (n > stab_max_qubits()). */
+int stab_tableau_bytes(int32_t n, int32_t shots, int32_t mode, uint64_t *bytes_out);
+
+/* Create a context holding `shots` tableaux of n qubits in |0...0> (destabilizer i = +X_i,
+ * stabilizer i = +Z_i; the initial state the paper leaves implicit), stored in dev_buf
+ * (>= stab_tableau_bytes bytes, 256-byte aligned, owned by the caller, which must keep it
+ * alive until stab_destroy).  The RNG key is (seed, first_shot + b) for shot b.
+ * Errors: STAB_EINVAL, STAB_ERANGE, STAB_ENOMEM (buffer too small), STAB_EDEVICE. */
+int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot,
+                void *dev_buf, uint64_t buf_bytes, void *hip_stream, stab_ctx **out);
+
+/* Release the context's own scratch memory.  Never frees dev_buf.  NULL is ignored. */
+void stab_destroy(stab_ctx *ctx);
+
+/* Run an op stream on every shot of the context (the paper's sim(circuit), Sec. 3.1.4, and
+ * the race-safe gate/measurement ordering of Fig. 2).  Measurement outcomes are written to
+ * out_bits (host, may be NULL when the stream records nothing): shot b's bits start at byte
+ * b * ceil(nrec / 8), LSB first, where nrec = number of M/MR targets in the stream.  The
+ * instruction counter advances by ninstr.  Errors: STAB_EINVAL (malformed stream, target out
+ * of range, CX with equal qubits), STAB_ENOMEM, STAB_EDEVICE, STAB_EINTERNAL. */
+int stab_run(stab_ctx *ctx, const stab_instr *instrs, int32_t ninstr, const int32_t *targets,
+             int64_t ntargets, uint8_t *out_bits);
+
+/* Apply gate and noise instructions only (no measurement kinds): a layer, or several, of
+ * Clifford gates (Table 1) and Pauli channels.  Same as stab_run otherwise. */
+int stab_apply_layer(stab_ctx *ctx, const stab_instr *instrs, int32_t ninstr,
+                     const int32_t *targets, int64_t ntargets);
+
+/* Measure qubits[0..k-1] in Z, in order (one M instruction; MR/R via `kind`), writing
+ * ceil(k/8) bytes per shot to out_bits (host; NULL allowed for R).  Pivot search, rowsum
+ * and the deterministic reduction follow Sec. 2.4 and Alg. 2 of the paper. */
+int stab_measure(stab_ctx *ctx, uint32_t kind, const int32_t *qubits, int32_t k,
+                 uint8_t *out_bits);
+
+/* Copy one shot's tableau to the host in row-major bytes: x[2n][n], z[2n][n] (0/1 per byte),
+ * r[2n]; rows 0..n-1 destabilizers, n..2n-1 stabilizers.  Any pointer may be NULL. */
+int stab_get_tableau(stab_ctx *ctx, int32_t shot, uint8_t *x, uint8_t *z, uint8_t *r);
+
+/* One-call sampler: create a context on dev_buf, run the stream, write the packed record
+ * (shots * ceil(nrec/8) bytes) to out_bits, destroy the context.  elapsed_ms (may be NULL)
+ * receives the device time from the first kernel to the record on the host. */
+int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets,
+                int64_t ntargets, int32_t n, int32_t shots, int32_t mode, uint64_t seed,
+                void *dev_buf, uint64_t buf_bytes, void *hip_stream, uint8_t *out_bits,
+                float *elapsed_ms);
+
+/* Work counters accumulated by a context since creation (for bandwidth accounting):
+ * counters[0] gate-ops x bands, [1] bands staged by the segment kernel, [2] deterministic
+ * measurements, [3] stabilizer rows read by deterministic measurements, [4] random
+ * measurements, [5] rows updated by rowsum, [6] measurements that turned deterministic
+ * within a layer, [7] noise events.  ncounters <= 8.  Synchronizes the stream. */
+int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
+
+/* Message of the last error on this thread ("" if none). */
+const char *stab_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STAB_H */
