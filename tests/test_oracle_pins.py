@@ -172,11 +172,6 @@ def _sv_check(n, circ, seed, shot):
             ri = 0
             for j, q in enumerate(targ):
                 p1 = sv.prob_one(q)
-                # the outcome the oracle reports for this target
-                if kind == Cc.R:
-                    # R records nothing: recover it from whether the qubit needed a flip --
-                    # instead compare via the flag and project on both consistent branches
-                    pass
                 if flags[j] == 0:
                     assert p1 < 1e-9 or p1 > 1 - 1e-9, "oracle says deterministic"
                     out = int(p1 > 0.5)
@@ -454,3 +449,85 @@ def test_malformed_stream_rejected():
     instr["ntargets"] = 2
     with pytest.raises(ValueError):
         t.execute(instr, np.array([0, 9], dtype=np.int32))
+
+
+# ---------------------------------------------------------------- hand-worked conventions --------
+def _pauli_str(x, z):
+    return "".join("IXZY"[int(a) + 2 * int(b)] for a, b in zip(x, z))
+
+
+def test_hand_worked_random_measurements():
+    """Expected tableaux are derived by hand in tests/golden/hand_worked_measurements.txt."""
+    # Case A: the pivot is the FIRST anticommuting stabilizer (reading of Sec. 2.4)
+    for shot in range(8):
+        c = Cc.Circuit(n=2)
+        c.gate(Cc.H, [0, 1])
+        c.gate(Cc.CX, [0, 1])
+        c.append(Cc.M, [1])
+        instr, tg = c.arrays()
+        t = O.Tableau(2)
+        m = int(t.execute(instr, tg, seed=3, shot=shot)[0])
+        x, z, r = t.get()
+        rows = [(int(r[i]), _pauli_str(x[i], z[i])) for i in range(4)]
+        assert rows == [(0, "XX"), (0, "ZZ"), (m, "IZ"), (0, "XI")]
+    # Case B: the destabilizer receives the pivot row WITH its sign
+    for shot in range(8):
+        c = Cc.Circuit(n=1)
+        c.gate(Cc.H, [0])
+        c.gate(Cc.Z, [0])
+        c.append(Cc.M, [0])
+        instr, tg = c.arrays()
+        t = O.Tableau(1)
+        m = int(t.execute(instr, tg, seed=3, shot=shot)[0])
+        x, z, r = t.get()
+        assert [(int(r[i]), _pauli_str(x[i], z[i])) for i in range(2)] == [(1, "X"), (m, "Z")]
+
+
+def _numpy_block(seed, shot, instr, pos):
+    """Philox block for counter (instr, pos, 0, 0), instr >= 1, from numpy's implementation
+    (which advances the counter before producing each block)."""
+    assert instr >= 1
+    bg = np.random.Philox(key=np.array([seed, shot], dtype=np.uint64),
+                          counter=np.array([instr - 1, pos, 0, 0], dtype=np.uint64))
+    return [int(v) for v in bg.random_raw(4)]
+
+
+def test_draw_format_exact():
+    """Noise and outcome draws follow the op-stream format exactly (numpy Philox as RNG)."""
+    n = 6
+    seed = 99
+    p = 0.4
+    px, py, pz = 0.2, 0.1, 0.3
+    c = Cc.Circuit(n=n)
+    c.tick()                                         # instruction 0
+    c.dep1(p, [0, 1, 2])                             # 1
+    c.dep2(p, [3, 4, 5, 0])                          # 2
+    c.pauli1(px, py, pz, [1, 2])                     # 3
+    c.append(Cc.M, list(range(n)))                   # 4
+    c.gate(Cc.H, [0, 1, 2])                          # 5
+    c.append(Cc.M, [0, 1, 2])                        # 6: random outcomes u0 >> 63
+    T = Cc.threshold(p)
+    tx, txy, txyz = Cc.pauli1_thresholds(px, py, pz)
+    rec = O.run(c, 64, seed=seed)
+    for shot in range(64):
+        flip = [0] * n                               # x-part of the accumulated Pauli per qubit
+        for q in range(3):
+            u = _numpy_block(seed, shot, 1, q)
+            if u[0] < T:
+                P = 1 + ((u[1] * 3) >> 64)
+                flip[[0, 1, 2][q]] ^= P in (1, 2)
+        pairs = [(3, 4), (5, 0)]
+        for j, (a, b) in enumerate(pairs):
+            u = _numpy_block(seed, shot, 2, j)
+            if u[0] < T:
+                k = 1 + ((u[1] * 15) >> 64)
+                flip[a] ^= (k >> 2) in (1, 2)
+                flip[b] ^= (k & 3) in (1, 2)
+        for j, q in enumerate([1, 2]):
+            u = _numpy_block(seed, shot, 3, j)
+            if u[0] < tx or (tx <= u[0] < txy):
+                flip[q] ^= 1
+        want = [int(f) for f in flip]
+        for q in range(3):
+            want.append(_numpy_block(seed, shot, 6, q)[0] >> 63)
+        assert list(rec[shot]) == want, shot
