@@ -32,8 +32,8 @@
  *     M/MR/R: a random outcome is u0 >> 63; MR and R then apply X if the outcome is 1 and R
  *             records nothing.  Records hold 1 bit per M/MR target (1 = eigenvalue -1).
  */
-#ifndef STAB_H
-#define STAB_H
+#ifndef LIBSTAB_ABI_H_
+#define LIBSTAB_ABI_H_
 
 #include <stdint.h>
 
@@ -114,6 +114,30 @@ int stab_measure(stab_ctx *ctx, uint32_t kind, const int32_t *qubits, int32_t k,
  * r[2n]; rows 0..n-1 destabilizers, n..2n-1 stabilizers.  Any pointer may be NULL. */
 int stab_get_tableau(stab_ctx *ctx, int32_t shot, uint8_t *x, uint8_t *z, uint8_t *r);
 
+/* A compiled op stream: validated, split into gate/noise segments and measurement layers,
+ * and uploaded to the device once, so it can be executed many times.  The RNG instruction
+ * index is taken relative to the context's counter at execution time. */
+typedef struct stab_program stab_program;
+
+/* Compile a stream for the context's geometry (n, shots).  Errors: STAB_EINVAL (malformed
+ * stream, target out of range, CX with equal qubits, target count mismatch), STAB_ENOMEM,
+ * STAB_EDEVICE. */
+int stab_compile(stab_ctx *ctx, const stab_instr *instrs, int32_t ninstr,
+                 const int32_t *targets, int64_t ntargets, stab_program **out);
+
+/* Execute a compiled stream (same semantics and out_bits layout as stab_run).  If elapsed_ms
+ * is not NULL it receives the device time from the first kernel to the record on the host. */
+int stab_execute(stab_ctx *ctx, stab_program *prog, uint8_t *out_bits, float *elapsed_ms);
+
+/* Number of M/MR targets a compiled stream records per shot. */
+int64_t stab_program_records(const stab_program *prog);
+
+void stab_program_destroy(stab_program *prog);
+
+/* Put every shot back in |0...0>, set the RNG key to (seed, first_shot + b) and the
+ * instruction counter to 0. */
+int stab_reset(stab_ctx *ctx, uint64_t seed, uint64_t first_shot);
+
 /* One-call sampler: create a context on dev_buf, run the stream, write the packed record
  * (shots * ceil(nrec/8) bytes) to out_bits, destroy the context.  elapsed_ms (may be NULL)
  * receives the device time from the first kernel to the record on the host. */
@@ -135,4 +159,4 @@ const char *stab_last_error(void);
 #ifdef __cplusplus
 }
 #endif
-#endif /* STAB_H */
+#endif /* LIBSTAB_ABI_H_ */

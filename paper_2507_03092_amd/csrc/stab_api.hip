@@ -1,0 +1,691 @@
+// stab_api.hip -- host side of libstab: argument validation, compilation of an op stream into
+// gate/noise segments and measurement layers, device buffers and the C ABI of include/stab.h.
+//
+// Execution order of one stream (the race-safe order of Fig. 2 of the paper): all gates and
+// noise up to a measurement layer run in one segment kernel per 64-row band; a measurement
+// layer then runs classify -> deterministic batch -> in-order random chain -> reset/record.
+#include "stab_kernels.hip"
+#include "stab.h"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace stabdev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
+constexpr int kSegThreads = 1024;
+constexpr int kChainThreads = 512;
+constexpr int kMCap = 32;                 // rows listed per deterministic measurement
+constexpr int kRedWords = 16;
+constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
+
+int seg_lds_words(int RS) { return 64 * (RS + 1) + kRedWords; }
+
+int max_qubits_for_lds(int lds_bytes)
+{
+    // 64 * (2*Wc + 1) + kRedWords words must fit
+    const int words = lds_bytes / 8 - kRedWords;
+    const int wc = (words / 64 - 1) / 2;
+    return std::min(wc, 64 * kMaxWordsPerLane) * 64;
+}
+
+Geom make_geom(int n, int shots, int mode)
+{
+    Geom g{};
+    g.n = n;
+    g.Wc = (n + 63) / 64;
+    g.Wr = g.Wc;
+    g.NR = 64 * g.Wr;
+    g.RS = 2 * g.Wc;
+    g.NB = 2 * g.Wr;
+    g.B = shots;
+    g.S = (mode == STAB_MODE_SHARED) ? 1 : shots;
+    g.bpc = g.B / g.S;
+    return g;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t tab, rs, rd, total;
+};
+
+Layout layout_of(const Geom& g)
+{
+    Layout L{};
+    L.tab = 0;
+    L.rs = align256(L.tab + (size_t)g.S * 2 * g.NR * g.RS * 8);
+    L.rd = align256(L.rs + (size_t)g.S * g.NB * 8);
+    L.total = align256(L.rd + (size_t)g.B * g.NB * 8);
+    return L;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct stab_ctx {
+    Geom g{};
+    int mode = 0;
+    uint64_t seed = 0, first_shot = 0, instr_counter = 0;
+    hipStream_t stream = nullptr;
+    uint64_t* tab = nullptr;
+    uint64_t* rs = nullptr;
+    uint64_t* rd = nullptr;
+    bool poisoned = false;
+    int max_lds = kLdsBytes;
+    int* d_err = nullptr;
+    unsigned long long* d_counters = nullptr;
+    int* d_tmap = nullptr;
+    DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+struct SegPlan {
+    int item_begin = 0, item_count = 0;
+    int modifies = 0;
+    int noise_begin = 0, noise_count = 0;
+    int units = 0;
+    long long ev_cap = 0;
+    int meas = -1;
+    long long gate_count = 0;
+};
+
+struct MeasPlan {
+    uint64_t instr;   // relative instruction index
+    int kind;
+    int pos_base;     // position of the first target within its instruction
+    int tq_begin;
+    int K;
+    long long rec_off;
+};
+
+}  // namespace
+
+struct stab_program {
+    int ninstr = 0;
+    long long nrec = 0;
+    int Kmax = 0;
+    long long ev_cap_max = 0;
+    int nnoise = 0;
+    std::vector<SegPlan> segs;
+    std::vector<MeasPlan> meas;
+    std::vector<std::pair<int, int>> steps;   // (0, segment) or (1, measurement layer)
+    // device copies
+    void* dev = nullptr;
+    int4* d_items = nullptr;
+    uint2* d_gates = nullptr;
+    NoiseDesc* d_noise = nullptr;
+    int* d_noise_tg = nullptr;
+    int* d_unit_start = nullptr;
+    int* d_ev_base = nullptr;
+    int* d_ev_count = nullptr;
+    int* d_mtq = nullptr;
+    // geometry it was compiled for
+    int n = 0, B = 0;
+};
+
+namespace {
+
+int ensure(DevBuf& b, size_t bytes)
+{
+    if (bytes <= b.cap) return STAB_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    bytes = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        return fail(STAB_ENOMEM, "device allocation failed");
+    }
+    b.cap = bytes;
+    return STAB_OK;
+}
+
+#define HIP_CHECK(ctx, call)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            (ctx)->poisoned = true;                                                            \
+            return fail(STAB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+        }                                                                                      \
+    } while (0)
+
+bool valid_kind(uint32_t k) { return k <= STAB_PAULI1; }
+
+// Split an op stream into segments (gate layers on disjoint qubits and noise layers) and
+// measurement layers (disjoint qubits); see the file header.
+int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32_t* tg,
+                   int64_t ntg, stab_program& P, std::vector<int4>& items,
+                   std::vector<uint2>& gates, std::vector<NoiseDesc>& noise,
+                   std::vector<int>& noise_tg, std::vector<int>& unit_start,
+                   std::vector<int>& ev_base, std::vector<int>& mtq)
+{
+    if (ninstr < 0 || ntg < 0) return fail(STAB_EINVAL, "negative count");
+    if ((ninstr > 0 && !ins) || (ntg > 0 && !tg)) return fail(STAB_EINVAL, "null stream");
+    const int n = g.n;
+    std::vector<int> stamp(n, -1), mstamp(n, -1);
+    int layer_id = 0, mlayer_id = 0;
+    SegPlan seg;
+    int open_begin = -1;
+    long long rec_off = 0;
+
+    auto close_layer = [&]() {
+        if (open_begin >= 0) {
+            const int cnt = (int)gates.size() - open_begin;
+            if (cnt > 0) {
+                items.push_back(make_int4(0, open_begin, cnt, -1));
+                seg.item_count++;
+                seg.gate_count += cnt;
+            }
+            open_begin = -1;
+        }
+        ++layer_id;
+    };
+    auto close_seg = [&](int meas_index) {
+        close_layer();
+        seg.meas = meas_index;
+        P.steps.push_back({0, (int)P.segs.size()});
+        P.ev_cap_max = std::max(P.ev_cap_max, seg.ev_cap);
+        P.segs.push_back(seg);
+        seg = SegPlan();
+        seg.item_begin = (int)items.size();
+        seg.noise_begin = (int)noise.size();
+    };
+
+    int64_t off = 0;
+    for (int k = 0; k < ninstr; ++k) {
+        const uint32_t kind = ins[k].kind, nt = ins[k].ntargets;
+        if (!valid_kind(kind)) return fail(STAB_EINVAL, "instruction " + std::to_string(k) + ": unknown kind");
+        if (off + (int64_t)nt > ntg) return fail(STAB_EINVAL, "instruction " + std::to_string(k) + ": targets run past the target array");
+        if ((kind == STAB_CX || kind == STAB_DEP2) && (nt & 1u))
+            return fail(STAB_EINVAL, "instruction " + std::to_string(k) + ": odd target count for a two-qubit kind");
+        const int32_t* t = tg + off;
+        for (uint32_t q = 0; q < nt; ++q)
+            if (t[q] < 0 || t[q] >= n)
+                return fail(STAB_EINVAL, "instruction " + std::to_string(k) + ": target " + std::to_string(t[q]) + " out of range");
+        switch (kind) {
+        case STAB_TICK:
+            break;
+        case STAB_H: case STAB_S: case STAB_X: case STAB_Y: case STAB_Z:
+            for (uint32_t q = 0; q < nt; ++q) {
+                if (stamp[t[q]] == layer_id) close_layer();
+                if (open_begin < 0) open_begin = (int)gates.size();
+                stamp[t[q]] = layer_id;
+                gates.push_back(make_uint2(kind | ((uint32_t)t[q] << 4), 0u));
+                if (kind == STAB_H || kind == STAB_S) seg.modifies = 1;
+            }
+            break;
+        case STAB_CX:
+            for (uint32_t q = 0; q < nt; q += 2) {
+                const int c = t[q], d = t[q + 1];
+                if (c == d) return fail(STAB_EINVAL, "instruction " + std::to_string(k) + ": CX with equal qubits");
+                if (stamp[c] == layer_id || stamp[d] == layer_id) close_layer();
+                if (open_begin < 0) open_begin = (int)gates.size();
+                stamp[c] = stamp[d] = layer_id;
+                gates.push_back(make_uint2(kind | ((uint32_t)c << 4), (uint32_t)d));
+                seg.modifies = 1;
+            }
+            break;
+        case STAB_DEP1: case STAB_DEP2: case STAB_PAULI1: {
+            close_layer();
+            const int units = (kind == STAB_DEP2) ? (int)nt / 2 : (int)nt;
+            if (units == 0) break;
+            NoiseDesc d{};
+            d.instr = (uint64_t)k;
+            d.t0 = ins[k].t0;
+            d.t1 = ins[k].t1;
+            d.t2 = ins[k].t2;
+            d.kind = (int)kind;
+            d.toff = (int)noise_tg.size();
+            d.units = units;
+            d.bucket = (int)noise.size();
+            noise_tg.insert(noise_tg.end(), t, t + nt);
+            unit_start.push_back(seg.units);
+            seg.units += units;
+            ev_base.push_back((int)seg.ev_cap);
+            seg.ev_cap += (long long)units * (kind == STAB_DEP2 ? 2 : 1) * g.B;
+            if (seg.ev_cap > (1ll << 31) - 1) return fail(STAB_ERANGE, "too many noise locations in one segment");
+            noise.push_back(d);
+            seg.noise_count++;
+            items.push_back(make_int4(1, 0, 0, d.bucket));
+            seg.item_count++;
+        } break;
+        case STAB_M: case STAB_MR: case STAB_R: {
+            uint32_t q = 0;
+            while (q < nt) {
+                ++mlayer_id;
+                const uint32_t begin = q;
+                while (q < nt && mstamp[t[q]] != mlayer_id) mstamp[t[q++]] = mlayer_id;
+                MeasPlan m{};
+                m.instr = (uint64_t)k;
+                m.kind = (int)kind;
+                m.pos_base = (int)begin;
+                m.tq_begin = (int)mtq.size();
+                m.K = (int)(q - begin);
+                m.rec_off = rec_off;
+                mtq.insert(mtq.end(), t + begin, t + q);
+                if (kind != STAB_R) rec_off += m.K;
+                close_seg((int)P.meas.size());
+                P.steps.push_back({1, (int)P.meas.size()});
+                P.Kmax = std::max(P.Kmax, m.K);
+                P.meas.push_back(m);
+            }
+        } break;
+        default:
+            return fail(STAB_EINVAL, "unknown kind");
+        }
+        off += nt;
+    }
+    if (off != ntg) return fail(STAB_EINVAL, "target array longer than the instructions consume");
+    close_seg(-1);
+    P.ninstr = ninstr;
+    P.nrec = rec_off;
+    P.nnoise = (int)noise.size();
+    return STAB_OK;
+}
+
+template <typename T>
+size_t put(std::vector<char>& blob, const std::vector<T>& v)
+{
+    const size_t at = align256(blob.size());
+    blob.resize(at + std::max<size_t>(v.size() * sizeof(T), 1));
+    if (!v.empty()) std::memcpy(blob.data() + at, v.data(), v.size() * sizeof(T));
+    return at;
+}
+
+int launch_init(stab_ctx* ctx)
+{
+    const Geom& g = ctx->g;
+    const size_t words = (size_t)g.S * 2 * g.NR * g.RS;
+    const int blocks = (int)std::min<size_t>((words + 255) / 256, 65536);
+    k_init<<<blocks, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd);
+    HIP_CHECK(ctx, hipGetLastError());
+    HIP_CHECK(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream));
+    return STAB_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* stab_last_error(void) { return g_err.c_str(); }
+
+int32_t stab_max_qubits(void) { return max_qubits_for_lds(kLdsBytes); }
+
+int stab_tableau_bytes(int32_t n, int32_t shots, int32_t mode, uint64_t* bytes_out)
+{
+    if (!bytes_out) return fail(STAB_EINVAL, "bytes_out is NULL");
+    if (n < 1 || shots < 1) return fail(STAB_EINVAL, "n and shots must be >= 1");
+    if (shots > kMaxShots) return fail(STAB_ERANGE, "shots exceeds 65535");
+    if (mode != STAB_MODE_SHARED && mode != STAB_MODE_FULL) return fail(STAB_EINVAL, "bad mode");
+    if (n > stab_max_qubits()) return fail(STAB_ERANGE, "n exceeds stab_max_qubits()");
+    *bytes_out = layout_of(make_geom(n, shots, mode)).total;
+    return STAB_OK;
+}
+
+int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot,
+                void* dev_buf, uint64_t buf_bytes, void* hip_stream, stab_ctx** out)
+{
+    if (!out) return fail(STAB_EINVAL, "out is NULL");
+    *out = nullptr;
+    uint64_t need = 0;
+    int rc = stab_tableau_bytes(n, shots, mode, &need);
+    if (rc) return rc;
+    if (!dev_buf) return fail(STAB_EINVAL, "dev_buf is NULL");
+    if (((uintptr_t)dev_buf & 255u) != 0) return fail(STAB_EINVAL, "dev_buf must be 256-byte aligned");
+    if (buf_bytes < need) return fail(STAB_ENOMEM, "dev_buf smaller than stab_tableau_bytes()");
+
+    stab_ctx* ctx = new stab_ctx();
+    ctx->g = make_geom(n, shots, mode);
+    ctx->mode = mode;
+    ctx->seed = seed;
+    ctx->first_shot = first_shot;
+    ctx->stream = (hipStream_t)hip_stream;
+    const Layout L = layout_of(ctx->g);
+    char* base = (char*)dev_buf;
+    ctx->tab = (uint64_t*)(base + L.tab);
+    ctx->rs = (uint64_t*)(base + L.rs);
+    ctx->rd = (uint64_t*)(base + L.rd);
+
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        delete ctx;
+        return fail(STAB_EDEVICE, "no HIP device");
+    }
+    ctx->max_lds = lds;
+    const int seg_bytes = seg_lds_words(ctx->g.RS) * 8;
+    if (seg_bytes > lds) {
+        delete ctx;
+        return fail(STAB_ERANGE, "a 64-row band does not fit in this device's LDS");
+    }
+    (void)hipFuncSetAttribute((const void*)k_segment, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipGetLastError();
+
+    bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
+              hipMalloc((void**)&ctx->d_counters, 8 * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&ctx->d_tmap, (size_t)ctx->g.S * n * sizeof(int)) == hipSuccess &&
+              hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
+    if (!ok) {
+        stab_destroy(ctx);
+        return fail(STAB_ENOMEM, "device allocation failed");
+    }
+    if (hipMemsetAsync(ctx->d_counters, 0, 8 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_tmap, 0xFF, (size_t)ctx->g.S * n * sizeof(int), ctx->stream) != hipSuccess) {
+        stab_destroy(ctx);
+        return fail(STAB_EDEVICE, "memset failed");
+    }
+    rc = launch_init(ctx);
+    if (rc == STAB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(STAB_EDEVICE, "init failed");
+    if (rc) {
+        stab_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return STAB_OK;
+}
+
+void stab_destroy(stab_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount,
+                      &ctx->obuf, &ctx->events, &ctx->record, &ctx->packed};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->d_err) (void)hipFree(ctx->d_err);
+    if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+    if (ctx->d_tmap) (void)hipFree(ctx->d_tmap);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+int stab_reset(stab_ctx* ctx, uint64_t seed, uint64_t first_shot)
+{
+    if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");
+    if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
+    ctx->seed = seed;
+    ctx->first_shot = first_shot;
+    ctx->instr_counter = 0;
+    int rc = launch_init(ctx);
+    if (rc) return rc;
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return STAB_OK;
+}
+
+int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const int32_t* targets,
+                 int64_t ntargets, stab_program** out)
+{
+    if (!ctx || !out) return fail(STAB_EINVAL, "null argument");
+    *out = nullptr;
+    if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
+    stab_program* P = new stab_program();
+    std::vector<int4> items;
+    std::vector<uint2> gates;
+    std::vector<NoiseDesc> noise;
+    std::vector<int> noise_tg, unit_start, ev_base, mtq;
+    int rc = compile_stream(ctx->g, instrs, ninstr, targets, ntargets, *P, items, gates, noise,
+                            noise_tg, unit_start, ev_base, mtq);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    P->n = ctx->g.n;
+    P->B = ctx->g.B;
+    std::vector<char> blob;
+    const size_t o_items = put(blob, items), o_gates = put(blob, gates), o_noise = put(blob, noise);
+    const size_t o_ntg = put(blob, noise_tg), o_us = put(blob, unit_start), o_eb = put(blob, ev_base);
+    const size_t o_ec = put(blob, std::vector<int>(std::max<int>(P->nnoise, 1), 0));
+    const size_t o_mtq = put(blob, mtq);
+    if (hipMalloc(&P->dev, blob.size()) != hipSuccess) {
+        delete P;
+        return fail(STAB_ENOMEM, "device allocation failed");
+    }
+    if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(P->dev);
+        delete P;
+        ctx->poisoned = true;
+        return fail(STAB_EDEVICE, "program upload failed");
+    }
+    char* d = (char*)P->dev;
+    P->d_items = (int4*)(d + o_items);
+    P->d_gates = (uint2*)(d + o_gates);
+    P->d_noise = (NoiseDesc*)(d + o_noise);
+    P->d_noise_tg = (int*)(d + o_ntg);
+    P->d_unit_start = (int*)(d + o_us);
+    P->d_ev_base = (int*)(d + o_eb);
+    P->d_ev_count = (int*)(d + o_ec);
+    P->d_mtq = (int*)(d + o_mtq);
+    *out = P;
+    return STAB_OK;
+}
+
+int64_t stab_program_records(const stab_program* prog) { return prog ? prog->nrec : -1; }
+
+void stab_program_destroy(stab_program* prog)
+{
+    if (!prog) return;
+    if (prog->dev) (void)hipFree(prog->dev);   // implicitly waits for work that uses it
+    delete prog;
+}
+
+int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elapsed_ms)
+{
+    if (!ctx || !P) return fail(STAB_EINVAL, "null argument");
+    if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
+    const Geom& g = ctx->g;
+    if (P->n != g.n || P->B != g.B) return fail(STAB_EINVAL, "program compiled for another geometry");
+    if (P->nrec > 0 && !out_bits) return fail(STAB_EINVAL, "out_bits is NULL but the stream records outcomes");
+    const size_t K = (size_t)std::max(P->Kmax, 1);
+    int rc;
+    if ((rc = ensure(ctx->xcol, (size_t)g.S * g.NB * K * 8)) || (rc = ensure(ctx->zcol, (size_t)g.S * g.NB * K * 8)) ||
+        (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->mcount, (size_t)g.S * K * 4)) ||
+        (rc = ensure(ctx->mlist, (size_t)g.S * kMCap * K * 4)) || (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
+        (rc = ensure(ctx->events, (size_t)std::max<long long>(P->ev_cap_max, 1) * 8)) ||
+        (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
+        (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))))
+        return rc;
+    uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
+    uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
+    int* cls = (int*)ctx->cls.p;
+    int* mcount = (int*)ctx->mcount.p;
+    int* mlist = (int*)ctx->mlist.p;
+    uint8_t* obuf = (uint8_t*)ctx->obuf.p;
+    uint2* events = (uint2*)ctx->events.p;
+    uint8_t* record = (uint8_t*)ctx->record.p;
+    const uint64_t base = ctx->instr_counter;
+
+    const int lds_rd = (seg_lds_words(g.RS) + g.bpc) * 8 <= ctx->max_lds ? 1 : 0;
+    const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 8;
+    const size_t chain_lds = (size_t)(2 * g.RS + 2 * g.NB + (g.bpc + 63) / 64) * 8 + (size_t)g.NB * 4 + 64;
+    if (chain_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
+
+    HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (P->nnoise > 0)
+        HIP_CHECK(ctx, hipMemsetAsync(P->d_ev_count, 0, (size_t)P->nnoise * sizeof(int), ctx->stream));
+    for (const auto& st : P->steps) {
+        if (st.first == 0) {
+            const SegPlan& sp = P->segs[st.second];
+            if (sp.noise_count > 0) {
+                const long long work = (long long)sp.units * g.B;
+                const int blocks = (int)std::min<long long>((work + 255) / 256, 1 << 16);
+                k_noise_draw<<<blocks, 256, 0, ctx->stream>>>(
+                    P->d_noise + sp.noise_begin, sp.noise_count, P->d_unit_start + sp.noise_begin,
+                    sp.units, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
+                    P->d_ev_base, P->d_ev_count);
+                HIP_CHECK(ctx, hipGetLastError());
+            }
+            if (sp.item_count > 0 || sp.meas >= 0) {
+                SegArgs a{};
+                a.items = P->d_items + sp.item_begin;
+                a.nitems = sp.item_count;
+                a.gates = P->d_gates;
+                a.events = events;
+                a.ev_count = P->d_ev_count;
+                a.ev_base = P->d_ev_base;
+                a.write_back = sp.modifies;
+                a.lds_rd = lds_rd;
+                if (sp.meas >= 0) {
+                    const MeasPlan& m = P->meas[sp.meas];
+                    a.ext_q = P->d_mtq + m.tq_begin;
+                    a.K = m.K;
+                } else {
+                    a.ext_q = nullptr;
+                    a.K = 0;
+                }
+                a.Xcol = Xcol;
+                a.Zcol = Zcol;
+                k_segment<<<dim3(g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a);
+                HIP_CHECK(ctx, hipGetLastError());
+            }
+        } else {
+            const MeasPlan& m = P->meas[st.second];
+            const int K2 = m.K;
+            k_classify<<<dim3((K2 + 255) / 256, g.S), 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap);
+            HIP_CHECK(ctx, hipGetLastError());
+            k_det<<<dim3((K2 + 3) / 4, g.S), 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
+                                                                   mcount, kMCap, obuf, ctx->d_err, ctx->d_counters);
+            HIP_CHECK(ctx, hipGetLastError());
+            k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+                g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin, ctx->d_tmap,
+                ctx->seed, ctx->first_shot, base + m.instr, m.pos_base, obuf, ctx->d_err, ctx->d_counters);
+            HIP_CHECK(ctx, hipGetLastError());
+            const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
+            k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(g, ctx->rd, Zcol, obuf, K2, do_reset, record,
+                                                                     (long long)P->nrec, m.rec_off, do_record);
+            HIP_CHECK(ctx, hipGetLastError());
+        }
+    }
+    const long long nbytes = (P->nrec + 7) / 8;
+    std::vector<uint8_t> host;
+    if (P->nrec > 0) {
+        const long long total = nbytes * g.B;
+        const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
+        k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p);
+        HIP_CHECK(ctx, hipGetLastError());
+        host.resize((size_t)total);
+        HIP_CHECK(ctx, hipMemcpyAsync(host.data(), ctx->packed.p, (size_t)total, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_CHECK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    int err = 0;
+    HIP_CHECK(ctx, hipMemcpy(&err, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+        ctx->poisoned = true;
+        return fail(STAB_EINTERNAL, "device consistency check failed (code " + std::to_string(err) + ")");
+    }
+    if (elapsed_ms) HIP_CHECK(ctx, hipEventElapsedTime(elapsed_ms, ctx->ev0, ctx->ev1));
+    if (P->nrec > 0) std::memcpy(out_bits, host.data(), host.size());
+    ctx->instr_counter += (uint64_t)P->ninstr;
+    return STAB_OK;
+}
+
+int stab_run(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const int32_t* targets,
+             int64_t ntargets, uint8_t* out_bits)
+{
+    stab_program* P = nullptr;
+    int rc = stab_compile(ctx, instrs, ninstr, targets, ntargets, &P);
+    if (rc) return rc;
+    rc = stab_execute(ctx, P, out_bits, nullptr);
+    stab_program_destroy(P);
+    return rc;
+}
+
+int stab_apply_layer(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr,
+                     const int32_t* targets, int64_t ntargets)
+{
+    for (int32_t k = 0; k < ninstr && instrs; ++k)
+        if (instrs[k].kind == STAB_M || instrs[k].kind == STAB_MR || instrs[k].kind == STAB_R)
+            return fail(STAB_EINVAL, "stab_apply_layer takes no measurement instructions");
+    return stab_run(ctx, instrs, ninstr, targets, ntargets, nullptr);
+}
+
+int stab_measure(stab_ctx* ctx, uint32_t kind, const int32_t* qubits, int32_t k, uint8_t* out_bits)
+{
+    if (kind != STAB_M && kind != STAB_MR && kind != STAB_R) return fail(STAB_EINVAL, "kind must be M, MR or R");
+    if (k < 0) return fail(STAB_EINVAL, "negative count");
+    stab_instr in{};
+    in.kind = kind;
+    in.ntargets = (uint32_t)k;
+    return stab_run(ctx, &in, 1, qubits, k, out_bits);
+}
+
+int stab_get_tableau(stab_ctx* ctx, int32_t shot, uint8_t* x, uint8_t* z, uint8_t* r)
+{
+    if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");
+    if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
+    const Geom& g = ctx->g;
+    if (shot < 0 || shot >= g.B) return fail(STAB_EINVAL, "shot out of range");
+    const int s = shot / g.bpc;
+    std::vector<uint64_t> tab((size_t)2 * g.NR * g.RS), rs(g.NB), rd(g.NB);
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_CHECK(ctx, hipMemcpy(tab.data(), ctx->tab + (size_t)s * 2 * g.NR * g.RS, tab.size() * 8, hipMemcpyDeviceToHost));
+    HIP_CHECK(ctx, hipMemcpy(rs.data(), ctx->rs + (size_t)s * g.NB, g.NB * 8, hipMemcpyDeviceToHost));
+    HIP_CHECK(ctx, hipMemcpy(rd.data(), ctx->rd + (size_t)shot * g.NB, g.NB * 8, hipMemcpyDeviceToHost));
+    const int n = g.n;
+    for (int half = 0; half < 2; ++half) {
+        for (int i = 0; i < n; ++i) {
+            const int row = half * g.NR + i;
+            const int out = half * n + i;
+            const uint64_t* w = &tab[(size_t)row * g.RS];
+            for (int j = 0; j < n; ++j) {
+                if (x) x[(size_t)out * n + j] = (uint8_t)((w[j >> 6] >> (j & 63)) & 1ull);
+                if (z) z[(size_t)out * n + j] = (uint8_t)((w[g.Wc + (j >> 6)] >> (j & 63)) & 1ull);
+            }
+            if (r) r[out] = (uint8_t)(((rs[row >> 6] ^ rd[row >> 6]) >> (row & 63)) & 1ull);
+        }
+    }
+    return STAB_OK;
+}
+
+int stab_get_counters(stab_ctx* ctx, uint64_t* counters, int32_t ncounters)
+{
+    if (!ctx || !counters || ncounters < 0 || ncounters > 8) return fail(STAB_EINVAL, "bad arguments");
+    unsigned long long c[8];
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_CHECK(ctx, hipMemcpy(c, ctx->d_counters, sizeof(c), hipMemcpyDeviceToHost));
+    for (int i = 0; i < ncounters; ++i) counters[i] = c[i];
+    return STAB_OK;
+}
+
+int stab_sample(const stab_instr* instrs, int32_t ninstr, const int32_t* targets, int64_t ntargets,
+                int32_t n, int32_t shots, int32_t mode, uint64_t seed, void* dev_buf, uint64_t buf_bytes,
+                void* hip_stream, uint8_t* out_bits, float* elapsed_ms)
+{
+    stab_ctx* ctx = nullptr;
+    int rc = stab_create(n, shots, mode, seed, 0, dev_buf, buf_bytes, hip_stream, &ctx);
+    if (rc) return rc;
+    stab_program* P = nullptr;
+    rc = stab_compile(ctx, instrs, ninstr, targets, ntargets, &P);
+    if (rc == STAB_OK) rc = stab_execute(ctx, P, out_bits, elapsed_ms);
+    stab_program_destroy(P);
+    stab_destroy(ctx);
+    return rc;
+}
+
+}  // extern "C"

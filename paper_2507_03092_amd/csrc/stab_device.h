@@ -1,0 +1,48 @@
+// stab_device.h -- structures shared by the kernels and the host side of libstab.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stabdev {
+
+// Most 64-bit column words a lane of the deterministic-measurement wave keeps in registers.
+constexpr int kMaxWordsPerLane = 4;
+
+struct Geom {
+    int n;    // qubits
+    int Wc;   // column words per row and component: ceil(n / 64)
+    int Wr;   // 64-row bands per half: ceil(n / 64)
+    int NR;   // rows per half, padded: 64 * Wr
+    int RS;   // row stride in words: 2 * Wc (x words, then z words)
+    int NB;   // bands (and sign words) per tableau: 2 * Wr
+    int S;    // tableau copies
+    int B;    // shots
+    int bpc;  // shots per copy (B / S)
+};
+
+// One noise instruction of a segment.
+struct NoiseDesc {
+    uint64_t instr;        // instruction index (Philox counter word 0)
+    uint64_t t0, t1, t2;   // thresholds
+    int kind;              // DEP1, DEP2 or PAULI1
+    int toff;              // first target in the segment's noise target array
+    int units;             // targets (DEP1, PAULI1) or pairs (DEP2)
+    int bucket;            // event bucket (= item.w of the noise layer)
+};
+
+struct SegArgs {
+    const int4* items;     // {type (0 gates, 1 noise), first gate, gate count, bucket}
+    int nitems;
+    const uint2* gates;    // {kind | q0 << 4, q1}
+    const uint2* events;   // noise events {qubit | pauli << 28, shot}
+    const int* ev_count;   // per bucket
+    const int* ev_base;    // per bucket: first slot in events
+    int write_back;        // 1 if some gate changes x|z (H, S, CX)
+    int lds_rd;            // 1: accumulate per-shot signs in LDS (bpc fits)
+    const int* ext_q;      // qubits whose columns the next measurement layer needs
+    int K;
+    uint64_t* Xcol;        // [S][NB][K]
+    uint64_t* Zcol;
+};
+
+}  // namespace stabdev

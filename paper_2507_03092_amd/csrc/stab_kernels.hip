@@ -1,0 +1,750 @@
+// stab_kernels.hip -- device code of the MI355X tableau simulator (gfx950, wave64).
+//
+// Storage (per tableau copy s):
+//   tab  [2*NR][RS] uint64, row-major.  Row i < NR is destabilizer i, row NR+i stabilizer i
+//        (NR = 64*ceil(n/64); rows >= n of each half are zero padding).  A row holds Wc x-words
+//        (bit j%64 of word j/64 = x at qubit j) then Wc z-words; RS = 2*Wc.
+//   rs   [NB] uint64 sign words of the copy (NB = 2*NR/64; word w holds rows 64w..64w+63).
+//   rd   [B][NB] per-shot sign words.  The sign of row i in shot b is rs ^ rd[b].  In the
+//        shared mode one x|z tableau serves every shot: gates only ever XOR shot-independent
+//        masks into signs, so those go to rs, while noise, random outcomes and resets (the
+//        only shot-dependent parts) go to rd.
+//
+// A "band" is 64 consecutive rows.  The segment kernel stages one band in LDS, turns its
+// 64x64 bit tiles into qubit-major words (word = 64 rows of one qubit column), applies a
+// whole run of gate and noise layers there, extracts the columns the next measurement layer
+// needs and writes the band back.  Measurements then work on rows (rowsum, Appendix A.2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stab_device.h"
+
+#define STAB_KIND_H 1
+#define STAB_KIND_S 2
+#define STAB_KIND_X 3
+#define STAB_KIND_Y 4
+#define STAB_KIND_Z 5
+#define STAB_KIND_CX 6
+#define STAB_KIND_DEP1 10
+#define STAB_KIND_DEP2 11
+#define STAB_KIND_PAULI1 12
+
+namespace stabdev {
+
+// ------------------------------------------------------------------------------------------
+// Philox4x64-10, from Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+// 1, 2, 3" (SC'11): ten rounds, each multiplying words 0 and 2 by the two published
+// multipliers (full 128-bit products) and mixing the halves with the other words and the
+// key; the key advances by the two published Weyl constants between rounds.
+// Counter = (c0, c1, 0, 0), key = (k0, k1).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1,
+                                       uint64_t& u0, uint64_t& u1)
+{
+    uint64_t a = c0, b = c1, c = 0, d = 0;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa_lo = 0xD2E7470EE14C6C93ull * a;
+        const uint64_t pa_hi = __umul64hi(0xD2E7470EE14C6C93ull, a);
+        const uint64_t pc_lo = 0xCA5A826395121157ull * c;
+        const uint64_t pc_hi = __umul64hi(0xCA5A826395121157ull, c);
+        a = pc_hi ^ b ^ k0;
+        b = pc_lo;
+        c = pa_hi ^ d ^ k1;
+        d = pa_lo;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    u0 = a;
+    u1 = b;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_xor(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v ^= shfl_xor_u64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v |= shfl_xor_u64(v, m);
+    return v;
+}
+
+// In-register transpose of a 64x64 bit matrix held one row per lane (bit c of lane r's word =
+// element (r, c)).  Six butterfly stages swap the off-diagonal blocks of size 32, 16, ..., 1.
+// Every lane of the wave must take part.
+__device__ __forceinline__ uint64_t transpose64(uint64_t v, int lane)
+{
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int j = 32 >> st;
+        const uint64_t m = masks[st];
+        const uint64_t o = shfl_xor_u64(v, j);
+        if (lane & j) {
+            v ^= ((o >> j) ^ v) & m;
+        } else {
+            v ^= (((v >> j) ^ o) & m) << j;
+        }
+    }
+    return v;
+}
+
+// Sum over the 64 bit positions of g(x1,z1,x2,z2) from the rowsum algorithm (Appendix A.2):
+// the power of i from multiplying the Pauli (x1,z1) into (x2,z2), per bit in {-1, 0, +1}.
+__device__ __forceinline__ int gsum(uint64_t x1, uint64_t z1, uint64_t x2, uint64_t z2)
+{
+    const uint64_t y1 = x1 & z1, xo = x1 & ~z1, zo = ~x1 & z1;
+    const uint64_t plus = (y1 & ~x2 & z2) | (xo & x2 & z2) | (zo & x2 & ~z2);
+    const uint64_t minus = (y1 & x2 & ~z2) | (xo & ~x2 & z2) | (zo & x2 & z2);
+    return __popcll(plus) - __popcll(minus);
+}
+
+__device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
+
+// ------------------------------------------------------------------------------------------
+// init: |0...0> -- destabilizer i = +X_i, stabilizer i = +Z_i, all signs 0.
+// ------------------------------------------------------------------------------------------
+__global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
+                       uint64_t* __restrict__ rd)
+{
+    const size_t rows = (size_t)g.S * 2 * g.NR;
+    const size_t total = rows * g.RS;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = idx / g.RS;
+        const int c = (int)(idx - row * g.RS);
+        const int rr = (int)(row % (2 * (size_t)g.NR));
+        uint64_t v = 0;
+        if (rr < g.NR) {
+            if (rr < g.n && c == (rr >> 6)) v = 1ull << (rr & 63);
+        } else {
+            const int i = rr - g.NR;
+            if (i < g.n && c == g.Wc + (i >> 6)) v = 1ull << (i & 63);
+        }
+        tab[idx] = v;
+    }
+    const size_t nrs = (size_t)g.S * g.NB, nrd = (size_t)g.B * g.NB;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nrs + nrd;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        if (idx < nrs) rs[idx] = 0;
+        else rd[idx - nrs] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Noise draws for one segment: one thread per (shot, noise unit).  Draws never depend on the
+// tableau, so they are made up front and the segment kernel applies them at their layer.
+// Event = (qubit | pauli << 28, shot).
+// ------------------------------------------------------------------------------------------
+__global__ void k_noise_draw(const NoiseDesc* __restrict__ nd, int nn,
+                             const int* __restrict__ unit_start, int total_units,
+                             const int* __restrict__ ntg, int B, uint64_t seed,
+                             uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
+                             const int* __restrict__ ev_base, int* __restrict__ ev_count)
+{
+    const long long total = (long long)total_units * B;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(idx / total_units);
+        const int u = (int)(idx - (long long)b * total_units);
+        int lo = 0, hi = nn - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (unit_start[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const NoiseDesc d = nd[lo];
+        const int pos = u - unit_start[lo];
+        uint64_t u0, u1;
+        philox(instr_base + d.instr, (uint64_t)pos, seed, first_shot + (uint64_t)b, u0, u1);
+        uint2 e0, e1;
+        int ne = 0;
+        if (d.kind == STAB_KIND_DEP1) {
+            if (u0 < d.t0) {
+                const int P = 1 + (int)__umul64hi(u1, 3ull);
+                e0 = make_uint2((uint32_t)ntg[d.toff + pos] | ((uint32_t)P << 28), (uint32_t)b);
+                ne = 1;
+            }
+        } else if (d.kind == STAB_KIND_DEP2) {
+            if (u0 < d.t0) {
+                const int k = 1 + (int)__umul64hi(u1, 15ull);
+                const int pa = k >> 2, pb = k & 3;
+                const uint32_t qa = (uint32_t)ntg[d.toff + 2 * pos];
+                const uint32_t qb = (uint32_t)ntg[d.toff + 2 * pos + 1];
+                if (pa) { e0 = make_uint2(qa | ((uint32_t)pa << 28), (uint32_t)b); ne = 1; }
+                if (pb) {
+                    const uint2 eb = make_uint2(qb | ((uint32_t)pb << 28), (uint32_t)b);
+                    if (ne) e1 = eb;
+                    else e0 = eb;
+                    ++ne;
+                }
+            }
+        } else {  // PAULI1 with cumulative thresholds
+            int P = 0;
+            if (u0 < d.t0) P = 1;
+            else if (u0 < d.t1) P = 2;
+            else if (u0 < d.t2) P = 3;
+            if (P) {
+                e0 = make_uint2((uint32_t)ntg[d.toff + pos] | ((uint32_t)P << 28), (uint32_t)b);
+                ne = 1;
+            }
+        }
+        if (ne) {
+            const int slot = atomicAdd(&ev_count[d.bucket], ne);
+            uint2* dst = events + ev_base[d.bucket] + slot;
+            dst[0] = e0;
+            if (ne == 2) dst[1] = e1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Segment kernel: grid (NB bands, S copies), 1024 threads.  See the file header.
+// Column j of the staged band: x word at T[(j & 63) * RSP + (j >> 6)], z word at + Wc.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
+          uint64_t* __restrict__ rd, SegArgs a)
+{
+    extern __shared__ uint64_t lds[];
+    const int band = blockIdx.x, s = blockIdx.y;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int RS = g.RS, RSP = g.RS + 1, Wc = g.Wc;
+    uint64_t* T = lds;
+    uint64_t* red = lds + 64 * RSP;              // nwaves words
+    uint64_t* rdacc = red + 16;                  // bpc words when a.lds_rd
+    uint64_t* gb = tab + ((size_t)s * 2 * g.NR + (size_t)band * 64) * RS;
+
+    for (int i = tid; i < 64 * RS; i += nt) {
+        const int r = i / RS;
+        T[r * RSP + (i - r * RS)] = gb[i];
+    }
+    if (a.lds_rd)
+        for (int b = tid; b < g.bpc; b += nt) rdacc[b] = 0;
+    __syncthreads();
+    for (int c = wave; c < RS; c += nwaves) {
+        uint64_t v = T[lane * RSP + c];
+        v = transpose64(v, lane);
+        T[lane * RSP + c] = v;
+    }
+    __syncthreads();
+
+    uint64_t racc = 0;
+    for (int it = 0; it < a.nitems; ++it) {
+        const int4 item = a.items[it];
+        if (item.x == 0) {
+            for (int gi = tid; gi < item.z; gi += nt) {
+                const uint2 gt = a.gates[item.y + gi];
+                const int kind = (int)(gt.x & 15u);
+                const int q0 = (int)(gt.x >> 4);
+                const int i0 = (q0 & 63) * RSP + (q0 >> 6);
+                const uint64_t x0 = T[i0], z0 = T[i0 + Wc];
+                switch (kind) {
+                case STAB_KIND_H:
+                    racc ^= x0 & z0;
+                    T[i0] = z0;
+                    T[i0 + Wc] = x0;
+                    break;
+                case STAB_KIND_S:
+                    racc ^= x0 & z0;
+                    T[i0 + Wc] = z0 ^ x0;
+                    break;
+                case STAB_KIND_X: racc ^= z0; break;
+                case STAB_KIND_Y: racc ^= x0 ^ z0; break;
+                case STAB_KIND_Z: racc ^= x0; break;
+                case STAB_KIND_CX: {
+                    const int q1 = (int)gt.y;
+                    const int i1 = (q1 & 63) * RSP + (q1 >> 6);
+                    const uint64_t x1 = T[i1], z1 = T[i1 + Wc];
+                    racc ^= x0 & z1 & ~(x1 ^ z0);
+                    T[i1] = x1 ^ x0;
+                    T[i0 + Wc] = z0 ^ z1;
+                } break;
+                default: break;
+                }
+            }
+        } else {
+            const int cnt = a.ev_count[item.w];
+            const uint2* ev = a.events + a.ev_base[item.w];
+            for (int e = tid; e < cnt; e += nt) {
+                const uint2 v = ev[e];
+                const int sb = (int)v.y - s * g.bpc;
+                if (sb < 0 || sb >= g.bpc) continue;
+                const int q = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
+                const int iq = (q & 63) * RSP + (q >> 6);
+                const uint64_t xq = T[iq], zq = T[iq + Wc];
+                const uint64_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
+                if (m) {
+                    if (a.lds_rd) atomicXor((unsigned long long*)&rdacc[sb], (unsigned long long)m);
+                    else atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + sb) * g.NB + band],
+                                   (unsigned long long)m);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    if (a.K > 0) {
+        uint64_t* Xc = a.Xcol + ((size_t)s * g.NB + band) * a.K;
+        uint64_t* Zc = a.Zcol + ((size_t)s * g.NB + band) * a.K;
+        for (int k = tid; k < a.K; k += nt) {
+            const int q = a.ext_q[k];
+            const int iq = (q & 63) * RSP + (q >> 6);
+            Xc[k] = T[iq];
+            Zc[k] = T[iq + Wc];
+        }
+    }
+    if (a.write_back) {
+        __syncthreads();
+        for (int c = wave; c < RS; c += nwaves) {
+            uint64_t v = T[lane * RSP + c];
+            v = transpose64(v, lane);
+            T[lane * RSP + c] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i < 64 * RS; i += nt) {
+            const int r = i / RS;
+            gb[i] = T[r * RSP + (i - r * RS)];
+        }
+    }
+    racc = wave_xor(racc);
+    if (lane == 0) red[wave] = racc;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < nwaves; ++w) t ^= red[w];
+        if (t) rs[(size_t)s * g.NB + band] ^= t;
+    }
+    if (a.lds_rd) {
+        for (int b = tid; b < g.bpc; b += nt) {
+            const uint64_t v = rdacc[b];
+            if (v) rd[(size_t)(s * g.bpc + b) * g.NB + band] ^= v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Classify each target of a measurement layer at layer start: pivot = first stabilizer row
+// with x at the qubit (Sec. 2.4), or -1 (deterministic).  For deterministic ones, list the
+// destabilizer rows with x at the qubit (they select the stabilizers whose product is +-Z_a).
+// Thread per (target k, copy s); reads of Xcol [s][band][k] are coalesced over k.
+// ------------------------------------------------------------------------------------------
+__global__ void k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K,
+                           int* __restrict__ cls, int* __restrict__ mlist,
+                           int* __restrict__ mcount, int mcap)
+{
+    const int s = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const uint64_t* X = Xcol + (size_t)s * g.NB * K;
+    int piv = -1;
+    for (int w = 0; w < g.Wr; ++w) {
+        const uint64_t v = X[(size_t)(g.Wr + w) * K + k];
+        if (v) {
+            piv = w * 64 + ctz64(v);
+            break;
+        }
+    }
+    cls[s * K + k] = piv;
+    if (piv < 0) {
+        int cnt = 0;
+        for (int w = 0; w < g.Wr; ++w) {
+            uint64_t v = X[(size_t)w * K + k];
+            while (v) {
+                const int bit = ctz64(v);
+                v &= v - 1;
+                if (cnt < mcap) mlist[((size_t)s * mcap + cnt) * K + k] = w * 64 + bit;
+                ++cnt;
+            }
+        }
+        mcount[s * K + k] = cnt;
+    }
+}
+
+// Deterministic outcome, one wave: product of stabilizer rows NR+i over the listed rows i,
+// in increasing i (Alg. 2 of the paper reduces the same product into a scratch row).  Each
+// lane owns column words j = lane + 64 t and keeps its part of the scratch row in registers;
+// the i-power of every rowsum step is accumulated per lane and reduced once at the end.
+// The x part of the product must vanish (the product is +-Z_a).
+template <typename RowFn>
+__device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __restrict__ tab,
+                                               const uint64_t* __restrict__ rs, int s, int lane,
+                                               int nrows, RowFn row_of, int* __restrict__ err)
+{
+    uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
+    int G = 0, rsum = 0;
+    const uint64_t* base = tab + ((size_t)s * 2 * g.NR + g.NR) * g.RS;
+    for (int c = 0; c < nrows; ++c) {
+        const int i = row_of(c);
+        const uint64_t* row = base + (size_t)i * g.RS;
+#pragma unroll
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int j = lane + 64 * t;
+            if (j < g.Wc) {
+                const uint64_t x1 = row[j], z1 = row[g.Wc + j];
+                G += gsum(x1, z1, sx[t], sz[t]);
+                sx[t] ^= x1;
+                sz[t] ^= z1;
+            }
+        }
+        rsum += (int)((rs[(size_t)s * g.NB + g.Wr + (i >> 6)] >> (i & 63)) & 1ull);
+    }
+    G = wave_sum(G);
+    uint64_t xres = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) xres |= sx[t];
+    xres = wave_or(xres);
+    const int e = (2 * rsum + G) & 3;
+    if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
+    return e >> 1;
+}
+
+// Thread per (copy, target): deterministic-at-start targets, one wave each.
+__global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
+                      const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K,
+                      const int* __restrict__ cls, const int* __restrict__ mlist,
+                      const int* __restrict__ mcount, int mcap, uint8_t* __restrict__ obuf,
+                      int* __restrict__ err, unsigned long long* __restrict__ counters)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    const int s = blockIdx.y;
+    if (k >= K) return;
+    if (cls[s * K + k] >= 0) return;
+    const int cnt = mcount[s * K + k];
+    const uint64_t* X = Xcol + (size_t)s * g.NB * K;
+    int shared;
+    if (cnt <= mcap) {
+        shared = det_wave_shared(g, tab, rs, s, lane, cnt,
+                                 [&](int c) { return mlist[((size_t)s * mcap + c) * K + k]; }, err);
+    } else {
+        // long list: walk the destabilizer x-words of the column directly
+        auto nth = [&](int c) {
+            int seen = 0;
+            for (int w = 0; w < g.Wr; ++w) {
+                uint64_t v = X[(size_t)w * K + k];
+                const int pc = __popcll(v);
+                if (seen + pc > c) {
+                    for (int q = 0; q < c - seen; ++q) v &= v - 1;
+                    return w * 64 + ctz64(v);
+                }
+                seen += pc;
+            }
+            return 0;
+        };
+        shared = det_wave_shared(g, tab, rs, s, lane, cnt, nth, err);
+    }
+    // per-shot part of the sign: parity of the shot's sign bits over the same rows
+    for (int b = lane; b < g.bpc; b += 64) {
+        const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * g.NB + g.Wr;
+        int par = 0;
+        for (int w = 0; w < g.Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+        obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
+    }
+    if (lane == 0 && counters) {
+        atomicAdd(&counters[2], 1ull);
+        atomicAdd(&counters[3], (unsigned long long)cnt);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Random-at-start targets of a layer, in op order, one block per copy.  Each may have turned
+// deterministic because of an earlier one in the same layer (then it is reduced like k_det on
+// the current tableau).  Otherwise (Sec. 2.4): pivot p = first stabilizer with x at the qubit;
+// rowsum(i, p) for every other row i with x at the qubit (the pivot's destabilizer is skipped:
+// it is overwritten next); destabilizer <- old pivot row; pivot row <- Z_a with the outcome.
+// Xcol/Zcol of the layer's targets are kept equal to the current tableau's columns.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(512)
+k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
+        uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
+        const int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
+        uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
+        uint8_t* __restrict__ obuf, int* __restrict__ err, unsigned long long* __restrict__ counters)
+{
+    extern __shared__ uint64_t sm[];
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS;
+    const int nrdw = (g.bpc + 63) >> 6;
+    uint64_t* rowp = sm;                 // RS words: old pivot row
+    uint64_t* rowq = rowp + RS;          // RS words: old destabilizer of the pivot
+    uint64_t* sM = rowq + RS;            // NB words: rows to rowsum into
+    uint64_t* sC = sM + NB;              // NB words: i-power bit of each rowsum
+    uint64_t* sRdp = sC + NB;            // nrdw words: per-shot sign of the pivot
+    int* nz = (int*)(sRdp + nrdw);       // NB ints: nonzero words of sM
+    __shared__ int s_piv, s_nnz, s_rsp, s_bad, s_G[16];
+
+    uint64_t* X = Xcol + (size_t)s * NB * K;
+    uint64_t* Z = Zcol + (size_t)s * NB * K;
+    uint64_t* tb = tab + (size_t)s * 2 * g.NR * RS;
+    int* tm = tmap + (size_t)s * g.n;
+
+    int mine = 0;
+    for (int k = tid; k < K; k += nt) mine |= cls[s * K + k] >= 0;
+    if (!__syncthreads_or(mine)) return;
+
+    for (int k = tid; k < K; k += nt) tm[tq[k]] = k;
+    __syncthreads();
+
+    for (int k = 0; k < K; ++k) {
+        if (cls[s * K + k] < 0) continue;
+        const int a = tq[k];
+        if (tid == 0) { s_piv = INT_MAX; s_nnz = 0; s_bad = 0; }
+        __syncthreads();
+        for (int w = tid; w < Wr; w += nt) {
+            const uint64_t v = X[(size_t)(Wr + w) * K + k];
+            if (v) atomicMin(&s_piv, w * 64 + ctz64(v));
+        }
+        __syncthreads();
+        const int ip = s_piv;
+        if (ip == INT_MAX) {
+            // Deterministic now: the block reduces the product, thread t owning column word t
+            // (requires Wc <= blockDim.x).
+            uint64_t sx = 0, sz = 0;
+            int G = 0, rsum = 0, nrows = 0;
+            const uint64_t* base = tb + (size_t)g.NR * RS;
+            for (int w = 0; w < Wr; ++w) {
+                uint64_t v = X[(size_t)w * K + k];
+                while (v) {
+                    const int i = w * 64 + ctz64(v);
+                    v &= v - 1;
+                    ++nrows;
+                    if (tid < Wc) {
+                        const uint64_t* row = base + (size_t)i * RS;
+                        const uint64_t x1 = row[tid], z1 = row[Wc + tid];
+                        G += gsum(x1, z1, sx, sz);
+                        sx ^= x1;
+                        sz ^= z1;
+                    }
+                    rsum += (int)((rs[(size_t)s * NB + Wr + (i >> 6)] >> (i & 63)) & 1ull);
+                }
+            }
+            G = wave_sum(G);
+            const uint64_t xr = wave_or(sx);
+            if (lane == 0) {
+                s_G[wave] = G;
+                if (xr) atomicOr(&s_bad, 1);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < nwaves; ++w) tot += s_G[w];
+                const int e = (2 * rsum + tot) & 3;
+                if ((e & 1) || s_bad) atomicOr(err, 2);
+                s_piv = e >> 1;
+            }
+            __syncthreads();
+            const int shared = s_piv;
+            for (int b = tid; b < g.bpc; b += nt) {
+                const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * NB + Wr;
+                int par = 0;
+                for (int w = 0; w < Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+                obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
+            }
+            if (tid == 0 && counters) {
+                atomicAdd(&counters[6], 1ull);
+                atomicAdd(&counters[3], (unsigned long long)nrows);
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // ---- random: phase A, gather ----
+        const int wq = ip >> 6;
+        const uint64_t bq = 1ull << (ip & 63);
+        const uint64_t* gp = tb + (size_t)(g.NR + ip) * RS;
+        const uint64_t* gq = tb + (size_t)ip * RS;
+        for (int j = tid; j < RS; j += nt) {
+            rowp[j] = gp[j];
+            rowq[j] = gq[j];
+        }
+        for (int w = tid; w < NB; w += nt) {
+            uint64_t v = X[(size_t)w * K + k];
+            if (w == wq || w == Wr + wq) v &= ~bq;   // neither the pivot nor its destabilizer
+            sM[w] = v;
+            sC[w] = 0;
+            if (v) nz[atomicAdd(&s_nnz, 1)] = w;
+        }
+        for (int t = tid; t < nrdw; t += nt) sRdp[t] = 0;
+        if (tid == 0) s_rsp = (int)((rs[(size_t)s * NB + Wr + wq] >> (ip & 63)) & 1ull);
+        __syncthreads();
+        // ---- phase B: pivot signs per shot; rowsum(i, p), one row per wave at a time ----
+        for (int b = tid; b < g.bpc; b += nt) {
+            const uint64_t bit = (rd[(size_t)(s * g.bpc + b) * NB + Wr + wq] >> (ip & 63)) & 1ull;
+            if (bit) atomicOr((unsigned long long*)&sRdp[b >> 6], 1ull << (b & 63));
+        }
+        const int nnz = s_nnz;
+        {
+            int idx = 0;
+            for (int t = 0; t < nnz; ++t) {
+                const int w = nz[t];
+                uint64_t v = sM[w];
+                while (v) {
+                    const int bit = ctz64(v);
+                    v &= v - 1;
+                    if ((idx++ % nwaves) != wave) continue;
+                    const int i = w * 64 + bit;          // row index over both halves
+                    uint64_t* row = tb + (size_t)i * RS;
+                    int G = 0;
+                    for (int j = lane; j < Wc; j += 64) {
+                        const uint64_t xp = rowp[j], zp = rowp[Wc + j];
+                        if ((xp | zp) == 0) continue;
+                        const uint64_t xi = row[j], zi = row[Wc + j];
+                        G += gsum(xp, zp, xi, zi);
+                        row[j] = xi ^ xp;
+                        row[Wc + j] = zi ^ zp;
+                    }
+                    G = wave_sum(G);
+                    if (lane == 0) {
+                        if (G & 1) atomicOr(err, 4);
+                        if (G & 2) atomicOr((unsigned long long*)&sC[w], 1ull << bit);
+                    }
+                }
+            }
+            if (tid == 0 && counters) atomicAdd(&counters[5], (unsigned long long)idx);
+        }
+        __syncthreads();
+        // ---- phase C: signs of the rowsum rows (r_i <- r_i ^ r_p ^ i-power/2); target columns
+        const int rsp = s_rsp;
+        for (int t = tid; t < nnz; t += nt) {
+            const int w = nz[t];
+            rs[(size_t)s * NB + w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
+        }
+        for (int idx = tid; idx < nnz * g.bpc; idx += nt) {
+            const int b = idx / nnz, t = idx - b * nnz;
+            if ((sRdp[b >> 6] >> (b & 63)) & 1ull) {
+                const int w = nz[t];
+                rd[(size_t)(s * g.bpc + b) * NB + w] ^= sM[w];
+            }
+        }
+        for (int j = tid; j < Wc; j += nt) {
+            uint64_t bits = rowp[j] | rowp[Wc + j] | rowq[j] | rowq[Wc + j];
+            while (bits) {
+                const int bit = ctz64(bits);
+                bits &= bits - 1;
+                const int qb = j * 64 + bit;
+                const int k2 = tm[qb];
+                if (k2 < 0) continue;
+                const uint64_t xpb = (rowp[j] >> bit) & 1ull, zpb = (rowp[Wc + j] >> bit) & 1ull;
+                uint64_t* X2 = X + k2;
+                uint64_t* Z2 = Z + k2;
+                if (xpb)
+                    for (int t = 0; t < nnz; ++t) X2[(size_t)nz[t] * K] ^= sM[nz[t]];
+                if (zpb)
+                    for (int t = 0; t < nnz; ++t) Z2[(size_t)nz[t] * K] ^= sM[nz[t]];
+                const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
+                X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
+                Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
+                X2[op] &= ~bq;
+                Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
+            }
+        }
+        __syncthreads();
+        // ---- phase D: row moves, the pivot's signs and the outcome ----
+        {
+            uint64_t* dq = tb + (size_t)ip * RS;
+            uint64_t* dp = tb + (size_t)(g.NR + ip) * RS;
+            const int za = Wc + (a >> 6);
+            for (int j = tid; j < RS; j += nt) {
+                dq[j] = rowp[j];
+                dp[j] = (j == za) ? (1ull << (a & 63)) : 0ull;
+            }
+            if (tid == 0) {
+                uint64_t* rq = &rs[(size_t)s * NB + wq];
+                *rq = (*rq & ~bq) | (rsp ? bq : 0ull);
+                rs[(size_t)s * NB + Wr + wq] &= ~bq;
+            }
+            for (int b = tid; b < g.bpc; b += nt) {
+                const uint64_t shot = first_shot + (uint64_t)(s * g.bpc + b);
+                uint64_t u0, u1;
+                philox(instr, (uint64_t)(pos_base + k), seed, shot, u0, u1);
+                const int out = (int)(u0 >> 63);
+                uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * NB;
+                const uint64_t rdp = (sRdp[b >> 6] >> (b & 63)) & 1ull;
+                rdb[wq] = (rdb[wq] & ~bq) | (rdp ? bq : 0ull);
+                rdb[Wr + wq] = (rdb[Wr + wq] & ~bq) | (out ? bq : 0ull);
+                obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)out;
+            }
+            if (tid == 0 && counters) atomicAdd(&counters[4], 1ull);
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < K; k += nt) tm[tq[k]] = -1;
+}
+
+// ------------------------------------------------------------------------------------------
+// End of a measurement layer: resets (X on the qubit when the outcome is 1: every row with z
+// at the qubit flips sign -- applied once for the whole layer, which is exact because sign
+// flips commute with rowsum and with the other measurements of the layer) and the record.
+// Block per (sign word w, shot b), threads over targets.
+// ------------------------------------------------------------------------------------------
+__global__ void k_reset_record(Geom g, uint64_t* __restrict__ rd, const uint64_t* __restrict__ Zcol,
+                               const uint8_t* __restrict__ obuf, int K, int do_reset,
+                               uint8_t* __restrict__ record, long long rec_stride, long long rec_off,
+                               int do_record)
+{
+    const int w = blockIdx.x, b = blockIdx.y;
+    const int s = b / g.bpc;
+    const uint8_t* ob = obuf + (size_t)b * K;
+    const uint64_t* Zc = Zcol + ((size_t)s * g.NB + w) * K;
+    uint64_t acc = 0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const uint8_t o = ob[k];
+        if (do_reset && o) acc ^= Zc[k];
+        if (do_record && w == 0) record[(size_t)b * rec_stride + rec_off + k] = o;
+    }
+    if (do_reset) {
+        __shared__ uint64_t red[16];
+        acc = wave_xor(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t ^= red[i];
+            if (t) rd[(size_t)b * g.NB + w] ^= t;
+        }
+    }
+}
+
+// Pack the byte-per-measurement record into bits, LSB first, ceil(M/8) bytes per shot.
+__global__ void k_pack(const uint8_t* __restrict__ rec, long long M, int B, uint8_t* __restrict__ out)
+{
+    const long long nbytes = (M + 7) / 8;
+    const long long total = nbytes * B;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long b = idx / nbytes, j = idx - b * nbytes;
+        uint8_t v = 0;
+        for (int t = 0; t < 8; ++t) {
+            const long long m = j * 8 + t;
+            if (m < M && rec[b * M + m]) v |= (uint8_t)(1u << t);
+        }
+        out[idx] = v;
+    }
+}
+
+}  // namespace stabdev

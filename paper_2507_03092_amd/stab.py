@@ -1,0 +1,200 @@
+"""Python binding of libstab (include/stab.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels behind the C ABI; torch provides the
+device buffer that holds the tableaux and the HIP stream.  There is no CPU fallback: if the
+library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import circuits as _circ
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstab.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EINTERNAL = 0, -1, -2, -3, -4, -5
+MODE_SHARED, MODE_FULL = 0, 1
+_MODES = {"shared": MODE_SHARED, "full": MODE_FULL, MODE_SHARED: MODE_SHARED, MODE_FULL: MODE_FULL}
+
+# every function declared in include/stab.h
+EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy", "stab_run",
+           "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
+           "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
+           "stab_get_counters", "stab_last_error")
+
+
+class StabError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libstab error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libstab.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2507_03092_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+    sig = {
+        "stab_max_qubits": (I32, []),
+        "stab_tableau_bytes": (C.c_int, [I32, I32, I32, C.POINTER(U64)]),
+        "stab_create": (C.c_int, [I32, I32, I32, U64, U64, P, U64, P, C.POINTER(P)]),
+        "stab_destroy": (None, [P]),
+        "stab_run": (C.c_int, [P, P, I32, P, I64, P]),
+        "stab_apply_layer": (C.c_int, [P, P, I32, P, I64]),
+        "stab_measure": (C.c_int, [P, U32, P, I32, P]),
+        "stab_get_tableau": (C.c_int, [P, I32, P, P, P]),
+        "stab_compile": (C.c_int, [P, P, I32, P, I64, C.POINTER(P)]),
+        "stab_execute": (C.c_int, [P, P, P, C.POINTER(C.c_float)]),
+        "stab_program_records": (I64, [P]),
+        "stab_program_destroy": (None, [P]),
+        "stab_reset": (C.c_int, [P, U64, U64]),
+        "stab_sample": (C.c_int, [P, I32, P, I64, I32, I32, I32, U64, P, U64, P, P, C.POINTER(C.c_float)]),
+        "stab_get_counters": (C.c_int, [P, P, I32]),
+        "stab_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise StabError(rc, lib().stab_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def unpack_record(bits: np.ndarray, shots: int, nrec: int) -> np.ndarray:
+    nbytes = (nrec + 7) // 8
+    b = bits.reshape(shots, nbytes)
+    return np.unpackbits(b, axis=1, bitorder="little")[:, :nrec]
+
+
+def tableau_bytes(n: int, shots: int, mode="shared") -> int:
+    out = C.c_uint64(0)
+    _check(lib().stab_tableau_bytes(n, shots, _MODES[mode], C.byref(out)))
+    return out.value
+
+
+def max_qubits() -> int:
+    return lib().stab_max_qubits()
+
+
+class Program:
+    def __init__(self, ctx: "Context", handle, nrec: int, ninstr: int):
+        self.ctx, self.h, self.nrec, self.ninstr = ctx, handle, nrec, ninstr
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().stab_program_destroy(self.h)
+            self.h = None
+
+
+class Context:
+    """`shots` tableaux of n qubits on one GPU (stab_create)."""
+
+    def __init__(self, n: int, shots: int = 1, mode="shared", seed: int = 0, first_shot: int = 0,
+                 device: str = "cuda:0"):
+        import torch
+
+        self.n, self.shots, self.mode = n, shots, _MODES[mode]
+        nbytes = tableau_bytes(n, shots, mode)
+        self.device = torch.device(device)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p(None)
+        _check(lib().stab_create(n, shots, self.mode, seed, first_shot, C.c_void_p(self.buf.data_ptr()),
+                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().stab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def compile(self, circ: _circ.Circuit) -> Program:
+        instr, tg = circ.arrays()
+        h = C.c_void_p(None)
+        _check(lib().stab_compile(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg), C.byref(h)))
+        return Program(self, h, lib().stab_program_records(h), len(instr))
+
+    def execute(self, prog: Program, timed: bool = False):
+        nbytes = (prog.nrec + 7) // 8
+        out = np.zeros(max(self.shots * nbytes, 1), dtype=np.uint8)
+        ms = C.c_float(0.0)
+        _check(lib().stab_execute(self.h, prog.h, _ptr(out), C.byref(ms)))
+        rec = unpack_record(out[: self.shots * nbytes], self.shots, prog.nrec)
+        return (rec, ms.value) if timed else rec
+
+    def run(self, circ: _circ.Circuit) -> np.ndarray:
+        instr, tg = circ.arrays()
+        nrec = circ.num_measurements()
+        nbytes = (nrec + 7) // 8
+        out = np.zeros(max(self.shots * nbytes, 1), dtype=np.uint8)
+        _check(lib().stab_run(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg), _ptr(out)))
+        return unpack_record(out[: self.shots * nbytes], self.shots, nrec)
+
+    def apply_layer(self, circ: _circ.Circuit) -> None:
+        instr, tg = circ.arrays()
+        _check(lib().stab_apply_layer(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg)))
+
+    def measure(self, qubits, kind: int = _circ.M) -> np.ndarray:
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        nbytes = (len(q) + 7) // 8
+        out = np.zeros(max(self.shots * nbytes, 1), dtype=np.uint8)
+        _check(lib().stab_measure(self.h, kind, _ptr(q), len(q), _ptr(out)))
+        if kind == _circ.R:
+            return np.zeros((self.shots, 0), dtype=np.uint8)
+        return unpack_record(out[: self.shots * nbytes], self.shots, len(q))
+
+    def get_tableau(self, shot: int = 0):
+        n = self.n
+        x = np.zeros((2 * n, n), dtype=np.uint8)
+        z = np.zeros((2 * n, n), dtype=np.uint8)
+        r = np.zeros(2 * n, dtype=np.uint8)
+        _check(lib().stab_get_tableau(self.h, shot, _ptr(x), _ptr(z), _ptr(r)))
+        return x, z, r
+
+    def reset(self, seed: int, first_shot: int = 0) -> None:
+        _check(lib().stab_reset(self.h, seed, first_shot))
+
+    def counters(self) -> np.ndarray:
+        c = np.zeros(8, dtype=np.uint64)
+        _check(lib().stab_get_counters(self.h, _ptr(c), 8))
+        return c
+
+
+def sample(circ: _circ.Circuit, shots: int, seed: int, mode="shared", device: str = "cuda:0"):
+    """stab_sample: returns (record [shots, nrec] uint8, device milliseconds)."""
+    import torch
+
+    instr, tg = circ.arrays()
+    nrec = circ.num_measurements()
+    nbytes = tableau_bytes(circ.n, shots, mode)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    out = np.zeros(max(shots * ((nrec + 7) // 8), 1), dtype=np.uint8)
+    ms = C.c_float(0.0)
+    _check(lib().stab_sample(_ptr(instr), len(instr), _ptr(tg), len(tg), circ.n, shots, _MODES[mode],
+                             seed, C.c_void_p(buf.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream),
+                             _ptr(out), C.byref(ms)))
+    return unpack_record(out[: shots * ((nrec + 7) // 8)], shots, nrec), ms.value

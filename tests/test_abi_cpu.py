@@ -1,0 +1,101 @@
+"""The C-ABI library loads and exports what include/stab.h declares; host-only argument checks.
+
+No GPU is touched: every call here returns before the library makes a HIP call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_03092_amd import build as hipbuild
+from paper_2507_03092_amd import circuits as Cc
+from paper_2507_03092_amd import stab
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    hipbuild.build(force=False)
+    return stab.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "stab.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stab_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declarations_match_binding():
+    assert declared_functions() == sorted(stab.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_instruction_record_is_32_bytes():
+    assert Cc.INSTR_DTYPE.itemsize == 32
+    # kinds match the header's enum
+    src = open(os.path.join(ROOT, "include", "stab.h")).read()
+    for name, code in Cc.NAME_TO_KIND.items():
+        m = re.search(r"STAB_%s = (\d+)" % name, src)
+        assert m and int(m.group(1)) == code, name
+
+
+def test_max_qubits(L):
+    # one 64-row band (64 x (2*ceil(n/64) + 1) words plus 16 reduction words) in 160 KB of LDS
+    assert stab.max_qubits() == 159 * 64
+
+
+def _bytes(n, shots, mode):
+    wc = (n + 63) // 64
+    nr = 64 * wc
+    s = 1 if mode == 0 else shots
+    a = lambda v: (v + 255) & ~255
+    tab = s * 2 * nr * 2 * wc * 8
+    rs = a(tab) + s * 2 * wc * 8
+    rd = a(rs) + shots * 2 * wc * 8
+    return a(rd)
+
+
+@pytest.mark.parametrize("n,shots,mode", [(1, 1, 0), (17, 1000, 0), (1249, 100, 0), (1249, 100, 1),
+                                          (10081, 10, 0), (64, 3, 1), (65, 3, 1)])
+def test_tableau_bytes(L, n, shots, mode):
+    assert stab.tableau_bytes(n, shots, mode) == _bytes(n, shots, mode)
+
+
+def test_argument_errors_without_gpu(L):
+    out = C.c_uint64(0)
+    assert L.stab_tableau_bytes(0, 1, 0, C.byref(out)) == stab.EINVAL
+    assert L.stab_tableau_bytes(5, 0, 0, C.byref(out)) == stab.EINVAL
+    assert L.stab_tableau_bytes(5, 1, 7, C.byref(out)) == stab.EINVAL
+    assert L.stab_tableau_bytes(stab.max_qubits() + 1, 1, 0, C.byref(out)) == stab.ERANGE
+    assert L.stab_tableau_bytes(5, 70000, 0, C.byref(out)) == stab.ERANGE
+    assert L.stab_tableau_bytes(5, 1, 0, None) == stab.EINVAL
+    h = C.c_void_p(None)
+    assert L.stab_create(5, 1, 0, 0, 0, None, 1 << 20, None, C.byref(h)) == stab.EINVAL
+    assert L.stab_create(5, 1, 0, 0, 0, C.c_void_p(0x1001), 1 << 20, None, C.byref(h)) == stab.EINVAL
+    assert L.stab_create(5, 1, 0, 0, 0, C.c_void_p(0x100000), 16, None, C.byref(h)) == stab.ENOMEM
+    assert b"stab_tableau_bytes" in L.stab_last_error()
+    assert L.stab_create(5, 1, 0, 0, 0, None, 0, None, None) == stab.EINVAL
+    # NULL handles are rejected or ignored
+    assert L.stab_run(None, None, 0, None, 0, None) == stab.EINVAL
+    assert L.stab_reset(None, 0, 0) == stab.EINVAL
+    assert L.stab_get_tableau(None, 0, None, None, None) == stab.EINVAL
+    L.stab_destroy(None)
+    L.stab_program_destroy(None)
+    assert L.stab_program_records(None) == -1
+
+
+def test_record_unpacking_layout():
+    # shot b's bits start at byte b*ceil(nrec/8), LSB first
+    rec = np.array([[1, 0, 1, 1, 0, 0, 0, 0, 1], [0, 1, 0, 0, 0, 0, 0, 1, 1]], dtype=np.uint8)
+    packed = np.packbits(rec, axis=1, bitorder="little").reshape(-1)
+    assert list(packed) == [0b00001101, 1, 0b10000010, 1]
+    assert np.array_equal(stab.unpack_record(packed, 2, 9), rec)
