@@ -153,6 +153,16 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
  * within a layer, [7] noise events.  ncounters <= 8.  Synchronizes the stream. */
 int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 
+/* Per-kernel device timing with HIP events recorded on the context's stream around every
+ * launch.  stab_set_timing(ctx, 1) clears the totals and starts timing; 0 stops it.
+ * stab_get_kernel_times writes, for each kernel id, the summed milliseconds and the number of
+ * launches since timing started.  Kernel ids: 0 init, 1 noise draw, 2 segment (gates + noise
+ * + column extraction), 3 classify, 4 deterministic batch, 5 random chain, 6 reset/record,
+ * 7 record packing.  nkernels <= 8. */
+#define STAB_NUM_KERNELS 8
+int stab_set_timing(stab_ctx *ctx, int32_t enable);
+int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t nkernels);
+
 /* Message of the last error on this thread ("" if none). */
 const char *stab_last_error(void);
 

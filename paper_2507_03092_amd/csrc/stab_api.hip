@@ -94,6 +94,13 @@ struct stab_ctx {
     int* d_tmap = nullptr;
     DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-kernel timing (stab_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<int> evkind;      // kernel id of each recorded pair
+    size_t evused = 0;            // events used in the current execution
+    double kms[8] = {0};
+    unsigned long long klaunch[8] = {0};
 };
 
 namespace {
@@ -171,6 +178,54 @@ int ensure(DevBuf& b, size_t bytes)
     } while (0)
 
 bool valid_kind(uint32_t k) { return k <= STAB_PAULI1; }
+
+// Timing brackets: tstart() before a launch, tstop(kind) after it (no-ops unless timing).
+int tstart(stab_ctx* ctx)
+{
+    if (!ctx->timing) return STAB_OK;
+    if (ctx->evused + 2 > ctx->evpool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            HIP_CHECK(ctx, hipEventCreate(&e));
+            ctx->evpool.push_back(e);
+        }
+    }
+    HIP_CHECK(ctx, hipEventRecord(ctx->evpool[ctx->evused], ctx->stream));
+    return STAB_OK;
+}
+
+int tstop(stab_ctx* ctx, int kind)
+{
+    if (!ctx->timing) return STAB_OK;
+    HIP_CHECK(ctx, hipEventRecord(ctx->evpool[ctx->evused + 1], ctx->stream));
+    ctx->evkind.push_back(kind);
+    ctx->evused += 2;
+    return STAB_OK;
+}
+
+// After the stream has synchronized: add the recorded pairs to the totals.
+int tcollect(stab_ctx* ctx)
+{
+    for (size_t i = 0; i < ctx->evkind.size(); ++i) {
+        float ms = 0.f;
+        HIP_CHECK(ctx, hipEventElapsedTime(&ms, ctx->evpool[2 * i], ctx->evpool[2 * i + 1]));
+        ctx->kms[ctx->evkind[i]] += ms;
+        ctx->klaunch[ctx->evkind[i]] += 1;
+    }
+    ctx->evkind.clear();
+    ctx->evused = 0;
+    return STAB_OK;
+}
+
+#define TIMED(ctx, kind, launch)                 \
+    do {                                         \
+        int rc_ = tstart(ctx);                   \
+        if (rc_) return rc_;                     \
+        launch;                                  \
+        HIP_CHECK(ctx, hipGetLastError());       \
+        rc_ = tstop(ctx, kind);                  \
+        if (rc_) return rc_;                     \
+    } while (0)
 
 // Split an op stream into segments (gate layers on disjoint qubits and noise layers) and
 // measurement layers (disjoint qubits); see the file header.
@@ -318,8 +373,7 @@ int launch_init(stab_ctx* ctx)
     const Geom& g = ctx->g;
     const size_t words = (size_t)g.S * 2 * g.NR * g.RS;
     const int blocks = (int)std::min<size_t>((words + 255) / 256, 65536);
-    k_init<<<blocks, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd);
-    HIP_CHECK(ctx, hipGetLastError());
+    TIMED(ctx, 0, (k_init<<<blocks, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd)));
     HIP_CHECK(ctx, hipMemsetAsync(ctx->d_err, 0, sizeof(int), ctx->stream));
     return STAB_OK;
 }
@@ -420,6 +474,7 @@ void stab_destroy(stab_ctx* ctx)
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
     if (ctx->d_tmap) (void)hipFree(ctx->d_tmap);
+    for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -435,6 +490,7 @@ int stab_reset(stab_ctx* ctx, uint64_t seed, uint64_t first_shot)
     int rc = launch_init(ctx);
     if (rc) return rc;
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->timing && (rc = tcollect(ctx))) return rc;
     return STAB_OK;
 }
 
@@ -534,11 +590,10 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             if (sp.noise_count > 0) {
                 const long long work = (long long)sp.units * g.B;
                 const int blocks = (int)std::min<long long>((work + 255) / 256, 1 << 16);
-                k_noise_draw<<<blocks, 256, 0, ctx->stream>>>(
+                TIMED(ctx, 1, (k_noise_draw<<<blocks, 256, 0, ctx->stream>>>(
                     P->d_noise + sp.noise_begin, sp.noise_count, P->d_unit_start + sp.noise_begin,
                     sp.units, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                    P->d_ev_base, P->d_ev_count);
-                HIP_CHECK(ctx, hipGetLastError());
+                    P->d_ev_base, P->d_ev_count)));
             }
             if (sp.item_count > 0 || sp.meas >= 0) {
                 SegArgs a{};
@@ -560,25 +615,25 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                 }
                 a.Xcol = Xcol;
                 a.Zcol = Zcol;
-                k_segment<<<dim3(g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a);
-                HIP_CHECK(ctx, hipGetLastError());
+                TIMED(ctx, 2, (k_segment<<<dim3(g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
+                                  g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
         } else {
             const MeasPlan& m = P->meas[st.second];
             const int K2 = m.K;
-            k_classify<<<dim3((K2 + 255) / 256, g.S), 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap);
-            HIP_CHECK(ctx, hipGetLastError());
-            k_det<<<dim3((K2 + 3) / 4, g.S), 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
-                                                                   mcount, kMCap, obuf, ctx->d_err, ctx->d_counters);
-            HIP_CHECK(ctx, hipGetLastError());
-            k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
-                g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin, ctx->d_tmap,
-                ctx->seed, ctx->first_shot, base + m.instr, m.pos_base, obuf, ctx->d_err, ctx->d_counters);
-            HIP_CHECK(ctx, hipGetLastError());
+            TIMED(ctx, 3, (k_classify<<<dim3((K2 + 255) / 256, g.S), 256, 0, ctx->stream>>>(
+                              g, Xcol, K2, cls, mlist, mcount, kMCap)));
+            TIMED(ctx, 4, (k_det<<<dim3((K2 + 3) / 4, g.S), 256, 0, ctx->stream>>>(
+                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist, mcount, kMCap, obuf,
+                              ctx->d_err, ctx->d_counters)));
+            TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
+                              ctx->d_tmap, ctx->seed, ctx->first_shot, base + m.instr, m.pos_base, obuf,
+                              ctx->d_err, ctx->d_counters)));
             const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
-            k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(g, ctx->rd, Zcol, obuf, K2, do_reset, record,
-                                                                     (long long)P->nrec, m.rec_off, do_record);
-            HIP_CHECK(ctx, hipGetLastError());
+            TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
+                              g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
+                              do_record)));
         }
     }
     const long long nbytes = (P->nrec + 7) / 8;
@@ -586,8 +641,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     if (P->nrec > 0) {
         const long long total = nbytes * g.B;
         const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
-        k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p);
-        HIP_CHECK(ctx, hipGetLastError());
+        TIMED(ctx, 7, (k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p)));
         host.resize((size_t)total);
         HIP_CHECK(ctx, hipMemcpyAsync(host.data(), ctx->packed.p, (size_t)total, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -600,6 +654,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         return fail(STAB_EINTERNAL, "device consistency check failed (code " + std::to_string(err) + ")");
     }
     if (elapsed_ms) HIP_CHECK(ctx, hipEventElapsedTime(elapsed_ms, ctx->ev0, ctx->ev1));
+    if (ctx->timing && (rc = tcollect(ctx))) return rc;
     if (P->nrec > 0) std::memcpy(out_bits, host.data(), host.size());
     ctx->instr_counter += (uint64_t)P->ninstr;
     return STAB_OK;
@@ -670,6 +725,30 @@ int stab_get_counters(stab_ctx* ctx, uint64_t* counters, int32_t ncounters)
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     HIP_CHECK(ctx, hipMemcpy(c, ctx->d_counters, sizeof(c), hipMemcpyDeviceToHost));
     for (int i = 0; i < ncounters; ++i) counters[i] = c[i];
+    return STAB_OK;
+}
+
+int stab_set_timing(stab_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->timing = enable != 0;
+    ctx->evkind.clear();
+    ctx->evused = 0;
+    for (int i = 0; i < 8; ++i) {
+        ctx->kms[i] = 0.0;
+        ctx->klaunch[i] = 0;
+    }
+    return STAB_OK;
+}
+
+int stab_get_kernel_times(stab_ctx* ctx, double* ms, uint64_t* launches, int32_t nkernels)
+{
+    if (!ctx || nkernels < 0 || nkernels > 8) return fail(STAB_EINVAL, "bad arguments");
+    for (int i = 0; i < nkernels; ++i) {
+        if (ms) ms[i] = ctx->kms[i];
+        if (launches) launches[i] = ctx->klaunch[i];
+    }
     return STAB_OK;
 }
 

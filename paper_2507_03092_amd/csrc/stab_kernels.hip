@@ -460,7 +460,14 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
     for (int b = lane; b < g.bpc; b += 64) {
         const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * g.NB + g.Wr;
         int par = 0;
-        for (int w = 0; w < g.Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+        if (cnt <= mcap) {
+            for (int c = 0; c < cnt; ++c) {
+                const int i = mlist[((size_t)s * mcap + c) * K + k];
+                par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
+            }
+        } else {
+            for (int w = 0; w < g.Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+        }
         obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
     }
     if (lane == 0 && counters) {

@@ -24,7 +24,8 @@ _MODES = {"shared": MODE_SHARED, "full": MODE_FULL, MODE_SHARED: MODE_SHARED, MO
 EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy", "stab_run",
            "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
            "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
-           "stab_get_counters", "stab_last_error")
+           "stab_get_counters", "stab_set_timing", "stab_get_kernel_times", "stab_last_error")
+KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack")
 
 
 class StabError(RuntimeError):
@@ -61,6 +62,8 @@ def lib():
         "stab_reset": (C.c_int, [P, U64, U64]),
         "stab_sample": (C.c_int, [P, I32, P, I64, I32, I32, I32, U64, P, U64, P, P, C.POINTER(C.c_float)]),
         "stab_get_counters": (C.c_int, [P, P, I32]),
+        "stab_set_timing": (C.c_int, [P, I32]),
+        "stab_get_kernel_times": (C.c_int, [P, P, P, I32]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -176,6 +179,16 @@ class Context:
 
     def reset(self, seed: int, first_shot: int = 0) -> None:
         _check(lib().stab_reset(self.h, seed, first_shot))
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().stab_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (total ms, launches)} since set_timing(True)."""
+        ms = np.zeros(8, dtype=np.float64)
+        n = np.zeros(8, dtype=np.uint64)
+        _check(lib().stab_get_kernel_times(self.h, _ptr(ms), _ptr(n), 8))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def counters(self) -> np.ndarray:
         c = np.zeros(8, dtype=np.uint64)
