@@ -92,7 +92,7 @@ struct stab_ctx {
     int* d_err = nullptr;
     unsigned long long* d_counters = nullptr;
     int* d_tmap = nullptr;
-    DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed;
+    DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed, pend;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing (stab_set_timing)
     bool timing = false;
@@ -468,7 +468,7 @@ void stab_destroy(stab_ctx* ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount,
-                      &ctx->obuf, &ctx->events, &ctx->record, &ctx->packed};
+                      &ctx->obuf, &ctx->events, &ctx->record, &ctx->packed, &ctx->pend};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
@@ -561,6 +561,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     int rc;
     if ((rc = ensure(ctx->xcol, (size_t)g.S * g.NB * K * 8)) || (rc = ensure(ctx->zcol, (size_t)g.S * g.NB * K * 8)) ||
         (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->mcount, (size_t)g.S * K * 4)) ||
+        (rc = ensure(ctx->pend, (size_t)g.S * K * 4)) ||
         (rc = ensure(ctx->mlist, (size_t)g.S * kMCap * K * 4)) || (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
         (rc = ensure(ctx->events, (size_t)std::max<long long>(P->ev_cap_max, 1) * 8)) ||
         (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
@@ -578,7 +579,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
 
     const int lds_rd = (seg_lds_words(g.RS) + g.bpc) * 8 <= ctx->max_lds ? 1 : 0;
     const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 8;
-    const size_t chain_lds = (size_t)(2 * g.RS + 2 * g.NB + (g.bpc + 63) / 64) * 8 + (size_t)g.NB * 4 + 64;
+    const size_t chain_lds = (size_t)chain_lds_layout(g).total;
     if (chain_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
 
     HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
@@ -621,15 +622,18 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         } else {
             const MeasPlan& m = P->meas[st.second];
             const int K2 = m.K;
-            TIMED(ctx, 3, (k_classify<<<dim3((K2 + 255) / 256, g.S), 256, 0, ctx->stream>>>(
-                              g, Xcol, K2, cls, mlist, mcount, kMCap)));
-            TIMED(ctx, 4, (k_det<<<dim3((K2 + 3) / 4, g.S), 256, 0, ctx->stream>>>(
-                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist, mcount, kMCap, obuf,
-                              ctx->d_err, ctx->d_counters)));
+            const dim3 cgrid((K2 + 255) / 256, g.S), dgrid((K2 + 3) / 4, g.S);
+            TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 0)));
+            TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
+                                                                 mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -1)));
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
-                              ctx->d_tmap, ctx->seed, ctx->first_shot, base + m.instr, m.pos_base, obuf,
-                              ctx->d_err, ctx->d_counters)));
+                              ctx->d_tmap, (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
+                              m.pos_base, obuf, ctx->d_err, ctx->d_counters)));
+            // targets the chain found deterministic: reduced in parallel on the final tableau
+            TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
+            TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
+                                                                 mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -3)));
             const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
             TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
                               g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,

@@ -30,6 +30,31 @@ struct NoiseDesc {
     int bucket;            // event bucket (= item.w of the noise layer)
 };
 
+// Random-measurement chain: window of pending targets and rows a batched target may touch.
+constexpr int kWin = 64;
+constexpr int kRCap = 32;
+
+// Dynamic LDS layout of the chain kernel (byte offsets), shared by host and device.
+struct ChainLds {
+    int solo;    // block-solo buffers: 2 rows, 2 band masks, per-shot pivot signs, word list
+    int owner;   // NR ints: first window target owning each row pair
+    int win;     // window arrays: 6 x kWin ints + kWin x kRCap row indices
+    int total;
+};
+
+__host__ __device__ inline int align16i(int v) { return (v + 15) & ~15; }
+
+__host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
+{
+    ChainLds L;
+    const int nrdw = (g.bpc + 63) / 64;
+    L.solo = 0;
+    L.owner = align16i((2 * g.RS + 2 * g.NB + nrdw) * 8 + g.NB * 4);
+    L.win = L.owner + align16i(g.NR * 4);
+    L.total = L.win + (6 * kWin + kWin * kRCap) * 4;
+    return L;
+}
+
 struct SegArgs {
     const int4* items;     // {type (0 gates, 1 noise), first gate, gate count, bucket}
     int nitems;

@@ -347,34 +347,44 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 // Classify each target of a measurement layer at layer start: pivot = first stabilizer row
 // with x at the qubit (Sec. 2.4), or -1 (deterministic).  For deterministic ones, list the
 // destabilizer rows with x at the qubit (they select the stabilizers whose product is +-Z_a).
+// Pass 1 (after the random chain) only lists the rows of targets the chain found
+// deterministic (cls == -2) and marks them -3.
 // Thread per (target k, copy s); reads of Xcol [s][band][k] are coalesced over k.
 // ------------------------------------------------------------------------------------------
 __global__ void k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K,
                            int* __restrict__ cls, int* __restrict__ mlist,
-                           int* __restrict__ mcount, int mcap)
+                           int* __restrict__ mcount, int mcap, int pass)
 {
     const int s = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
+    if (pass == 1 && cls[s * K + k] != -2) return;
     const uint64_t* X = Xcol + (size_t)s * g.NB * K;
+    // 8 independent loads in flight per step: the scan is latency-bound otherwise
     int piv = -1;
-    for (int w = 0; w < g.Wr; ++w) {
-        const uint64_t v = X[(size_t)(g.Wr + w) * K + k];
-        if (v) {
-            piv = w * 64 + ctz64(v);
-            break;
-        }
+    for (int w0 = 0; pass == 0 && w0 < g.Wr && piv < 0; w0 += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (w0 + u < g.Wr) ? X[(size_t)(g.Wr + w0 + u) * K + k] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (piv < 0 && v[u]) piv = (w0 + u) * 64 + ctz64(v[u]);
     }
-    cls[s * K + k] = piv;
+    cls[s * K + k] = (pass == 0) ? piv : -3;
     if (piv < 0) {
         int cnt = 0;
-        for (int w = 0; w < g.Wr; ++w) {
-            uint64_t v = X[(size_t)w * K + k];
-            while (v) {
-                const int bit = ctz64(v);
-                v &= v - 1;
-                if (cnt < mcap) mlist[((size_t)s * mcap + cnt) * K + k] = w * 64 + bit;
-                ++cnt;
+        for (int w0 = 0; w0 < g.Wr; w0 += 8) {
+            uint64_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (w0 + u < g.Wr) ? X[(size_t)(w0 + u) * K + k] : 0ull;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                while (v[u]) {
+                    const int bit = ctz64(v[u]);
+                    v[u] &= v[u] - 1;
+                    if (cnt < mcap) mlist[((size_t)s * mcap + cnt) * K + k] = (w0 + u) * 64 + bit;
+                    ++cnt;
+                }
             }
         }
         mcount[s * K + k] = cnt;
@@ -386,16 +396,17 @@ __global__ void k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K,
 // lane owns column words j = lane + 64 t and keeps its part of the scratch row in registers;
 // the i-power of every rowsum step is accumulated per lane and reduced once at the end.
 // The x part of the product must vanish (the product is +-Z_a).
+// tb / rsc: this copy's tableau and sign words.
 template <typename RowFn>
-__device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __restrict__ tab,
-                                               const uint64_t* __restrict__ rs, int s, int lane,
+__device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __restrict__ tb,
+                                               const uint64_t* __restrict__ rsc, int lane,
                                                int nrows, RowFn row_of, int* __restrict__ err)
 {
     uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
     int G = 0, rsum = 0;
-    const uint64_t* base = tab + ((size_t)s * 2 * g.NR + g.NR) * g.RS;
+    const uint64_t* base = tb + (size_t)g.NR * g.RS;
     for (int c = 0; c < nrows; ++c) {
         const int i = row_of(c);
         const uint64_t* row = base + (size_t)i * g.RS;
@@ -409,7 +420,7 @@ __device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __
                 sz[t] ^= z1;
             }
         }
-        rsum += (int)((rs[(size_t)s * g.NB + g.Wr + (i >> 6)] >> (i & 63)) & 1ull);
+        rsum += (int)((rsc[g.Wr + (i >> 6)] >> (i & 63)) & 1ull);
     }
     G = wave_sum(G);
     uint64_t xres = 0;
@@ -421,23 +432,28 @@ __device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __
     return e >> 1;
 }
 
-// Thread per (copy, target): deterministic-at-start targets, one wave each.
+// One wave per (copy, target) whose class is `want`: -1 for the targets deterministic at layer
+// start, -3 for those the random chain found deterministic.  A deterministic outcome is the
+// same at any later point of the layer (Z measurements and X resets on other qubits keep +-Z_a
+// in the stabilizer group with its sign), so both kinds are reduced in parallel.
 __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
                       const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K,
                       const int* __restrict__ cls, const int* __restrict__ mlist,
                       const int* __restrict__ mcount, int mcap, uint8_t* __restrict__ obuf,
-                      int* __restrict__ err, unsigned long long* __restrict__ counters)
+                      int* __restrict__ err, unsigned long long* __restrict__ counters, int want)
 {
     const int lane = threadIdx.x & 63;
     const int k = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
     const int s = blockIdx.y;
     if (k >= K) return;
-    if (cls[s * K + k] >= 0) return;
+    if (cls[s * K + k] != want) return;
     const int cnt = mcount[s * K + k];
     const uint64_t* X = Xcol + (size_t)s * g.NB * K;
+    const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
+    const uint64_t* rsc = rs + (size_t)s * g.NB;
     int shared;
     if (cnt <= mcap) {
-        shared = det_wave_shared(g, tab, rs, s, lane, cnt,
+        shared = det_wave_shared(g, tb, rsc, lane, cnt,
                                  [&](int c) { return mlist[((size_t)s * mcap + c) * K + k]; }, err);
     } else {
         // long list: walk the destabilizer x-words of the column directly
@@ -454,7 +470,7 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
             }
             return 0;
         };
-        shared = det_wave_shared(g, tab, rs, s, lane, cnt, nth, err);
+        shared = det_wave_shared(g, tb, rsc, lane, cnt, nth, err);
     }
     // per-shot part of the sign: parity of the shot's sign bits over the same rows
     for (int b = lane; b < g.bpc; b += 64) {
@@ -477,230 +493,629 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
 }
 
 // ------------------------------------------------------------------------------------------
-// Random-at-start targets of a layer, in op order, one block per copy.  Each may have turned
-// deterministic because of an earlier one in the same layer (then it is reduced like k_det on
-// the current tableau).  Otherwise (Sec. 2.4): pivot p = first stabilizer with x at the qubit;
-// rowsum(i, p) for every other row i with x at the qubit (the pivot's destabilizer is skipped:
-// it is overwritten next); destabilizer <- old pivot row; pivot row <- Z_a with the outcome.
-// Xcol/Zcol of the layer's targets are kept equal to the current tableau's columns.
+// Random-at-start targets of a measurement layer, one block per tableau copy.
+//
+// Sequential semantics (Sec. 2.4): targets are measured in op order; each may have turned
+// deterministic because of an earlier one in the same layer.  A random one: pivot p = first
+// stabilizer with x at the qubit; rowsum(i, p) for every other row i with x at the qubit (the
+// pivot's destabilizer q is skipped: it is overwritten next); q <- old row p; p <- Z_a with
+// the outcome as sign.  A deterministic one reads the stabilizers selected by the
+// destabilizers with x at the qubit.
+//
+// Batching: the block looks at a window of the next pending targets.  A target's "pairs" are
+// the row indices (mod NR, so a destabilizer and its stabilizer count as one) it reads or
+// writes.  Target t of the window runs now iff none of its pairs belongs to an earlier window
+// target (run or deferred).  Such targets touch disjoint rows, and every later target whose
+// inputs an earlier one could change shares a pair with it, so running them at once gives
+// exactly the sequential result; shared words (signs, target columns) are updated with XOR,
+// AND and OR atomics on distinct bits.  A target touching more than kRCap rows runs alone,
+// with the whole block.  Xcol/Zcol of all the layer's targets are kept equal to the current
+// tableau's columns (Zcol is what the end-of-layer reset needs).
 // ------------------------------------------------------------------------------------------
+enum { T_RANDOM = 0, T_DET = 1, T_BIG_RANDOM = 2, T_BIG_DET = 3, T_UNKNOWN = 4, T_DEAD = 5 };
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane)
+{
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    return incl - v;
+}
+
+struct ChainCtx {
+    Geom g;
+    uint64_t* tb;        // this copy's tableau
+    uint64_t* rs;        // this copy's sign words
+    uint64_t* rd;        // all shots' sign words
+    uint64_t* X;         // this copy's Xcol
+    uint64_t* Z;
+    int K, s;
+    const int* tq;
+    const int* tm;
+    uint64_t seed, first_shot, instr;
+    int pos_base;
+    uint8_t* obuf;
+    int* err;
+    unsigned long long* counters;
+};
+
+// Outcome draw of target k for global shot index b.
+__device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
+{
+    uint64_t u0, u1;
+    philox(c.instr, (uint64_t)(c.pos_base + k), c.seed, c.first_shot + (uint64_t)b, u0, u1);
+    return (int)(u0 >> 63);
+}
+
+// One wave: random measurement of target k, pivot stabilizer index ip, rowsum rows[0..n).
+__device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
+{
+    const Geom& g = c.g;
+    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
+    const int a = c.tq[k];
+    uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
+    uint64_t* gq = c.tb + (size_t)ip * RS;
+    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t;
+        const bool in = cw < Wc;
+        xp[t] = in ? gp[cw] : 0ull;
+        zp[t] = in ? gp[Wc + cw] : 0ull;
+        xq[t] = in ? gq[cw] : 0ull;
+        zq[t] = in ? gq[Wc + cw] : 0ull;
+    }
+    const int wq = ip >> 6;
+    const uint64_t bq = 1ull << (ip & 63);
+    const int rsp = (int)((c.rs[Wr + wq] >> (ip & 63)) & 1ull);
+    // rowsum(i, p) for each listed row; sign r_i <- r_i ^ r_p ^ (i-power / 2)
+    for (int r = 0; r < nrows; ++r) {
+        const int i = rows[r];
+        uint64_t* row = c.tb + (size_t)i * RS;
+        int G = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int cw = lane + 64 * t;
+            if (cw < Wc && (xp[t] | zp[t])) {
+                const uint64_t xi = row[cw], zi = row[Wc + cw];
+                G += gsum(xp[t], zp[t], xi, zi);
+                row[cw] = xi ^ xp[t];
+                row[Wc + cw] = zi ^ zp[t];
+            }
+        }
+        G = wave_sum(G);
+        if (lane == 0) {
+            if (G & 1) atomicOr(c.err, 4);
+            const uint64_t flip = (uint64_t)((rsp ^ (G >> 1)) & 1) << (i & 63);
+            if (flip) atomicXor((unsigned long long*)&c.rs[i >> 6], (unsigned long long)flip);
+        }
+    }
+    if (lane == 0) {
+        atomicAnd((unsigned long long*)&c.rs[wq], ~(unsigned long long)bq);
+        if (rsp) atomicOr((unsigned long long*)&c.rs[wq], (unsigned long long)bq);
+        atomicAnd((unsigned long long*)&c.rs[Wr + wq], ~(unsigned long long)bq);
+    }
+    // per-shot signs: the listed rows take the pivot's shot sign; q gets it too; p the outcome
+    for (int b = lane; b < g.bpc; b += 64) {
+        const int gb = c.s * g.bpc + b;
+        uint64_t* rdb = c.rd + (size_t)gb * NB;
+        const uint64_t rdp = (rdb[Wr + wq] >> (ip & 63)) & 1ull;
+        if (rdp)
+            for (int r = 0; r < nrows; ++r)
+                atomicXor((unsigned long long*)&rdb[rows[r] >> 6], 1ull << (rows[r] & 63));
+        const int out = outcome_bit(c, k, gb);
+        atomicAnd((unsigned long long*)&rdb[wq], ~(unsigned long long)bq);
+        if (rdp) atomicOr((unsigned long long*)&rdb[wq], (unsigned long long)bq);
+        atomicAnd((unsigned long long*)&rdb[Wr + wq], ~(unsigned long long)bq);
+        if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
+        c.obuf[(size_t)gb * K + k] = (uint8_t)out;
+    }
+    // columns of the layer's targets that rows p or q touch
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t;
+        if (cw >= Wc) continue;
+        uint64_t bits = xp[t] | zp[t] | xq[t] | zq[t];
+        while (bits) {
+            const int bit = ctz64(bits);
+            bits &= bits - 1;
+            const int qb = cw * 64 + bit;
+            const int k2 = c.tm[qb];
+            if (k2 < 0) continue;
+            const bool xpb = (xp[t] >> bit) & 1ull, zpb = (zp[t] >> bit) & 1ull;
+            unsigned long long* X2 = (unsigned long long*)(c.X + k2);
+            unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
+            for (int r = 0; r < nrows; ++r) {
+                const int i = rows[r];
+                const unsigned long long bb = 1ull << (i & 63);
+                if (xpb) atomicXor(&X2[(size_t)(i >> 6) * K], bb);
+                if (zpb) atomicXor(&Z2[(size_t)(i >> 6) * K], bb);
+            }
+            const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
+            if (xpb) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~(unsigned long long)bq);
+            if (zpb) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~(unsigned long long)bq);
+            atomicAnd(&X2[op], ~(unsigned long long)bq);
+            if (qb == a) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~(unsigned long long)bq);
+        }
+    }
+    // row moves: q <- old p; p <- Z_a
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t;
+        if (cw < Wc) {
+            gq[cw] = xp[t];
+            gq[Wc + cw] = zp[t];
+            gp[cw] = 0ull;
+            gp[Wc + cw] = (cw == (a >> 6)) ? (1ull << (a & 63)) : 0ull;
+        }
+    }
+    if (lane == 0 && c.counters) {
+        atomicAdd(&c.counters[4], 1ull);
+        atomicAdd(&c.counters[5], (unsigned long long)nrows);
+    }
+}
+
+// One wave: a target that turned deterministic; rows = destabilizer indices with x at it.
+__device__ void wave_det(const ChainCtx& c, int k, const int* rows, int nrows, int lane)
+{
+    const Geom& g = c.g;
+    const int shared = det_wave_shared(g, c.tb, c.rs, lane, nrows, [&](int r) { return rows[r]; }, c.err);
+    for (int b = lane; b < g.bpc; b += 64) {
+        const int gb = c.s * g.bpc + b;
+        const uint64_t* rdb = c.rd + (size_t)gb * g.NB + g.Wr;
+        int par = 0;
+        for (int r = 0; r < nrows; ++r) par ^= (int)((rdb[rows[r] >> 6] >> (rows[r] & 63)) & 1ull);
+        c.obuf[(size_t)gb * c.K + k] = (uint8_t)(shared ^ par);
+    }
+    if (lane == 0 && c.counters) {
+        atomicAdd(&c.counters[6], 1ull);
+        atomicAdd(&c.counters[3], (unsigned long long)nrows);
+    }
+}
+
+// Whole block: one target with many rows (dense tableaux).  Called by every thread.
+__device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int nt)
+{
+    const Geom& g = c.g;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
+    const int nrdw = (g.bpc + 63) >> 6;
+    uint64_t* rowp = sm;
+    uint64_t* rowq = rowp + RS;
+    uint64_t* sM = rowq + RS;
+    uint64_t* sC = sM + NB;
+    uint64_t* sRdp = sC + NB;
+    int* nz = (int*)(sRdp + nrdw);
+    __shared__ int s_piv, s_nnz, s_rsp, s_bad, s_G[16];
+    const int a = c.tq[k];
+    uint64_t* X = c.X;
+    uint64_t* Z = c.Z;
+    uint64_t* tb = c.tb;
+
+    if (tid == 0) { s_piv = INT_MAX; s_nnz = 0; s_bad = 0; }
+    __syncthreads();
+    for (int w = tid; w < Wr; w += nt) {
+        const uint64_t v = X[(size_t)(Wr + w) * K + k];
+        if (v) atomicMin(&s_piv, w * 64 + ctz64(v));
+    }
+    __syncthreads();
+    const int ip = s_piv;
+    if (ip == INT_MAX) {
+        // deterministic: thread t owns column word t (Wc <= blockDim.x)
+        uint64_t sx = 0, sz = 0;
+        int G = 0, rsum = 0, nrows = 0;
+        const uint64_t* base = tb + (size_t)g.NR * RS;
+        for (int w = 0; w < Wr; ++w) {
+            uint64_t v = X[(size_t)w * K + k];
+            while (v) {
+                const int i = w * 64 + ctz64(v);
+                v &= v - 1;
+                ++nrows;
+                if (tid < Wc) {
+                    const uint64_t* row = base + (size_t)i * RS;
+                    const uint64_t x1 = row[tid], z1 = row[Wc + tid];
+                    G += gsum(x1, z1, sx, sz);
+                    sx ^= x1;
+                    sz ^= z1;
+                }
+                rsum += (int)((c.rs[Wr + (i >> 6)] >> (i & 63)) & 1ull);
+            }
+        }
+        G = wave_sum(G);
+        const uint64_t xr = wave_or(sx);
+        if (lane == 0) {
+            s_G[wave] = G;
+            if (xr) atomicOr(&s_bad, 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < nwaves; ++w) tot += s_G[w];
+            const int e = (2 * rsum + tot) & 3;
+            if ((e & 1) || s_bad) atomicOr(c.err, 2);
+            s_piv = e >> 1;
+        }
+        __syncthreads();
+        const int shared = s_piv;
+        for (int b = tid; b < g.bpc; b += nt) {
+            const int gb = c.s * g.bpc + b;
+            const uint64_t* rdb = c.rd + (size_t)gb * NB + Wr;
+            int par = 0;
+            for (int w = 0; w < Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+            c.obuf[(size_t)gb * K + k] = (uint8_t)(shared ^ par);
+        }
+        if (tid == 0 && c.counters) {
+            atomicAdd(&c.counters[6], 1ull);
+            atomicAdd(&c.counters[3], (unsigned long long)nrows);
+        }
+        __syncthreads();
+        return;
+    }
+    // random, phase A: gather
+    const int wq = ip >> 6;
+    const uint64_t bq = 1ull << (ip & 63);
+    uint64_t* gp = tb + (size_t)(g.NR + ip) * RS;
+    uint64_t* gq = tb + (size_t)ip * RS;
+    for (int j = tid; j < RS; j += nt) {
+        rowp[j] = gp[j];
+        rowq[j] = gq[j];
+    }
+    for (int w = tid; w < NB; w += nt) {
+        uint64_t v = X[(size_t)w * K + k];
+        if (w == wq || w == Wr + wq) v &= ~bq;
+        sM[w] = v;
+        sC[w] = 0;
+        if (v) nz[atomicAdd(&s_nnz, 1)] = w;
+    }
+    for (int t = tid; t < nrdw; t += nt) sRdp[t] = 0;
+    if (tid == 0) s_rsp = (int)((c.rs[Wr + wq] >> (ip & 63)) & 1ull);
+    __syncthreads();
+    // phase B: per-shot pivot signs; rowsum(i, p), one row per wave at a time
+    for (int b = tid; b < g.bpc; b += nt) {
+        const uint64_t bit = (c.rd[(size_t)(c.s * g.bpc + b) * NB + Wr + wq] >> (ip & 63)) & 1ull;
+        if (bit) atomicOr((unsigned long long*)&sRdp[b >> 6], 1ull << (b & 63));
+    }
+    const int nnz = s_nnz;
+    int idx = 0;
+    for (int t = 0; t < nnz; ++t) {
+        const int w = nz[t];
+        uint64_t v = sM[w];
+        while (v) {
+            const int bit = ctz64(v);
+            v &= v - 1;
+            if ((idx++ % nwaves) != wave) continue;
+            const int i = w * 64 + bit;
+            uint64_t* row = tb + (size_t)i * RS;
+            int G = 0;
+            for (int j = lane; j < Wc; j += 64) {
+                const uint64_t xp = rowp[j], zp = rowp[Wc + j];
+                if ((xp | zp) == 0) continue;
+                const uint64_t xi = row[j], zi = row[Wc + j];
+                G += gsum(xp, zp, xi, zi);
+                row[j] = xi ^ xp;
+                row[Wc + j] = zi ^ zp;
+            }
+            G = wave_sum(G);
+            if (lane == 0) {
+                if (G & 1) atomicOr(c.err, 4);
+                if (G & 2) atomicOr((unsigned long long*)&sC[w], 1ull << bit);
+            }
+        }
+    }
+    if (tid == 0 && c.counters) {
+        atomicAdd(&c.counters[4], 1ull);
+        atomicAdd(&c.counters[5], (unsigned long long)idx);
+    }
+    __syncthreads();
+    // phase C: signs of the rowsum rows; target columns
+    const int rsp = s_rsp;
+    for (int t = tid; t < nnz; t += nt) {
+        const int w = nz[t];
+        c.rs[w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
+    }
+    for (int id = tid; id < nnz * g.bpc; id += nt) {
+        const int b = id / nnz, t = id - b * nnz;
+        if ((sRdp[b >> 6] >> (b & 63)) & 1ull) {
+            const int w = nz[t];
+            c.rd[(size_t)(c.s * g.bpc + b) * NB + w] ^= sM[w];
+        }
+    }
+    for (int j = tid; j < Wc; j += nt) {
+        uint64_t bits = rowp[j] | rowp[Wc + j] | rowq[j] | rowq[Wc + j];
+        while (bits) {
+            const int bit = ctz64(bits);
+            bits &= bits - 1;
+            const int qb = j * 64 + bit;
+            const int k2 = c.tm[qb];
+            if (k2 < 0) continue;
+            const uint64_t xpb = (rowp[j] >> bit) & 1ull, zpb = (rowp[Wc + j] >> bit) & 1ull;
+            uint64_t* X2 = X + k2;
+            uint64_t* Z2 = Z + k2;
+            if (xpb)
+                for (int t = 0; t < nnz; ++t) X2[(size_t)nz[t] * K] ^= sM[nz[t]];
+            if (zpb)
+                for (int t = 0; t < nnz; ++t) Z2[(size_t)nz[t] * K] ^= sM[nz[t]];
+            const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
+            X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
+            Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
+            X2[op] &= ~bq;
+            Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
+        }
+    }
+    __syncthreads();
+    // phase D: row moves, the pivot's signs and the outcome
+    const int za = Wc + (a >> 6);
+    for (int j = tid; j < RS; j += nt) {
+        gq[j] = rowp[j];
+        gp[j] = (j == za) ? (1ull << (a & 63)) : 0ull;
+    }
+    if (tid == 0) {
+        c.rs[wq] = (c.rs[wq] & ~bq) | (rsp ? bq : 0ull);
+        c.rs[Wr + wq] &= ~bq;
+    }
+    for (int b = tid; b < g.bpc; b += nt) {
+        const int gb = c.s * g.bpc + b;
+        const int out = outcome_bit(c, k, gb);
+        uint64_t* rdb = c.rd + (size_t)gb * NB;
+        const uint64_t rdp = (sRdp[b >> 6] >> (b & 63)) & 1ull;
+        rdb[wq] = (rdb[wq] & ~bq) | (rdp ? bq : 0ull);
+        rdb[Wr + wq] = (rdb[Wr + wq] & ~bq) | (out ? bq : 0ull);
+        c.obuf[(size_t)gb * K + k] = (uint8_t)out;
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(512)
 k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
-        const int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
-        uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
+        int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
+        int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
         uint8_t* __restrict__ obuf, int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t sm[];
     const int s = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
-    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS;
-    const int nrdw = (g.bpc + 63) >> 6;
-    uint64_t* rowp = sm;                 // RS words: old pivot row
-    uint64_t* rowq = rowp + RS;          // RS words: old destabilizer of the pivot
-    uint64_t* sM = rowq + RS;            // NB words: rows to rowsum into
-    uint64_t* sC = sM + NB;              // NB words: i-power bit of each rowsum
-    uint64_t* sRdp = sC + NB;            // nrdw words: per-shot sign of the pivot
-    int* nz = (int*)(sRdp + nrdw);       // NB ints: nonzero words of sM
-    __shared__ int s_piv, s_nnz, s_rsp, s_bad, s_G[16];
+    const ChainLds L = chain_lds_layout(g);
+    int* owner = (int*)((char*)sm + L.owner);
+    // window entries live in fixed slots; wpos[] lists the slots in op order
+    int* sk = (int*)((char*)sm + L.win);   // target id per slot
+    int* stype = sk + kWin;                 // T_RANDOM, T_BIG_RANDOM, T_UNKNOWN, T_DEAD
+    int* spiv = stype + kWin;
+    int* scnt = spiv + kWin;
+    int* wpos = scnt + kWin;                // window order -> slot
+    int* wsel = wpos + kWin;                // per window position: selected this round
+    int* srows = wsel + kWin;               // kWin * kRCap
+    __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nkeep, s_any;
 
-    uint64_t* X = Xcol + (size_t)s * NB * K;
-    uint64_t* Z = Zcol + (size_t)s * NB * K;
-    uint64_t* tb = tab + (size_t)s * 2 * g.NR * RS;
-    int* tm = tmap + (size_t)s * g.n;
+    ChainCtx c;
+    c.g = g;
+    c.tb = tab + (size_t)s * 2 * g.NR * g.RS;
+    c.rs = rs + (size_t)s * g.NB;
+    c.rd = rd;
+    c.X = Xcol + (size_t)s * g.NB * K;
+    c.Z = Zcol + (size_t)s * g.NB * K;
+    c.K = K;
+    c.s = s;
+    c.tq = tq;
+    c.tm = tmap + (size_t)s * g.n;
+    c.seed = seed;
+    c.first_shot = first_shot;
+    c.instr = instr;
+    c.pos_base = pos_base;
+    c.obuf = obuf;
+    c.err = err;
+    c.counters = counters;
+    int* pd = pend + (size_t)s * K;
+    int* tmw = tmap + (size_t)s * g.n;
+    int* cl = cls + (size_t)s * K;
 
-    int mine = 0;
-    for (int k = tid; k < K; k += nt) mine |= cls[s * K + k] >= 0;
-    if (!__syncthreads_or(mine)) return;
-
-    for (int k = tid; k < K; k += nt) tm[tq[k]] = k;
+    // pending list: random-at-start targets in op order (stable compaction)
+    int base = 0;
+    for (int k0 = 0; k0 < K; k0 += nt) {
+        const int k = k0 + tid;
+        const bool f = k < K && cl[k] >= 0;
+        const uint64_t m = __ballot(f);
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) before += s_cnt[w];
+            total += s_cnt[w];
+        }
+        if (f) pd[base + before + rank] = k;
+        base += total;
+        __syncthreads();
+    }
+    const int npend = base;
+    if (npend == 0) return;
+    for (int k = tid; k < K; k += nt) tmw[tq[k]] = k;
+    for (int i = tid; i < g.NR; i += nt) owner[i] = INT_MAX;
+    const int w0 = min(kWin, npend);
+    for (int t = tid; t < w0; t += nt) {
+        sk[t] = pd[t];
+        stype[t] = T_UNKNOWN;
+        wpos[t] = t;
+    }
+    if (tid == 0) {
+        s_nwin = w0;
+        s_tail = w0;
+    }
     __syncthreads();
+    int rounds = 0;
 
-    for (int k = 0; k < K; ++k) {
-        if (cls[s * K + k] < 0) continue;
-        const int a = tq[k];
-        if (tid == 0) { s_piv = INT_MAX; s_nnz = 0; s_bad = 0; }
-        __syncthreads();
-        for (int w = tid; w < Wr; w += nt) {
-            const uint64_t v = X[(size_t)(Wr + w) * K + k];
-            if (v) atomicMin(&s_piv, w * 64 + ctz64(v));
-        }
-        __syncthreads();
-        const int ip = s_piv;
-        if (ip == INT_MAX) {
-            // Deterministic now: the block reduces the product, thread t owning column word t
-            // (requires Wc <= blockDim.x).
-            uint64_t sx = 0, sz = 0;
-            int G = 0, rsum = 0, nrows = 0;
-            const uint64_t* base = tb + (size_t)g.NR * RS;
-            for (int w = 0; w < Wr; ++w) {
-                uint64_t v = X[(size_t)w * K + k];
-                while (v) {
-                    const int i = w * 64 + ctz64(v);
-                    v &= v - 1;
-                    ++nrows;
-                    if (tid < Wc) {
-                        const uint64_t* row = base + (size_t)i * RS;
-                        const uint64_t x1 = row[tid], z1 = row[Wc + tid];
-                        G += gsum(x1, z1, sx, sz);
-                        sx ^= x1;
-                        sz ^= z1;
-                    }
-                    rsum += (int)((rs[(size_t)s * NB + Wr + (i >> 6)] >> (i & 63)) & 1ull);
+    while (s_nwin > 0) {
+        ++rounds;
+        const int nwin = s_nwin;
+        // ---- analysis of entries not yet analysed (new, or touched by executed targets) ----
+        for (int t = wave; t < nwin; t += nwaves) {
+            const int sl = wpos[t];
+            if (stype[sl] != T_UNKNOWN) continue;
+            const int k = sk[sl];
+            int pv = INT_MAX;
+            for (int w = lane; w < g.Wr; w += 64) {
+                const uint64_t v = c.X[(size_t)(g.Wr + w) * K + k];
+                if (v) pv = min(pv, w * 64 + ctz64(v));
+            }
+            pv = wave_min(pv);
+            if (pv == INT_MAX) {
+                // deterministic now: evaluated after the chain
+                if (lane == 0) {
+                    stype[sl] = T_DEAD;
+                    cl[k] = -2;
                 }
+                continue;
             }
-            G = wave_sum(G);
-            const uint64_t xr = wave_or(sx);
-            if (lane == 0) {
-                s_G[wave] = G;
-                if (xr) atomicOr(&s_bad, 1);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int tot = 0;
-                for (int w = 0; w < nwaves; ++w) tot += s_G[w];
-                const int e = (2 * rsum + tot) & 3;
-                if ((e & 1) || s_bad) atomicOr(err, 2);
-                s_piv = e >> 1;
-            }
-            __syncthreads();
-            const int shared = s_piv;
-            for (int b = tid; b < g.bpc; b += nt) {
-                const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * NB + Wr;
-                int par = 0;
-                for (int w = 0; w < Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
-                obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
-            }
-            if (tid == 0 && counters) {
-                atomicAdd(&counters[6], 1ull);
-                atomicAdd(&counters[3], (unsigned long long)nrows);
-            }
-            __syncthreads();
-            continue;
-        }
-
-        // ---- random: phase A, gather ----
-        const int wq = ip >> 6;
-        const uint64_t bq = 1ull << (ip & 63);
-        const uint64_t* gp = tb + (size_t)(g.NR + ip) * RS;
-        const uint64_t* gq = tb + (size_t)ip * RS;
-        for (int j = tid; j < RS; j += nt) {
-            rowp[j] = gp[j];
-            rowq[j] = gq[j];
-        }
-        for (int w = tid; w < NB; w += nt) {
-            uint64_t v = X[(size_t)w * K + k];
-            if (w == wq || w == Wr + wq) v &= ~bq;   // neither the pivot nor its destabilizer
-            sM[w] = v;
-            sC[w] = 0;
-            if (v) nz[atomicAdd(&s_nnz, 1)] = w;
-        }
-        for (int t = tid; t < nrdw; t += nt) sRdp[t] = 0;
-        if (tid == 0) s_rsp = (int)((rs[(size_t)s * NB + Wr + wq] >> (ip & 63)) & 1ull);
-        __syncthreads();
-        // ---- phase B: pivot signs per shot; rowsum(i, p), one row per wave at a time ----
-        for (int b = tid; b < g.bpc; b += nt) {
-            const uint64_t bit = (rd[(size_t)(s * g.bpc + b) * NB + Wr + wq] >> (ip & 63)) & 1ull;
-            if (bit) atomicOr((unsigned long long*)&sRdp[b >> 6], 1ull << (b & 63));
-        }
-        const int nnz = s_nnz;
-        {
-            int idx = 0;
-            for (int t = 0; t < nnz; ++t) {
-                const int w = nz[t];
-                uint64_t v = sM[w];
+            const int pw = pv >> 6;
+            const uint64_t pb = 1ull << (pv & 63);
+            int cnt = 0;
+            for (int wb = 0; wb < g.NB; wb += 64) {
+                const int w = wb + lane;
+                uint64_t v = (w < g.NB) ? c.X[(size_t)w * K + k] : 0ull;
+                if (w == pw || w == g.Wr + pw) v &= ~pb;
+                const int pc = __popcll(v);
+                int off = cnt + wave_excl_scan(pc, lane);
                 while (v) {
                     const int bit = ctz64(v);
                     v &= v - 1;
-                    if ((idx++ % nwaves) != wave) continue;
-                    const int i = w * 64 + bit;          // row index over both halves
-                    uint64_t* row = tb + (size_t)i * RS;
-                    int G = 0;
-                    for (int j = lane; j < Wc; j += 64) {
-                        const uint64_t xp = rowp[j], zp = rowp[Wc + j];
-                        if ((xp | zp) == 0) continue;
-                        const uint64_t xi = row[j], zi = row[Wc + j];
-                        G += gsum(xp, zp, xi, zi);
-                        row[j] = xi ^ xp;
-                        row[Wc + j] = zi ^ zp;
-                    }
-                    G = wave_sum(G);
-                    if (lane == 0) {
-                        if (G & 1) atomicOr(err, 4);
-                        if (G & 2) atomicOr((unsigned long long*)&sC[w], 1ull << bit);
-                    }
+                    if (off < kRCap) srows[sl * kRCap + off] = w * 64 + bit;
+                    ++off;
                 }
+                cnt += wave_sum(pc);
             }
-            if (tid == 0 && counters) atomicAdd(&counters[5], (unsigned long long)idx);
-        }
-        __syncthreads();
-        // ---- phase C: signs of the rowsum rows (r_i <- r_i ^ r_p ^ i-power/2); target columns
-        const int rsp = s_rsp;
-        for (int t = tid; t < nnz; t += nt) {
-            const int w = nz[t];
-            rs[(size_t)s * NB + w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
-        }
-        for (int idx = tid; idx < nnz * g.bpc; idx += nt) {
-            const int b = idx / nnz, t = idx - b * nnz;
-            if ((sRdp[b >> 6] >> (b & 63)) & 1ull) {
-                const int w = nz[t];
-                rd[(size_t)(s * g.bpc + b) * NB + w] ^= sM[w];
-            }
-        }
-        for (int j = tid; j < Wc; j += nt) {
-            uint64_t bits = rowp[j] | rowp[Wc + j] | rowq[j] | rowq[Wc + j];
-            while (bits) {
-                const int bit = ctz64(bits);
-                bits &= bits - 1;
-                const int qb = j * 64 + bit;
-                const int k2 = tm[qb];
-                if (k2 < 0) continue;
-                const uint64_t xpb = (rowp[j] >> bit) & 1ull, zpb = (rowp[Wc + j] >> bit) & 1ull;
-                uint64_t* X2 = X + k2;
-                uint64_t* Z2 = Z + k2;
-                if (xpb)
-                    for (int t = 0; t < nnz; ++t) X2[(size_t)nz[t] * K] ^= sM[nz[t]];
-                if (zpb)
-                    for (int t = 0; t < nnz; ++t) Z2[(size_t)nz[t] * K] ^= sM[nz[t]];
-                const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
-                X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
-                Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
-                X2[op] &= ~bq;
-                Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
+            if (lane == 0) {
+                stype[sl] = cnt > kRCap ? T_BIG_RANDOM : T_RANDOM;
+                spiv[sl] = pv;
+                scnt[sl] = cnt;
             }
         }
         __syncthreads();
-        // ---- phase D: row moves, the pivot's signs and the outcome ----
-        {
-            uint64_t* dq = tb + (size_t)ip * RS;
-            uint64_t* dp = tb + (size_t)(g.NR + ip) * RS;
-            const int za = Wc + (a >> 6);
-            for (int j = tid; j < RS; j += nt) {
-                dq[j] = rowp[j];
-                dp[j] = (j == za) ? (1ull << (a & 63)) : 0ull;
+        // ---- drop entries that turned deterministic, refill from the pending list ----
+        if (wave == 0) {
+            const int sl = lane < nwin ? wpos[lane] : -1;
+            const bool keep = sl >= 0 && stype[sl] != T_DEAD;
+            const uint64_t m = __ballot(keep);
+            if (keep) wsel[__popcll(m & ((1ull << lane) - 1ull))] = sl;   // wsel as scratch
+            if (lane == 0) s_nkeep = __popcll(m);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const int nkeep = s_nkeep, tail = s_tail;
+            const int nnew = min(kWin - nkeep, npend - tail);
+            uint64_t usedmask = 0;
+            for (int j = 0; j < nkeep; ++j) usedmask |= 1ull << wsel[j];
+            const uint64_t freem = ~usedmask;
+            const bool fr = (freem >> lane) & 1ull;                 // lane = a free slot
+            const int r = __popcll(freem & ((1ull << lane) - 1ull));  // its rank among free slots
+            if (lane < nkeep) wpos[lane] = wsel[lane];
+            if (fr && r < nnew) {
+                wpos[nkeep + r] = lane;
+                sk[lane] = pd[tail + r];
+                stype[lane] = T_UNKNOWN;
             }
-            if (tid == 0) {
-                uint64_t* rq = &rs[(size_t)s * NB + wq];
-                *rq = (*rq & ~bq) | (rsp ? bq : 0ull);
-                rs[(size_t)s * NB + Wr + wq] &= ~bq;
+            if (lane == 0) {
+                s_nwin = nkeep + nnew;
+                s_tail = tail + nnew;
             }
-            for (int b = tid; b < g.bpc; b += nt) {
-                const uint64_t shot = first_shot + (uint64_t)(s * g.bpc + b);
-                uint64_t u0, u1;
-                philox(instr, (uint64_t)(pos_base + k), seed, shot, u0, u1);
-                const int out = (int)(u0 >> 63);
-                uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * NB;
-                const uint64_t rdp = (sRdp[b >> 6] >> (b & 63)) & 1ull;
-                rdb[wq] = (rdb[wq] & ~bq) | (rdp ? bq : 0ull);
-                rdb[Wr + wq] = (rdb[Wr + wq] & ~bq) | (out ? bq : 0ull);
-                obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)out;
+        }
+        __syncthreads();
+        const int nw = s_nwin;
+        if (nw == 0) break;
+        // ---- selection: only analysed entries before the first unknown or big one ----
+        if (tid == 0) s_bar = nw;
+        __syncthreads();
+        for (int t = tid; t < nw; t += nt) {
+            const int ty = stype[wpos[t]];
+            if (ty == T_UNKNOWN || ty == T_BIG_RANDOM) atomicMin(&s_bar, t);
+            wsel[t] = 0;
+        }
+        __syncthreads();
+        const int bar = s_bar;
+        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
+            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
+            const int sl = wpos[t];
+            int pair = -1;
+            if (r < scnt[sl]) pair = srows[sl * kRCap + r] % g.NR;
+            else if (r == kRCap) pair = spiv[sl];
+            if (pair >= 0) atomicMin(&owner[pair], t);
+        }
+        __syncthreads();
+        for (int t = tid; t < bar; t += nt) {
+            const int sl = wpos[t];
+            bool sel = owner[spiv[sl]] == t;
+            for (int r = 0; sel && r < scnt[sl]; ++r)
+                if (owner[srows[sl * kRCap + r] % g.NR] != t) sel = false;
+            wsel[t] = sel ? 1 : 0;
+        }
+        __syncthreads();
+        // entries sharing a pair with a selected one must be analysed again (big ones, whose
+        // row list is incomplete, always are once anything runs)
+        for (int t = tid; t < nw; t += nt) {
+            const int sl = wpos[t];
+            if (t < bar && wsel[t]) continue;
+            if (stype[sl] == T_UNKNOWN) continue;
+            if (stype[sl] == T_BIG_RANDOM) {
+                if (bar > 0) stype[sl] = T_UNKNOWN;
+                continue;
             }
-            if (tid == 0 && counters) atomicAdd(&counters[4], 1ull);
+            bool stale = false;
+            int o = owner[spiv[sl]];
+            if (o != INT_MAX && o != t && wsel[o]) stale = true;
+            for (int r = 0; !stale && r < scnt[sl]; ++r) {
+                o = owner[srows[sl * kRCap + r] % g.NR];
+                if (o != INT_MAX && o != t && wsel[o]) stale = true;
+            }
+            if (stale) stype[sl] = T_UNKNOWN;
+        }
+        __syncthreads();
+        // ---- execution ----
+        const bool solo = bar == 0 && stype[wpos[0]] == T_BIG_RANDOM;
+        if (solo) {
+            block_solo(c, sk[wpos[0]], sm, tid, nt);
+            if (tid == 0) wsel[0] = 1;
+            // a dense update may touch anything: analyse every remaining entry again
+            for (int t = tid + 1; t < nw; t += nt) stype[wpos[t]] = T_UNKNOWN;
+        } else {
+            for (int t = wave; t < bar; t += nwaves) {
+                if (!wsel[t]) continue;
+                const int sl = wpos[t];
+                wave_random(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
+            }
+        }
+        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
+            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
+            const int sl = wpos[t];
+            if (r < scnt[sl]) owner[srows[sl * kRCap + r] % g.NR] = INT_MAX;
+            else if (r == kRCap) owner[spiv[sl]] = INT_MAX;
+        }
+        __syncthreads();
+        // ---- remove executed entries (their slots become free) ----
+        if (wave == 0) {
+            const bool keep = lane < nw && !wsel[lane];
+            const int sl = lane < nw ? wpos[lane] : 0;
+            const uint64_t m = __ballot(keep);
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            // gather through registers: every lane reads before any lane writes
+            const int v = sl;
+            __builtin_amdgcn_wave_barrier();
+            if (keep) wpos[rank] = v;
+            if (lane == 0) s_nwin = __popcll(m);
         }
         __syncthreads();
     }
-    for (int k = tid; k < K; k += nt) tm[tq[k]] = -1;
+    if (tid == 0 && counters) atomicAdd(&counters[0], (unsigned long long)rounds);
+    for (int k = tid; k < K; k += nt) tmw[tq[k]] = -1;
 }
 
 // ------------------------------------------------------------------------------------------

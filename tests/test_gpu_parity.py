@@ -208,3 +208,46 @@ def test_surface_d71_workload_against_stored_oracle_digests(stab):
     for s in range(shots):
         assert _record_digest(got[s]) == ref["sha256"][s], f"shot {s}"
         assert int(got[s].sum()) == ref["ones"][s]
+
+
+def test_chain_ghz_layer(stab):
+    # one random outcome then every other target deterministic within the same layer
+    n = 300
+    c = Cc.Circuit(n=n)
+    c.gate(Cc.H, [0])
+    for q in range(n - 1):
+        c.gate(Cc.CX, [q, q + 1])
+    c.append(Cc.M, list(np.random.default_rng(1).permutation(n)))
+    _compare(stab, c, shots=8, seed=2, mode="shared", tableau_shots=(0, 7))
+
+
+def test_chain_independent_random_layer(stab):
+    n = 700
+    c = Cc.Circuit(n=n)
+    c.gate(Cc.H, list(range(n)))
+    c.append(Cc.MR, list(range(n)))
+    c.gate(Cc.H, list(range(0, n, 2)))
+    c.append(Cc.M, list(range(n)))
+    _compare(stab, c, shots=4, seed=3, mode="shared", tableau_shots=(0, 3))
+
+
+@pytest.mark.parametrize("order", ["reversed", "random"])
+def test_chain_surface_readout_orders(stab, order):
+    # the final data readout is the most sequential layer; vary its order
+    circ, lay = Cc.surface_code_memory(7, 3, 0.01)
+    data = list(lay.data)
+    data = data[::-1] if order == "reversed" else [int(q) for q in np.random.default_rng(5).permutation(data)]
+    c = Cc.Circuit(n=circ.n)
+    c.kinds, c.ntargets, c.thresholds = list(circ.kinds[:-1]), list(circ.ntargets[:-1]), list(circ.thresholds[:-1])
+    c.targets = list(circ.targets[: len(circ.targets) - circ.ntargets[-1]])
+    c.append(Cc.M, data)
+    _compare(stab, c, shots=16, seed=4, mode="shared", tableau_shots=(0, 15))
+    _compare(stab, c, shots=4, seed=4, mode="full", tableau_shots=(0, 3))
+
+
+def test_chain_mixed_random_layers(stab):
+    # layered random Cliffords with mid-circuit M on 10% (the batched random-circuit workload's shape)
+    for n, seed in ((96, 1), (257, 2)):
+        c = Cc.random_layered_clifford(n, layers=60, seed=seed, meas_every=10, meas_frac=0.1)
+        c.append(Cc.M, list(range(n)))
+        _compare(stab, c, shots=2, seed=seed, mode="shared", tableau_shots=(0, 1))
