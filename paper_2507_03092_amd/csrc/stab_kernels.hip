@@ -221,6 +221,87 @@ __global__ void k_noise_draw(const NoiseDesc* __restrict__ nd, int nn,
 // Segment kernel: grid (NB bands, S copies), 1024 threads.  See the file header.
 // Column j of the staged band: x word at T[(j & 63) * RSP + (j >> 6)], z word at + Wc.
 // ------------------------------------------------------------------------------------------
+constexpr int kSegPrefetch = 8;   // gates / events per thread prefetched into registers
+
+// Registers holding one item's gate or noise-event list (first kSegPrefetch * blockDim.x).
+struct ItemBuf {
+    uint2 v[kSegPrefetch];
+    int count;     // units in the item
+    int type;      // 0 gates, 1 noise, -1 none
+    const uint2* src;
+};
+
+__device__ __forceinline__ void fetch_item(const SegArgs& a, int it, int tid, int nt, ItemBuf& b)
+{
+    if (it >= a.nitems) {
+        b.type = -1;
+        b.count = 0;
+        return;
+    }
+    const int4 item = a.items[it];
+    b.type = item.x;
+    if (item.x == 0) {
+        b.src = a.gates + item.y;
+        b.count = item.z;
+    } else {
+        b.src = a.events + a.ev_base[item.w];
+        b.count = a.ev_count[item.w];
+    }
+#pragma unroll
+    for (int u = 0; u < kSegPrefetch; ++u) {
+        const int i = tid + u * nt;
+        if (i < b.count) b.v[u] = b.src[i];
+    }
+}
+
+__device__ __forceinline__ void apply_gate(uint64_t* T, int RSP, int Wc, uint2 gt, uint64_t& racc)
+{
+    const int kind = (int)(gt.x & 15u);
+    const int q0 = (int)(gt.x >> 4);
+    const int i0 = (q0 & 63) * RSP + (q0 >> 6);
+    const uint64_t x0 = T[i0], z0 = T[i0 + Wc];
+    switch (kind) {
+    case STAB_KIND_H:
+        racc ^= x0 & z0;
+        T[i0] = z0;
+        T[i0 + Wc] = x0;
+        break;
+    case STAB_KIND_S:
+        racc ^= x0 & z0;
+        T[i0 + Wc] = z0 ^ x0;
+        break;
+    case STAB_KIND_X: racc ^= z0; break;
+    case STAB_KIND_Y: racc ^= x0 ^ z0; break;
+    case STAB_KIND_Z: racc ^= x0; break;
+    case STAB_KIND_CX: {
+        const int q1 = (int)gt.y;
+        const int i1 = (q1 & 63) * RSP + (q1 >> 6);
+        const uint64_t x1 = T[i1], z1 = T[i1 + Wc];
+        racc ^= x0 & z1 & ~(x1 ^ z0);
+        T[i1] = x1 ^ x0;
+        T[i0 + Wc] = z0 ^ z1;
+    } break;
+    default: break;
+    }
+}
+
+// Noise event {qubit | pauli << 28, shot}: flip the signs of the rows the Pauli anticommutes with.
+__device__ __forceinline__ void apply_event(const uint64_t* T, int RSP, int Wc, uint2 v, int s, int band,
+                                            const Geom& g, const SegArgs& a, uint64_t* rdacc,
+                                            uint64_t* rd)
+{
+    const int sb = (int)v.y - s * g.bpc;
+    if (sb < 0 || sb >= g.bpc) return;
+    const int q = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
+    const int iq = (q & 63) * RSP + (q >> 6);
+    const uint64_t xq = T[iq], zq = T[iq + Wc];
+    const uint64_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
+    if (m) {
+        if (a.lds_rd) atomicXor((unsigned long long*)&rdacc[sb], (unsigned long long)m);
+        else atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + sb) * g.NB + band], (unsigned long long)m);
+    }
+}
+
 __global__ void __launch_bounds__(1024)
 k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
           uint64_t* __restrict__ rd, SegArgs a)
@@ -235,9 +316,31 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
     uint64_t* rdacc = red + 16;                  // bpc words when a.lds_rd
     uint64_t* gb = tab + ((size_t)s * 2 * g.NR + (size_t)band * 64) * RS;
 
-    for (int i = tid; i < 64 * RS; i += nt) {
-        const int r = i / RS;
-        T[r * RSP + (i - r * RS)] = gb[i];
+    // the first item's list is fetched while the band loads
+    ItemBuf cur, nxt;
+    fetch_item(a, 0, tid, nt, cur);
+
+    // band -> LDS: 16-byte loads (RS is even, so a pair never crosses a row), 8 in flight
+    const int npairs = 32 * RS;
+    const ulonglong2* gb2 = (const ulonglong2*)gb;
+    for (int p0 = 0; p0 < npairs; p0 += 8 * nt) {
+        ulonglong2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * nt + tid;
+            if (p < npairs) v[u] = gb2[p];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = p0 + u * nt + tid;
+            if (p < npairs) {
+                const int i = 2 * p;
+                const int r = i / RS;
+                const int c = i - r * RS;
+                T[r * RSP + c] = v[u].x;
+                T[r * RSP + c + 1] = v[u].y;
+            }
+        }
     }
     if (a.lds_rd)
         for (int b = tid; b < g.bpc; b += nt) rdacc[b] = 0;
@@ -249,59 +352,25 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
     }
     __syncthreads();
 
+    // column j: x word at T[(j & 63) * RSP + (j >> 6)], z word at + Wc
     uint64_t racc = 0;
     for (int it = 0; it < a.nitems; ++it) {
-        const int4 item = a.items[it];
-        if (item.x == 0) {
-            for (int gi = tid; gi < item.z; gi += nt) {
-                const uint2 gt = a.gates[item.y + gi];
-                const int kind = (int)(gt.x & 15u);
-                const int q0 = (int)(gt.x >> 4);
-                const int i0 = (q0 & 63) * RSP + (q0 >> 6);
-                const uint64_t x0 = T[i0], z0 = T[i0 + Wc];
-                switch (kind) {
-                case STAB_KIND_H:
-                    racc ^= x0 & z0;
-                    T[i0] = z0;
-                    T[i0 + Wc] = x0;
-                    break;
-                case STAB_KIND_S:
-                    racc ^= x0 & z0;
-                    T[i0 + Wc] = z0 ^ x0;
-                    break;
-                case STAB_KIND_X: racc ^= z0; break;
-                case STAB_KIND_Y: racc ^= x0 ^ z0; break;
-                case STAB_KIND_Z: racc ^= x0; break;
-                case STAB_KIND_CX: {
-                    const int q1 = (int)gt.y;
-                    const int i1 = (q1 & 63) * RSP + (q1 >> 6);
-                    const uint64_t x1 = T[i1], z1 = T[i1 + Wc];
-                    racc ^= x0 & z1 & ~(x1 ^ z0);
-                    T[i1] = x1 ^ x0;
-                    T[i0 + Wc] = z0 ^ z1;
-                } break;
-                default: break;
-                }
-            }
+        fetch_item(a, it + 1, tid, nt, nxt);       // next item's list, in flight meanwhile
+        if (cur.type == 0) {
+#pragma unroll
+            for (int u = 0; u < kSegPrefetch; ++u)
+                if (tid + u * nt < cur.count) apply_gate(T, RSP, Wc, cur.v[u], racc);
+            for (int gi = tid + kSegPrefetch * nt; gi < cur.count; gi += nt)
+                apply_gate(T, RSP, Wc, cur.src[gi], racc);
         } else {
-            const int cnt = a.ev_count[item.w];
-            const uint2* ev = a.events + a.ev_base[item.w];
-            for (int e = tid; e < cnt; e += nt) {
-                const uint2 v = ev[e];
-                const int sb = (int)v.y - s * g.bpc;
-                if (sb < 0 || sb >= g.bpc) continue;
-                const int q = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
-                const int iq = (q & 63) * RSP + (q >> 6);
-                const uint64_t xq = T[iq], zq = T[iq + Wc];
-                const uint64_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
-                if (m) {
-                    if (a.lds_rd) atomicXor((unsigned long long*)&rdacc[sb], (unsigned long long)m);
-                    else atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + sb) * g.NB + band],
-                                   (unsigned long long)m);
-                }
-            }
+#pragma unroll
+            for (int u = 0; u < kSegPrefetch; ++u)
+                if (tid + u * nt < cur.count) apply_event(T, RSP, Wc, cur.v[u], s, band, g, a, rdacc, rd);
+            for (int e = tid + kSegPrefetch * nt; e < cur.count; e += nt)
+                apply_event(T, RSP, Wc, cur.src[e], s, band, g, a, rdacc, rd);
         }
         __syncthreads();
+        cur = nxt;
     }
 
     if (a.K > 0) {
@@ -322,9 +391,15 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
             T[lane * RSP + c] = v;
         }
         __syncthreads();
-        for (int i = tid; i < 64 * RS; i += nt) {
+        ulonglong2* gw2 = (ulonglong2*)gb;
+        for (int p = tid; p < npairs; p += nt) {
+            const int i = 2 * p;
             const int r = i / RS;
-            gb[i] = T[r * RSP + (i - r * RS)];
+            const int c = i - r * RS;
+            ulonglong2 v;
+            v.x = T[r * RSP + c];
+            v.y = T[r * RSP + c + 1];
+            gw2[p] = v;
         }
     }
     racc = wave_xor(racc);
