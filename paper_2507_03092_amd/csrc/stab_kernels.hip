@@ -526,10 +526,59 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
     const uint64_t* X = Xcol + (size_t)s * g.NB * K;
     const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
     const uint64_t* rsc = rs + (size_t)s * g.NB;
-    int shared;
-    if (cnt <= mcap) {
-        shared = det_wave_shared(g, tb, rsc, lane, cnt,
-                                 [&](int c) { return mlist[((size_t)s * mcap + c) * K + k]; }, err);
+    if (cnt <= mcap && cnt <= 64) {
+        // short list: all loads of a step issued together (row ids, then up to 4 rows at once)
+        const int myrow = lane < cnt ? mlist[((size_t)s * mcap + lane) * K + k] : 0;
+        const int rbit = lane < cnt ? (int)((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull) : 0;
+        const uint64_t* base = tb + (size_t)g.NR * g.RS;
+        uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
+#pragma unroll
+        for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
+        int G = 0;
+        for (int c0 = 0; c0 < cnt; c0 += 4) {
+            uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = __shfl(myrow, min(c0 + u, 63), 64);
+                const uint64_t* row = base + (size_t)i * g.RS;
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    const int j = lane + 64 * t;
+                    const bool ok = c0 + u < cnt && j < g.Wc;
+                    rx[u][t] = ok ? row[j] : 0ull;
+                    rz[u][t] = ok ? row[g.Wc + j] : 0ull;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    G += gsum(rx[u][t], rz[u][t], sx[t], sz[t]);
+                    sx[t] ^= rx[u][t];
+                    sz[t] ^= rz[u][t];
+                }
+            }
+        }
+        G = wave_sum(G);
+        const int rsum = wave_sum(rbit);
+        uint64_t xres = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxWordsPerLane; ++t) xres |= sx[t];
+        xres = wave_or(xres);
+        const int e = (2 * rsum + G) & 3;
+        if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
+        const int shared = e >> 1;
+        // per-shot part of the sign: parity of the shot's sign bits over the same rows
+        for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+            const int b = b0 + lane;
+            const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b, g.bpc - 1)) * g.NB + g.Wr;
+            int par = 0;
+            for (int c = 0; c < cnt; ++c) {
+                const int i = __shfl(myrow, c, 64);
+                par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
+            }
+            if (b < g.bpc) obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
+        }
     } else {
         // long list: walk the destabilizer x-words of the column directly
         auto nth = [&](int c) {
@@ -545,21 +594,13 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
             }
             return 0;
         };
-        shared = det_wave_shared(g, tb, rsc, lane, cnt, nth, err);
-    }
-    // per-shot part of the sign: parity of the shot's sign bits over the same rows
-    for (int b = lane; b < g.bpc; b += 64) {
-        const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * g.NB + g.Wr;
-        int par = 0;
-        if (cnt <= mcap) {
-            for (int c = 0; c < cnt; ++c) {
-                const int i = mlist[((size_t)s * mcap + c) * K + k];
-                par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
-            }
-        } else {
+        const int shared = det_wave_shared(g, tb, rsc, lane, cnt, nth, err);
+        for (int b = lane; b < g.bpc; b += 64) {
+            const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * g.NB + g.Wr;
+            int par = 0;
             for (int w = 0; w < g.Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
+            obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
         }
-        obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
     }
     if (lane == 0 && counters) {
         atomicAdd(&counters[2], 1ull);
