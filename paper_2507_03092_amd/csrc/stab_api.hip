@@ -110,6 +110,7 @@ struct SegPlan {
     int modifies = 0;
     int noise_begin = 0, noise_count = 0;
     int units = 0;
+    int max_units = 0;     // largest noise instruction of the segment (units)
     long long ev_cap = 0;
     int meas = -1;
     long long gate_count = 0;
@@ -317,6 +318,7 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
             noise_tg.insert(noise_tg.end(), t, t + nt);
             unit_start.push_back(seg.units);
             seg.units += units;
+            seg.max_units = std::max(seg.max_units, units);
             ev_base.push_back((int)seg.ev_cap);
             seg.ev_cap += (long long)units * (kind == STAB_DEP2 ? 2 : 1) * g.B;
             if (seg.ev_cap > (1ll << 31) - 1) return fail(STAB_ERANGE, "too many noise locations in one segment");
@@ -589,11 +591,11 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         if (st.first == 0) {
             const SegPlan& sp = P->segs[st.second];
             if (sp.noise_count > 0) {
-                const long long work = (long long)sp.units * g.B;
-                const int blocks = (int)std::min<long long>((work + 255) / 256, 1 << 16);
-                TIMED(ctx, 1, (k_noise_draw<<<blocks, 256, 0, ctx->stream>>>(
-                    P->d_noise + sp.noise_begin, sp.noise_count, P->d_unit_start + sp.noise_begin,
-                    sp.units, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
+                const long long most = (long long)sp.max_units * g.B;
+                const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
+                                (unsigned)sp.noise_count);
+                TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
+                    P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
                     P->d_ev_base, P->d_ev_count)));
             }
             if (sp.item_count > 0 || sp.meas >= 0) {

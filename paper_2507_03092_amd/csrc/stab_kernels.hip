@@ -151,70 +151,64 @@ __global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------
-// Noise draws for one segment: one thread per (shot, noise unit).  Draws never depend on the
-// tableau, so they are made up front and the segment kernel applies them at their layer.
-// Event = (qubit | pauli << 28, shot).
+// Noise draws for one segment: block (x, y) handles kNoiseUnitsPerBlock consecutive (shot,
+// unit) pairs of noise layer y.  Draws never depend on the tableau, so they are made up front
+// and the segment kernel applies them at their layer.  Event = (qubit | pauli << 28, shot).
+// A block gathers its events in LDS and reserves space with one atomic.
 // ------------------------------------------------------------------------------------------
-__global__ void k_noise_draw(const NoiseDesc* __restrict__ nd, int nn,
-                             const int* __restrict__ unit_start, int total_units,
-                             const int* __restrict__ ntg, int B, uint64_t seed,
-                             uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
-                             const int* __restrict__ ev_base, int* __restrict__ ev_count)
+constexpr int kNoiseThreads = 1024;
+constexpr int kNoiseUnitsPerBlock = 4 * kNoiseThreads;
+constexpr int kNoiseLdsEvents = 2048;
+
+__global__ void __launch_bounds__(1024)
+k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int B, uint64_t seed,
+             uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
+             const int* __restrict__ ev_base, int* __restrict__ ev_count)
 {
-    const long long total = (long long)total_units * B;
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(idx / total_units);
-        const int u = (int)(idx - (long long)b * total_units);
-        int lo = 0, hi = nn - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (unit_start[mid] <= u) lo = mid;
-            else hi = mid - 1;
-        }
-        const NoiseDesc d = nd[lo];
-        const int pos = u - unit_start[lo];
+    __shared__ uint2 sev[kNoiseLdsEvents];
+    __shared__ int s_n, s_base;
+    const NoiseDesc d = nd[blockIdx.y];
+    const long long total = (long long)d.units * B;
+    const long long start = (long long)blockIdx.x * kNoiseUnitsPerBlock;
+    if (start >= total) return;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    uint2* gdst = events + ev_base[d.bucket];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const long long idx = start + threadIdx.x + (long long)j * kNoiseThreads;
+        if (idx >= total) break;
+        const int b = (int)(idx / d.units);
+        const int pos = (int)(idx - (long long)b * d.units);
         uint64_t u0, u1;
         philox(instr_base + d.instr, (uint64_t)pos, seed, first_shot + (uint64_t)b, u0, u1);
-        uint2 e0, e1;
+        uint32_t e[2];
         int ne = 0;
         if (d.kind == STAB_KIND_DEP1) {
-            if (u0 < d.t0) {
-                const int P = 1 + (int)__umul64hi(u1, 3ull);
-                e0 = make_uint2((uint32_t)ntg[d.toff + pos] | ((uint32_t)P << 28), (uint32_t)b);
-                ne = 1;
-            }
+            if (u0 < d.t0) e[ne++] = (uint32_t)ntg[d.toff + pos] | ((uint32_t)(1 + (int)__umul64hi(u1, 3ull)) << 28);
         } else if (d.kind == STAB_KIND_DEP2) {
             if (u0 < d.t0) {
                 const int k = 1 + (int)__umul64hi(u1, 15ull);
-                const int pa = k >> 2, pb = k & 3;
-                const uint32_t qa = (uint32_t)ntg[d.toff + 2 * pos];
-                const uint32_t qb = (uint32_t)ntg[d.toff + 2 * pos + 1];
-                if (pa) { e0 = make_uint2(qa | ((uint32_t)pa << 28), (uint32_t)b); ne = 1; }
-                if (pb) {
-                    const uint2 eb = make_uint2(qb | ((uint32_t)pb << 28), (uint32_t)b);
-                    if (ne) e1 = eb;
-                    else e0 = eb;
-                    ++ne;
-                }
+                if (k >> 2) e[ne++] = (uint32_t)ntg[d.toff + 2 * pos] | ((uint32_t)(k >> 2) << 28);
+                if (k & 3) e[ne++] = (uint32_t)ntg[d.toff + 2 * pos + 1] | ((uint32_t)(k & 3) << 28);
             }
         } else {  // PAULI1 with cumulative thresholds
-            int P = 0;
-            if (u0 < d.t0) P = 1;
-            else if (u0 < d.t1) P = 2;
-            else if (u0 < d.t2) P = 3;
-            if (P) {
-                e0 = make_uint2((uint32_t)ntg[d.toff + pos] | ((uint32_t)P << 28), (uint32_t)b);
-                ne = 1;
-            }
+            const int P = (u0 < d.t0) ? 1 : (u0 < d.t1) ? 2 : (u0 < d.t2) ? 3 : 0;
+            if (P) e[ne++] = (uint32_t)ntg[d.toff + pos] | ((uint32_t)P << 28);
         }
-        if (ne) {
-            const int slot = atomicAdd(&ev_count[d.bucket], ne);
-            uint2* dst = events + ev_base[d.bucket] + slot;
-            dst[0] = e0;
-            if (ne == 2) dst[1] = e1;
+        for (int i = 0; i < ne; ++i) {
+            const int slot = atomicAdd(&s_n, 1);
+            const uint2 ev = make_uint2(e[i], (uint32_t)b);
+            if (slot < kNoiseLdsEvents) sev[slot] = ev;
+            else gdst[atomicAdd(&ev_count[d.bucket], 1)] = ev;   // LDS full: direct
         }
     }
+    __syncthreads();
+    const int n = min(s_n, kNoiseLdsEvents);
+    if (n == 0) return;
+    if (threadIdx.x == 0) s_base = atomicAdd(&ev_count[d.bucket], n);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) gdst[s_base + i] = sev[i];
 }
 
 // ------------------------------------------------------------------------------------------
