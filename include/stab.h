@@ -138,6 +138,16 @@ void stab_program_destroy(stab_program *prog);
  * instruction counter to 0. */
 int stab_reset(stab_ctx *ctx, uint64_t seed, uint64_t first_shot);
 
+/* Host-only: validate an op stream and describe how it would be executed for n qubits and
+ * `shots` shots, without touching a device.  out[0..nout) receives, in order: segments (runs of
+ * gate/noise layers between measurement layers), measurement layers, gate layers, gates, noise
+ * instructions, noise units, recorded measurements per shot, largest measurement layer.
+ * Errors: as stab_compile, STAB_EINVAL for nout outside [0, 8]. */
+#define STAB_PLAN_FIELDS 8
+int stab_plan_describe(int32_t n, int32_t shots, int32_t mode, const stab_instr *instrs,
+                       int32_t ninstr, const int32_t *targets, int64_t ntargets, int64_t *out,
+                       int32_t nout);
+
 /* One-call sampler: create a context on dev_buf, run the stream, write the packed record
  * (shots * ceil(nrec/8) bytes) to out_bits, destroy the context.  elapsed_ms (may be NULL)
  * receives the device time from the first kernel to the record on the host. */

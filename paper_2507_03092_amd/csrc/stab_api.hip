@@ -545,6 +545,30 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
 
 int64_t stab_program_records(const stab_program* prog) { return prog ? prog->nrec : -1; }
 
+int stab_plan_describe(int32_t n, int32_t shots, int32_t mode, const stab_instr* instrs, int32_t ninstr,
+                       const int32_t* targets, int64_t ntargets, int64_t* out, int32_t nout)
+{
+    if (nout < 0 || nout > STAB_PLAN_FIELDS || (nout > 0 && !out)) return fail(STAB_EINVAL, "bad output array");
+    uint64_t bytes = 0;
+    int rc = stab_tableau_bytes(n, shots, mode, &bytes);
+    if (rc) return rc;
+    stab_program P;
+    std::vector<int4> items;
+    std::vector<uint2> gates;
+    std::vector<NoiseDesc> noise;
+    std::vector<int> noise_tg, unit_start, ev_base, mtq;
+    rc = compile_stream(make_geom(n, shots, mode), instrs, ninstr, targets, ntargets, P, items, gates, noise,
+                        noise_tg, unit_start, ev_base, mtq);
+    if (rc) return rc;
+    long long gate_layers = 0, units = 0;
+    for (const int4& it : items) gate_layers += it.x == 0 ? 1 : 0;
+    for (const NoiseDesc& d : noise) units += d.units;
+    const int64_t v[STAB_PLAN_FIELDS] = {(int64_t)P.segs.size(), (int64_t)P.meas.size(), gate_layers,
+                                         (int64_t)gates.size(), (int64_t)noise.size(), units, P.nrec, P.Kmax};
+    for (int i = 0; i < nout; ++i) out[i] = v[i];
+    return STAB_OK;
+}
+
 void stab_program_destroy(stab_program* prog)
 {
     if (!prog) return;

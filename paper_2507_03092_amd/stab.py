@@ -24,7 +24,10 @@ _MODES = {"shared": MODE_SHARED, "full": MODE_FULL, MODE_SHARED: MODE_SHARED, MO
 EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy", "stab_run",
            "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
            "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
-           "stab_get_counters", "stab_set_timing", "stab_get_kernel_times", "stab_last_error")
+           "stab_get_counters", "stab_set_timing", "stab_get_kernel_times", "stab_plan_describe",
+           "stab_last_error")
+PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
+               "noise_units", "records", "max_layer")
 KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack")
 
 
@@ -64,6 +67,7 @@ def lib():
         "stab_get_counters": (C.c_int, [P, P, I32]),
         "stab_set_timing": (C.c_int, [P, I32]),
         "stab_get_kernel_times": (C.c_int, [P, P, P, I32]),
+        "stab_plan_describe": (C.c_int, [I32, I32, I32, P, I32, P, I64, P, I32]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -93,6 +97,15 @@ def tableau_bytes(n: int, shots: int, mode="shared") -> int:
     out = C.c_uint64(0)
     _check(lib().stab_tableau_bytes(n, shots, _MODES[mode], C.byref(out)))
     return out.value
+
+
+def plan_describe(circ: _circ.Circuit, shots: int = 1, mode="shared") -> dict:
+    """Host-only: how the library splits a stream into segments and layers (no GPU used)."""
+    instr, tg = circ.arrays()
+    out = np.zeros(len(PLAN_FIELDS), dtype=np.int64)
+    _check(lib().stab_plan_describe(circ.n, shots, _MODES[mode], _ptr(instr), len(instr), _ptr(tg), len(tg),
+                                    _ptr(out), len(PLAN_FIELDS)))
+    return dict(zip(PLAN_FIELDS, (int(v) for v in out)))
 
 
 def max_qubits() -> int:

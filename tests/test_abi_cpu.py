@@ -99,3 +99,66 @@ def test_record_unpacking_layout():
     packed = np.packbits(rec, axis=1, bitorder="little").reshape(-1)
     assert list(packed) == [0b00001101, 1, 0b10000010, 1]
     assert np.array_equal(stab.unpack_record(packed, 2, 9), rec)
+
+
+# ---------------------------------------------------------------- host-side stream compilation ---
+def _c(n):
+    return Cc.Circuit(n=n)
+
+
+def test_plan_splits_layers_and_segments(L):
+    c = _c(4)
+    c.gate(Cc.H, [0, 1])
+    c.gate(Cc.S, [2])            # disjoint: same layer as the H's
+    c.gate(Cc.H, [0])            # repeats qubit 0: new layer ...
+    c.gate(Cc.CX, [1, 2, 2, 3])  # ... which CX(1,2) joins; CX(2,3) repeats 2: new layer
+    c.dep1(0.1, [0, 0])          # noise closes the layer; repeated targets allowed
+    c.gate(Cc.X, [1])
+    c.append(Cc.M, [0, 1, 0])    # repeat splits the measurement into two layers
+    c.append(Cc.R, [2])
+    c.append(Cc.MR, [3])
+    p = stab.plan_describe(c)
+    # layers: [H0 H1 S2] [H0 CX12] [CX23] [X1]
+    assert p["gate_layers"] == 4 and p["gates"] == 7
+    assert p["noise_instructions"] == 1 and p["noise_units"] == 2
+    assert p["measurement_layers"] == 4 and p["records"] == 4 and p["max_layer"] == 2
+    assert p["segments"] == 5      # one before each measurement layer + the trailing one
+
+
+def test_plan_surface_code_counts(L):
+    for d, rounds in ((3, 3), (25, 25)):
+        circ, lay = Cc.surface_code_memory(d, rounds, 1e-3)
+        p = stab.plan_describe(circ, shots=100)
+        assert p["measurement_layers"] == rounds + 1
+        assert p["gate_layers"] == 6 * rounds
+        assert p["gates"] == rounds * (4 * d * (d - 1) + 2 * (d * d - 1) // 2)
+        assert p["records"] == circ.num_measurements() == rounds * (d * d - 1) + d * d
+        assert p["max_layer"] == d * d
+
+
+@pytest.mark.parametrize("bad", ["kind", "range", "neg", "odd", "cx_same", "short", "long"])
+def test_plan_rejects_malformed_streams(L, bad):
+    c = _c(5)
+    c.gate(Cc.H, [0])
+    c.gate(Cc.CX, [0, 1])
+    instr, tg = c.arrays()
+    if bad == "kind":
+        instr["kind"][0] = 99
+    elif bad == "range":
+        tg[0] = 5
+    elif bad == "neg":
+        tg[0] = -1
+    elif bad == "odd":
+        instr["ntargets"][1] = 1
+        tg = tg[:2]
+    elif bad == "cx_same":
+        tg[2] = tg[1]
+    elif bad == "short":
+        tg = tg[:2]
+    elif bad == "long":
+        tg = np.concatenate([tg, np.array([1], dtype=np.int32)])
+    out = np.zeros(8, dtype=np.int64)
+    rc = L.stab_plan_describe(5, 1, 0, instr.ctypes.data_as(C.c_void_p), len(instr),
+                              tg.ctypes.data_as(C.c_void_p), len(tg), out.ctypes.data_as(C.c_void_p), 8)
+    assert rc == stab.EINVAL
+    assert L.stab_last_error()
