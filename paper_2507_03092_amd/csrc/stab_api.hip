@@ -38,7 +38,9 @@ int max_qubits_for_lds(int lds_bytes)
     // 64 * (2*Wc + 1) + kRedWords words must fit
     const int words = lds_bytes / 8 - kRedWords;
     const int wc = (words / 64 - 1) / 2;
-    return std::min(wc, 64 * kMaxWordsPerLane) * 64;
+    // register-resident limits: column words per lane (deterministic wave), band words per lane
+    // (chain analysis: 2 * wc <= 64 * kMaxBandsPerLane)
+    return std::min(std::min(wc, 64 * kMaxWordsPerLane), 32 * kMaxBandsPerLane) * 64;
 }
 
 Geom make_geom(int n, int shots, int mode)

@@ -7,6 +7,8 @@ namespace stabdev {
 
 // Most 64-bit column words a lane of the deterministic-measurement wave keeps in registers.
 constexpr int kMaxWordsPerLane = 4;
+// Most sign/band words (2 * ceil(n/64)) a lane of the chain's analysis wave reads.
+constexpr int kMaxBandsPerLane = 5;
 
 struct Geom {
     int n;    // qubits

@@ -668,6 +668,8 @@ __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
 }
 
 // One wave: random measurement of target k, pivot stabilizer index ip, rowsum rows[0..n).
+// Loads are issued in batches (rows p and q, 4 rowsum rows at a time, the pivot's signs) so a
+// step costs few dependent memory round trips.
 __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
 {
     const Geom& g = c.g;
@@ -675,6 +677,8 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
     const int a = c.tq[k];
     uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
     uint64_t* gq = c.tb + (size_t)ip * RS;
+    const int wq = ip >> 6;
+    const uint64_t bq = 1ull << (ip & 63);
     uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) {
@@ -685,29 +689,46 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
         xq[t] = in ? gq[cw] : 0ull;
         zq[t] = in ? gq[Wc + cw] : 0ull;
     }
-    const int wq = ip >> 6;
-    const uint64_t bq = 1ull << (ip & 63);
-    const int rsp = (int)((c.rs[Wr + wq] >> (ip & 63)) & 1ull);
+    const uint64_t rsw = c.rs[Wr + wq];
+    const int b_lane = min(lane, g.bpc - 1);
+    const uint64_t rdw0 = c.rd[(size_t)(c.s * g.bpc + b_lane) * NB + Wr + wq];   // shot `lane`'s pivot signs
+    const int rsp = (int)((rsw >> (ip & 63)) & 1ull);
     // rowsum(i, p) for each listed row; sign r_i <- r_i ^ r_p ^ (i-power / 2)
-    for (int r = 0; r < nrows; ++r) {
-        const int i = rows[r];
-        uint64_t* row = c.tb + (size_t)i * RS;
-        int G = 0;
+    for (int r0 = 0; r0 < nrows; r0 += 4) {
+        uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
-            const int cw = lane + 64 * t;
-            if (cw < Wc && (xp[t] | zp[t])) {
-                const uint64_t xi = row[cw], zi = row[Wc + cw];
-                G += gsum(xp[t], zp[t], xi, zi);
-                row[cw] = xi ^ xp[t];
-                row[Wc + cw] = zi ^ zp[t];
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t* row = c.tb + (size_t)rows[min(r0 + u, nrows - 1)] * RS;
+#pragma unroll
+            for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                const int cw = lane + 64 * t;
+                const bool ok = r0 + u < nrows && cw < Wc && (xp[t] | zp[t]);
+                rx[u][t] = ok ? row[cw] : 0ull;
+                rz[u][t] = ok ? row[Wc + cw] : 0ull;
             }
         }
-        G = wave_sum(G);
-        if (lane == 0) {
-            if (G & 1) atomicOr(c.err, 4);
-            const uint64_t flip = (uint64_t)((rsp ^ (G >> 1)) & 1) << (i & 63);
-            if (flip) atomicXor((unsigned long long*)&c.rs[i >> 6], (unsigned long long)flip);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (r0 + u < nrows) {
+                const int i = rows[r0 + u];
+                uint64_t* row = c.tb + (size_t)i * RS;
+                int G = 0;
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    const int cw = lane + 64 * t;
+                    if (cw < Wc && (xp[t] | zp[t])) {
+                        G += gsum(xp[t], zp[t], rx[u][t], rz[u][t]);
+                        row[cw] = rx[u][t] ^ xp[t];
+                        row[Wc + cw] = rz[u][t] ^ zp[t];
+                    }
+                }
+                G = wave_sum(G);
+                if (lane == 0) {
+                    if (G & 1) atomicOr(c.err, 4);
+                    const uint64_t flip = (uint64_t)((rsp ^ (G >> 1)) & 1) << (i & 63);
+                    if (flip) atomicXor((unsigned long long*)&c.rs[i >> 6], (unsigned long long)flip);
+                }
+            }
         }
     }
     if (lane == 0) {
@@ -719,7 +740,7 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
     for (int b = lane; b < g.bpc; b += 64) {
         const int gb = c.s * g.bpc + b;
         uint64_t* rdb = c.rd + (size_t)gb * NB;
-        const uint64_t rdp = (rdb[Wr + wq] >> (ip & 63)) & 1ull;
+        const uint64_t rdp = ((b < 64 ? rdw0 : rdb[Wr + wq]) >> (ip & 63)) & 1ull;
         if (rdp)
             for (int r = 0; r < nrows; ++r)
                 atomicXor((unsigned long long*)&rdb[rows[r] >> 6], 1ull << (rows[r] & 63));
@@ -1073,10 +1094,18 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int sl = wpos[t];
             if (stype[sl] != T_UNKNOWN) continue;
             const int k = sk[sl];
+            // all column words at once (NB <= 64 * kMaxBandsPerLane); pivot from the stabilizer half
+            uint64_t cw[kMaxBandsPerLane];
+#pragma unroll
+            for (int u = 0; u < kMaxBandsPerLane; ++u) {
+                const int w = lane + 64 * u;
+                cw[u] = (w < g.NB) ? c.X[(size_t)w * K + k] : 0ull;
+            }
             int pv = INT_MAX;
-            for (int w = lane; w < g.Wr; w += 64) {
-                const uint64_t v = c.X[(size_t)(g.Wr + w) * K + k];
-                if (v) pv = min(pv, w * 64 + ctz64(v));
+#pragma unroll
+            for (int u = 0; u < kMaxBandsPerLane; ++u) {
+                const int w = lane + 64 * u;
+                if (w >= g.Wr && w < g.NB && cw[u]) pv = min(pv, (w - g.Wr) * 64 + ctz64(cw[u]));
             }
             pv = wave_min(pv);
             if (pv == INT_MAX) {
@@ -1090,9 +1119,10 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int pw = pv >> 6;
             const uint64_t pb = 1ull << (pv & 63);
             int cnt = 0;
-            for (int wb = 0; wb < g.NB; wb += 64) {
-                const int w = wb + lane;
-                uint64_t v = (w < g.NB) ? c.X[(size_t)w * K + k] : 0ull;
+#pragma unroll
+            for (int u = 0; u < kMaxBandsPerLane; ++u) {
+                const int w = lane + 64 * u;
+                uint64_t v = cw[u];
                 if (w == pw || w == g.Wr + pw) v &= ~pb;
                 const int pc = __popcll(v);
                 int off = cnt + wave_excl_scan(pc, lane);

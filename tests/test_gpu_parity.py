@@ -251,3 +251,22 @@ def test_chain_mixed_random_layers(stab):
         c = Cc.random_layered_clifford(n, layers=60, seed=seed, meas_every=10, meas_frac=0.1)
         c.append(Cc.M, list(range(n)))
         _compare(stab, c, shots=2, seed=seed, mode="shared", tableau_shots=(0, 1))
+
+
+def test_largest_supported_n(stab):
+    # n = stab_max_qubits(): every band of both halves, the last column word and the last
+    # sign words are exercised; measurements include random and deterministic ones far apart
+    n = stab.max_qubits()
+    rng = np.random.default_rng(11)
+    c = Cc.Circuit(n=n)
+    c.gate(Cc.H, list(range(0, n, 5)) + [n - 1])
+    perm = rng.permutation(n)
+    c.gate(Cc.CX, [int(q) for q in perm[:1200]])
+    c.gate(Cc.S, [int(q) for q in perm[1200:1300]])
+    meas = sorted(set([0, 63, 64, n - 64, n - 2, n - 1] + [int(q) for q in rng.choice(n, 300, replace=False)]))
+    c.append(Cc.M, meas)
+    c.gate(Cc.CX, [int(q) for q in rng.permutation(n)[:800]])
+    c.dep1(0.05, list(range(n - 200, n)))
+    c.append(Cc.MR, [int(q) for q in rng.choice(n, 200, replace=False)])
+    c.append(Cc.M, [n - 1, n - 2, 0])
+    _compare(stab, c, shots=2, seed=1, mode="shared", tableau_shots=(1,))
