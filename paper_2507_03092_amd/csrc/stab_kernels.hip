@@ -1086,7 +1086,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     __syncthreads();
     int rounds = 0;
 
-    while (s_nwin > 0) {
+    // a round can empty the window; the refill below brings in the next pending targets
+    while (s_nwin > 0 || s_tail < npend) {
         ++rounds;
         const int nwin = s_nwin;
         // ---- analysis of entries not yet analysed (new, or touched by executed targets) ----
