@@ -32,15 +32,18 @@ struct NoiseDesc {
     int bucket;            // event bucket (= item.w of the noise layer)
 };
 
-// Random-measurement chain: window of pending targets and rows a batched target may touch.
+// Random-measurement chain: window of pending targets, rows a batched target may touch, and
+// the largest batch whose pivot rows are staged in LDS so all waves share its rowsums.
 constexpr int kWin = 64;
-constexpr int kRCap = 32;
+constexpr int kRCap = 128;
+constexpr int kWide = 4;
 
 // Dynamic LDS layout of the chain kernel (byte offsets), shared by host and device.
 struct ChainLds {
     int solo;    // block-solo buffers: 2 rows, 2 band masks, per-shot pivot signs, word list
     int owner;   // NR ints: first window target owning each row pair
-    int win;     // window arrays: 6 x kWin ints + kWin x kRCap row indices
+    int wide;    // kWide x 2 rows (pivot row and its destabilizer) of the batch
+    int win;     // window arrays: 8 x kWin ints + kWin x kRCap row indices
     int total;
 };
 
@@ -52,8 +55,9 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
     const int nrdw = (g.bpc + 63) / 64;
     L.solo = 0;
     L.owner = align16i((2 * g.RS + 2 * g.NB + nrdw) * 8 + g.NB * 4);
-    L.win = L.owner + align16i(g.NR * 4);
-    L.total = L.win + (6 * kWin + kWin * kRCap) * 4;
+    L.wide = L.owner + align16i(g.NR * 4);
+    L.win = L.wide + kWide * 2 * g.RS * 8;
+    L.total = L.win + (8 * kWin + kWin * kRCap) * 4;
     return L;
 }
 

@@ -667,50 +667,33 @@ __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
     return (int)(u0 >> 63);
 }
 
-// One wave: random measurement of target k, pivot stabilizer index ip, rowsum rows[0..n).
-// Loads are issued in batches (rows p and q, 4 rowsum rows at a time, the pivot's signs) so a
-// step costs few dependent memory round trips.
-__device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
+// rowsum(i, p) for rows[r], r = r0, r0 + stride, ... < nrows, pivot row words in registers
+// (lane owns column words lane + 64 t).  Sign r_i <- r_i ^ r_p ^ (i-power / 2).  Loads of 4 rows
+// are issued together.
+__device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_t* zp, int rsp,
+                            const int* rows, int nrows, int r0, int stride, int lane)
 {
     const Geom& g = c.g;
-    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
-    const int a = c.tq[k];
-    uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
-    uint64_t* gq = c.tb + (size_t)ip * RS;
-    const int wq = ip >> 6;
-    const uint64_t bq = 1ull << (ip & 63);
-    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
-#pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-        const int cw = lane + 64 * t;
-        const bool in = cw < Wc;
-        xp[t] = in ? gp[cw] : 0ull;
-        zp[t] = in ? gp[Wc + cw] : 0ull;
-        xq[t] = in ? gq[cw] : 0ull;
-        zq[t] = in ? gq[Wc + cw] : 0ull;
-    }
-    const uint64_t rsw = c.rs[Wr + wq];
-    const int b_lane = min(lane, g.bpc - 1);
-    const uint64_t rdw0 = c.rd[(size_t)(c.s * g.bpc + b_lane) * NB + Wr + wq];   // shot `lane`'s pivot signs
-    const int rsp = (int)((rsw >> (ip & 63)) & 1ull);
-    // rowsum(i, p) for each listed row; sign r_i <- r_i ^ r_p ^ (i-power / 2)
-    for (int r0 = 0; r0 < nrows; r0 += 4) {
+    const int Wc = g.Wc, RS = g.RS;
+    for (int rb = r0; rb < nrows; rb += 4 * stride) {
         uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint64_t* row = c.tb + (size_t)rows[min(r0 + u, nrows - 1)] * RS;
+            const int r = rb + u * stride;
+            const uint64_t* row = c.tb + (size_t)rows[min(r, nrows - 1)] * RS;
 #pragma unroll
             for (int t = 0; t < kMaxWordsPerLane; ++t) {
                 const int cw = lane + 64 * t;
-                const bool ok = r0 + u < nrows && cw < Wc && (xp[t] | zp[t]);
+                const bool ok = r < nrows && cw < Wc && (xp[t] | zp[t]);
                 rx[u][t] = ok ? row[cw] : 0ull;
                 rz[u][t] = ok ? row[Wc + cw] : 0ull;
             }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (r0 + u < nrows) {
-                const int i = rows[r0 + u];
+            const int r = rb + u * stride;
+            if (r < nrows) {
+                const int i = rows[r];
                 uint64_t* row = c.tb + (size_t)i * RS;
                 int G = 0;
 #pragma unroll
@@ -731,16 +714,31 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
             }
         }
     }
+}
+
+// The rest of a random measurement, one wave: per-shot signs and outcomes, the columns of the
+// layer's targets touched by rows p or q, the pivot's signs, and the row moves q <- p,
+// p <- Z_a.  xp..zq: the old rows p and q (lane owns column words lane + 64 t).
+__device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
+                                const uint64_t* zp, const uint64_t* xq, const uint64_t* zq,
+                                const int* rows, int nrows, int lane)
+{
+    const Geom& g = c.g;
+    const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
+    const int a = c.tq[k];
+    uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
+    uint64_t* gq = c.tb + (size_t)ip * RS;
+    const int wq = ip >> 6;
+    const uint64_t bq = 1ull << (ip & 63);
     if (lane == 0) {
         atomicAnd((unsigned long long*)&c.rs[wq], ~(unsigned long long)bq);
         if (rsp) atomicOr((unsigned long long*)&c.rs[wq], (unsigned long long)bq);
         atomicAnd((unsigned long long*)&c.rs[Wr + wq], ~(unsigned long long)bq);
     }
-    // per-shot signs: the listed rows take the pivot's shot sign; q gets it too; p the outcome
     for (int b = lane; b < g.bpc; b += 64) {
         const int gb = c.s * g.bpc + b;
         uint64_t* rdb = c.rd + (size_t)gb * NB;
-        const uint64_t rdp = ((b < 64 ? rdw0 : rdb[Wr + wq]) >> (ip & 63)) & 1ull;
+        const uint64_t rdp = (rdb[Wr + wq] >> (ip & 63)) & 1ull;
         if (rdp)
             for (int r = 0; r < nrows; ++r)
                 atomicXor((unsigned long long*)&rdb[rows[r] >> 6], 1ull << (rows[r] & 63));
@@ -751,7 +749,6 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
         if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
         c.obuf[(size_t)gb * K + k] = (uint8_t)out;
     }
-    // columns of the layer's targets that rows p or q touch
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) {
         const int cw = lane + 64 * t;
@@ -779,7 +776,6 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
             if (qb == a) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~(unsigned long long)bq);
         }
     }
-    // row moves: q <- old p; p <- Z_a
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) {
         const int cw = lane + 64 * t;
@@ -794,6 +790,30 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
         atomicAdd(&c.counters[4], 1ull);
         atomicAdd(&c.counters[5], (unsigned long long)nrows);
     }
+}
+
+// Load one row's words for this lane (from global or LDS).
+__device__ __forceinline__ void load_row_lane(const uint64_t* row, int Wc, int lane, uint64_t* x, uint64_t* z)
+{
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t;
+        const bool in = cw < Wc;
+        x[t] = in ? row[cw] : 0ull;
+        z[t] = in ? row[Wc + cw] : 0ull;
+    }
+}
+
+// One wave: the whole random measurement of target k (pivot stabilizer index ip).
+__device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
+{
+    const Geom& g = c.g;
+    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
+    load_row_lane(c.tb + (size_t)(g.NR + ip) * g.RS, g.Wc, lane, xp, zp);
+    load_row_lane(c.tb + (size_t)ip * g.RS, g.Wc, lane, xq, zq);
+    const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+    rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
+    random_epilogue(c, k, ip, rsp, xp, zp, xq, zq, rows, nrows, lane);
 }
 
 // One wave: a target that turned deterministic; rows = destabilizer indices with x at it.
@@ -1026,8 +1046,12 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* scnt = spiv + kWin;
     int* wpos = scnt + kWin;                // window order -> slot
     int* wsel = wpos + kWin;                // per window position: selected this round
-    int* srows = wsel + kWin;               // kWin * kRCap
-    __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nkeep, s_any;
+    int* wstale = wsel + kWin;              // per window position: must be analysed again
+    int* selpos = wstale + kWin;            // positions selected this round
+    int* srows = selpos + kWin;             // kWin * kRCap
+    uint64_t* wideP = (uint64_t*)((char*)sm + L.wide);   // kWide pivot rows
+    uint64_t* wideQ = wideP + kWide * g.RS;               // and their destabilizers
+    __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nsel, s_rsp[kWide];
 
     ChainCtx c;
     c.g = g;
@@ -1147,19 +1171,17 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int sl = lane < nwin ? wpos[lane] : -1;
             const bool keep = sl >= 0 && stype[sl] != T_DEAD;
             const uint64_t m = __ballot(keep);
-            if (keep) wsel[__popcll(m & ((1ull << lane) - 1ull))] = sl;   // wsel as scratch
-            if (lane == 0) s_nkeep = __popcll(m);
-        }
-        __syncthreads();
-        if (wave == 0) {
-            const int nkeep = s_nkeep, tail = s_tail;
+            const int nkeep = __popcll(m);
+            const uint64_t usedmask = wave_or(keep ? (1ull << sl) : 0ull);
+            const int tail = s_tail;
             const int nnew = min(kWin - nkeep, npend - tail);
-            uint64_t usedmask = 0;
-            for (int j = 0; j < nkeep; ++j) usedmask |= 1ull << wsel[j];
             const uint64_t freem = ~usedmask;
-            const bool fr = (freem >> lane) & 1ull;                 // lane = a free slot
-            const int r = __popcll(freem & ((1ull << lane) - 1ull));  // its rank among free slots
-            if (lane < nkeep) wpos[lane] = wsel[lane];
+            const bool fr = (freem >> lane) & 1ull;                   // lane = a free slot
+            const int r = __popcll(freem & ((1ull << lane) - 1ull));   // its rank among free slots
+            const int kp = __popcll(m & ((1ull << lane) - 1ull));
+            // every lane has read what it needs; now write the new order
+            __builtin_amdgcn_wave_barrier();
+            if (keep) wpos[kp] = sl;
             if (fr && r < nnew) {
                 wpos[nkeep + r] = lane;
                 sk[lane] = pd[tail + r];
@@ -1179,66 +1201,98 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         for (int t = tid; t < nw; t += nt) {
             const int ty = stype[wpos[t]];
             if (ty == T_UNKNOWN || ty == T_BIG_RANDOM) atomicMin(&s_bar, t);
-            wsel[t] = 0;
+            wstale[t] = 0;
         }
         __syncthreads();
         const int bar = s_bar;
+        // first owner of every row pair among the eligible entries
         for (int id = tid; id < bar * (kRCap + 1); id += nt) {
             const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
             const int sl = wpos[t];
-            int pair = -1;
-            if (r < scnt[sl]) pair = srows[sl * kRCap + r] % g.NR;
-            else if (r == kRCap) pair = spiv[sl];
+            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
             if (pair >= 0) atomicMin(&owner[pair], t);
         }
+        for (int t = tid; t < nw; t += nt) wsel[t] = t < bar ? 1 : 0;
         __syncthreads();
-        for (int t = tid; t < bar; t += nt) {
+        // an eligible entry runs iff it owns all its pairs
+        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
+            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
             const int sl = wpos[t];
-            bool sel = owner[spiv[sl]] == t;
-            for (int r = 0; sel && r < scnt[sl]; ++r)
-                if (owner[srows[sl * kRCap + r] % g.NR] != t) sel = false;
-            wsel[t] = sel ? 1 : 0;
+            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
+            if (pair >= 0 && owner[pair] != t) wsel[t] = 0;
         }
         __syncthreads();
-        // entries sharing a pair with a selected one must be analysed again (big ones, whose
-        // row list is incomplete, always are once anything runs)
+        // entries sharing a pair with a selected one must be analysed again
+        for (int id = tid; id < nw * (kRCap + 1); id += nt) {
+            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
+            const int sl = wpos[t];
+            if (wsel[t] || stype[sl] != T_RANDOM) continue;
+            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
+            if (pair < 0) continue;
+            const int o = owner[pair];
+            if (o != INT_MAX && o != t && wsel[o]) wstale[t] = 1;
+        }
+        __syncthreads();
+        // big entries (incomplete row lists) are analysed again whenever anything runs
         for (int t = tid; t < nw; t += nt) {
             const int sl = wpos[t];
-            if (t < bar && wsel[t]) continue;
-            if (stype[sl] == T_UNKNOWN) continue;
-            if (stype[sl] == T_BIG_RANDOM) {
-                if (bar > 0) stype[sl] = T_UNKNOWN;
-                continue;
-            }
-            bool stale = false;
-            int o = owner[spiv[sl]];
-            if (o != INT_MAX && o != t && wsel[o]) stale = true;
-            for (int r = 0; !stale && r < scnt[sl]; ++r) {
-                o = owner[srows[sl * kRCap + r] % g.NR];
-                if (o != INT_MAX && o != t && wsel[o]) stale = true;
-            }
-            if (stale) stype[sl] = T_UNKNOWN;
+            if (wstale[t] || (stype[sl] == T_BIG_RANDOM && bar > 0)) stype[sl] = T_UNKNOWN;
+        }
+        if (wave == 0) {
+            const bool sel = lane < bar && wsel[lane];
+            const uint64_t m = __ballot(sel);
+            if (sel) selpos[__popcll(m & ((1ull << lane) - 1ull))] = lane;
+            if (lane == 0) s_nsel = __popcll(m);
         }
         __syncthreads();
+        const int nsel = s_nsel;
         // ---- execution ----
-        const bool solo = bar == 0 && stype[wpos[0]] == T_BIG_RANDOM;
-        if (solo) {
+        if (bar == 0 && stype[wpos[0]] == T_BIG_RANDOM) {
             block_solo(c, sk[wpos[0]], sm, tid, nt);
-            if (tid == 0) wsel[0] = 1;
+            if (tid == 0) {
+                wsel[0] = 1;
+                if (counters) atomicAdd(&counters[1], 1ull);
+            }
             // a dense update may touch anything: analyse every remaining entry again
             for (int t = tid + 1; t < nw; t += nt) stype[wpos[t]] = T_UNKNOWN;
+        } else if (nsel <= kWide) {
+            // few targets: stage their pivot rows, spread their rowsum rows over all waves
+            for (int id = tid; id < nsel * g.RS; id += nt) {
+                const int j = id / g.RS, w = id - j * g.RS;
+                const int ip = spiv[wpos[selpos[j]]];
+                wideP[j * g.RS + w] = c.tb[(size_t)(g.NR + ip) * g.RS + w];
+                wideQ[j * g.RS + w] = c.tb[(size_t)ip * g.RS + w];
+            }
+            if (tid < nsel) {
+                const int ip = spiv[wpos[selpos[tid]]];
+                s_rsp[tid] = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+            }
+            __syncthreads();
+            for (int j = 0; j < nsel; ++j) {
+                const int sl = wpos[selpos[j]];
+                if (wave >= scnt[sl]) continue;
+                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
+                load_row_lane(wideP + j * g.RS, g.Wc, lane, xp, zp);
+                rowsum_rows(c, xp, zp, s_rsp[j], srows + sl * kRCap, scnt[sl], wave, nwaves, lane);
+            }
+            if (wave < nsel) {
+                const int sl = wpos[selpos[wave]];
+                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
+                load_row_lane(wideP + wave * g.RS, g.Wc, lane, xp, zp);
+                load_row_lane(wideQ + wave * g.RS, g.Wc, lane, xq, zq);
+                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, xq, zq, srows + sl * kRCap, scnt[sl], lane);
+            }
         } else {
-            for (int t = wave; t < bar; t += nwaves) {
-                if (!wsel[t]) continue;
-                const int sl = wpos[t];
+            for (int j = wave; j < nsel; j += nwaves) {
+                const int sl = wpos[selpos[j]];
                 wave_random(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
             }
         }
         for (int id = tid; id < bar * (kRCap + 1); id += nt) {
             const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
             const int sl = wpos[t];
-            if (r < scnt[sl]) owner[srows[sl * kRCap + r] % g.NR] = INT_MAX;
-            else if (r == kRCap) owner[spiv[sl]] = INT_MAX;
+            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
+            if (pair >= 0) owner[pair] = INT_MAX;
         }
         __syncthreads();
         // ---- remove executed entries (their slots become free) ----
@@ -1247,10 +1301,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int sl = lane < nw ? wpos[lane] : 0;
             const uint64_t m = __ballot(keep);
             const int rank = __popcll(m & ((1ull << lane) - 1ull));
-            // gather through registers: every lane reads before any lane writes
-            const int v = sl;
             __builtin_amdgcn_wave_barrier();
-            if (keep) wpos[rank] = v;
+            if (keep) wpos[rank] = sl;
             if (lane == 0) s_nwin = __popcll(m);
         }
         __syncthreads();
