@@ -657,7 +657,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               ctx->d_tmap, (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
-                              m.pos_base, obuf, ctx->d_err, ctx->d_counters)));
+                              m.pos_base, m.kind != STAB_M ? 1 : 0, obuf, ctx->d_err, ctx->d_counters)));
             // targets the chain found deterministic: reduced in parallel on the final tableau
             TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
             TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,

@@ -651,7 +651,8 @@ struct ChainCtx {
     uint64_t* Z;
     int K, s;
     const int* tq;
-    const int* tm;
+    int* tm;                 // qubit -> column-upkeep code (see random_epilogue)
+    int zcols;               // 1 when the layer resets, so z columns are needed
     uint64_t seed, first_shot, instr;
     int pos_base;
     uint8_t* obuf;
@@ -718,7 +719,10 @@ __device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_
 
 // The rest of a random measurement, one wave: per-shot signs and outcomes, the columns of the
 // layer's targets touched by rows p or q, the pivot's signs, and the row moves q <- p,
-// p <- Z_a.  xp..zq: the old rows p and q (lane owns column words lane + 64 t).
+// p <- Z_a.  xp..zq: the old rows p and q (lane owns column words lane + 64 t).  rows[] is
+// sorted, so runs in one 64-row word are applied as one word mask.
+// Column upkeep follows tmap: k >= 0 keeps both columns of target k, -(k+2) only its z column
+// (needed by the end-of-layer reset), -1 neither (nothing reads them again).
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const uint64_t* xq, const uint64_t* zq,
                                 const int* rows, int nrows, int lane)
@@ -739,9 +743,20 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         const int gb = c.s * g.bpc + b;
         uint64_t* rdb = c.rd + (size_t)gb * NB;
         const uint64_t rdp = (rdb[Wr + wq] >> (ip & 63)) & 1ull;
-        if (rdp)
-            for (int r = 0; r < nrows; ++r)
-                atomicXor((unsigned long long*)&rdb[rows[r] >> 6], 1ull << (rows[r] & 63));
+        if (rdp) {
+            uint64_t m = 0;
+            int wc = -1;
+            for (int r = 0; r < nrows; ++r) {
+                const int w = rows[r] >> 6;
+                if (w != wc) {
+                    if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
+                    wc = w;
+                    m = 0;
+                }
+                m |= 1ull << (rows[r] & 63);
+            }
+            if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
+        }
         const int out = outcome_bit(c, k, gb);
         atomicAnd((unsigned long long*)&rdb[wq], ~(unsigned long long)bq);
         if (rdp) atomicOr((unsigned long long*)&rdb[wq], (unsigned long long)bq);
@@ -758,22 +773,39 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
             const int bit = ctz64(bits);
             bits &= bits - 1;
             const int qb = cw * 64 + bit;
-            const int k2 = c.tm[qb];
-            if (k2 < 0) continue;
+            const int code = c.tm[qb];
+            if (code == -1) continue;
+            const bool xupd = code >= 0;
+            const int k2 = xupd ? code : -code - 2;
             const bool xpb = (xp[t] >> bit) & 1ull, zpb = (zp[t] >> bit) & 1ull;
             unsigned long long* X2 = (unsigned long long*)(c.X + k2);
             unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
-            for (int r = 0; r < nrows; ++r) {
-                const int i = rows[r];
-                const unsigned long long bb = 1ull << (i & 63);
-                if (xpb) atomicXor(&X2[(size_t)(i >> 6) * K], bb);
-                if (zpb) atomicXor(&Z2[(size_t)(i >> 6) * K], bb);
+            const bool dx = xupd && xpb, dz = c.zcols && zpb;
+            if (dx || dz) {
+                uint64_t m = 0;
+                int wc = -1;
+                for (int r = 0; r <= nrows; ++r) {
+                    const int w = r < nrows ? rows[r] >> 6 : -2;
+                    if (w != wc) {
+                        if (m) {
+                            if (dx) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
+                            if (dz) atomicXor(&Z2[(size_t)wc * K], (unsigned long long)m);
+                        }
+                        wc = w;
+                        m = 0;
+                    }
+                    if (r < nrows) m |= 1ull << (rows[r] & 63);
+                }
             }
             const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
-            if (xpb) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~(unsigned long long)bq);
-            if (zpb) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~(unsigned long long)bq);
-            atomicAnd(&X2[op], ~(unsigned long long)bq);
-            if (qb == a) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~(unsigned long long)bq);
+            if (xupd) {
+                if (xpb) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~(unsigned long long)bq);
+                atomicAnd(&X2[op], ~(unsigned long long)bq);
+            }
+            if (c.zcols) {
+                if (zpb) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~(unsigned long long)bq);
+                if (qb == a) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~(unsigned long long)bq);
+            }
         }
     }
 #pragma unroll
@@ -786,6 +818,8 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
             gp[Wc + cw] = (cw == (a >> 6)) ? (1ull << (a & 63)) : 0ull;
         }
     }
+    // this target's x column is never read again
+    if (lane == 0) c.tm[a] = c.zcols ? -(k + 2) : -1;
     if (lane == 0 && c.counters) {
         atomicAdd(&c.counters[4], 1ull);
         atomicAdd(&c.counters[5], (unsigned long long)nrows);
@@ -987,20 +1021,26 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
             const int bit = ctz64(bits);
             bits &= bits - 1;
             const int qb = j * 64 + bit;
-            const int k2 = c.tm[qb];
-            if (k2 < 0) continue;
+            const int code = c.tm[qb];
+            if (code == -1) continue;
+            const bool xupd = code >= 0;
+            const int k2 = xupd ? code : -code - 2;
             const uint64_t xpb = (rowp[j] >> bit) & 1ull, zpb = (rowp[Wc + j] >> bit) & 1ull;
             uint64_t* X2 = X + k2;
             uint64_t* Z2 = Z + k2;
-            if (xpb)
+            if (xupd && xpb)
                 for (int t = 0; t < nnz; ++t) X2[(size_t)nz[t] * K] ^= sM[nz[t]];
-            if (zpb)
+            if (c.zcols && zpb)
                 for (int t = 0; t < nnz; ++t) Z2[(size_t)nz[t] * K] ^= sM[nz[t]];
             const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
-            X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
-            Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
-            X2[op] &= ~bq;
-            Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
+            if (xupd) {
+                X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
+                X2[op] &= ~bq;
+            }
+            if (c.zcols) {
+                Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
+                Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
+            }
         }
     }
     __syncthreads();
@@ -1023,6 +1063,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
         rdb[Wr + wq] = (rdb[Wr + wq] & ~bq) | (out ? bq : 0ull);
         c.obuf[(size_t)gb * K + k] = (uint8_t)out;
     }
+    if (tid == 0) c.tm[a] = c.zcols ? -(k + 2) : -1;
     __syncthreads();
 }
 
@@ -1031,7 +1072,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
         int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
         int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
-        uint8_t* __restrict__ obuf, int* __restrict__ err, unsigned long long* __restrict__ counters)
+        int zcols, uint8_t* __restrict__ obuf, int* __restrict__ err,
+        unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t sm[];
     const int s = blockIdx.x;
@@ -1064,6 +1106,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.s = s;
     c.tq = tq;
     c.tm = tmap + (size_t)s * g.n;
+    c.zcols = zcols;
     c.seed = seed;
     c.first_shot = first_shot;
     c.instr = instr;
@@ -1095,7 +1138,9 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     }
     const int npend = base;
     if (npend == 0) return;
-    for (int k = tid; k < K; k += nt) tmw[tq[k]] = k;
+    // column upkeep codes: pending random targets need both columns; the others only z, and
+    // only when the layer resets
+    for (int k = tid; k < K; k += nt) tmw[tq[k]] = cl[k] >= 0 ? k : (zcols ? -(k + 2) : -1);
     for (int i = tid; i < g.NR; i += nt) owner[i] = INT_MAX;
     const int w0 = min(kWin, npend);
     for (int t = tid; t < w0; t += nt) {
