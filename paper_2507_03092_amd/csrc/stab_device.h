@@ -37,13 +37,17 @@ struct NoiseDesc {
 constexpr int kWin = 64;
 constexpr int kRCap = 128;
 constexpr int kWide = 4;
+constexpr int kAnalyze = 16;     // window entries (re)analysed per round, at most
+constexpr int kAffCap = 1024;    // column-upkeep work list of a wide batch
 
 // Dynamic LDS layout of the chain kernel (byte offsets), shared by host and device.
 struct ChainLds {
     int solo;    // block-solo buffers: 2 rows, 2 band masks, per-shot pivot signs, word list
     int owner;   // NR ints: first window target owning each row pair
     int wide;    // kWide x 2 rows (pivot row and its destabilizer) of the batch
-    int win;     // window arrays: 8 x kWin ints + kWin x kRCap row indices
+    int words;   // kWide x kRCap (word, mask) lists of the batch's rowsum rows
+    int aff;     // kAffCap column-upkeep entries {code, flags, batch index}
+    int win;     // window arrays: 9 x kWin ints + kWin x kRCap row indices
     int total;
 };
 
@@ -56,8 +60,10 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
     L.solo = 0;
     L.owner = align16i((2 * g.RS + 2 * g.NB + nrdw) * 8 + g.NB * 4);
     L.wide = L.owner + align16i(g.NR * 4);
-    L.win = L.wide + kWide * 2 * g.RS * 8;
-    L.total = L.win + (8 * kWin + kWin * kRCap) * 4;
+    L.words = L.wide + kWide * 2 * g.RS * 8;
+    L.aff = L.words + kWide * kRCap * 12;
+    L.win = L.aff + kAffCap * 12;
+    L.total = L.win + (9 * kWin + kWin * kRCap) * 4;
     return L;
 }
 

@@ -723,9 +723,13 @@ __device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_
 // sorted, so runs in one 64-row word are applied as one word mask.
 // Column upkeep follows tmap: k >= 0 keeps both columns of target k, -(k+2) only its z column
 // (needed by the end-of-layer reset), -1 neither (nothing reads them again).
+// When `aff` is given (wide batches), the per-target column work is appended there as
+// {code, flags, batch index j} for the whole block to apply; it is done in-wave otherwise or
+// when the list is full.
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const uint64_t* xq, const uint64_t* zq,
-                                const int* rows, int nrows, int lane)
+                                const int* rows, int nrows, int lane, int* aff = nullptr,
+                                int* aff_n = nullptr, int j = 0)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
@@ -778,6 +782,15 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
             const bool xupd = code >= 0;
             const int k2 = xupd ? code : -code - 2;
             const bool xpb = (xp[t] >> bit) & 1ull, zpb = (zp[t] >> bit) & 1ull;
+            if (aff) {
+                const int slot = atomicAdd(aff_n, 1);
+                if (slot < kAffCap) {
+                    aff[3 * slot] = code;
+                    aff[3 * slot + 1] = (xpb ? 1 : 0) | (zpb ? 2 : 0) | (qb == a ? 4 : 0);
+                    aff[3 * slot + 2] = j;
+                    continue;
+                }
+            }
             unsigned long long* X2 = (unsigned long long*)(c.X + k2);
             unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
             const bool dx = xupd && xpb, dz = c.zcols && zpb;
@@ -1090,10 +1103,14 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* wsel = wpos + kWin;                // per window position: selected this round
     int* wstale = wsel + kWin;              // per window position: must be analysed again
     int* selpos = wstale + kWin;            // positions selected this round
-    int* srows = selpos + kWin;             // kWin * kRCap
+    int* alist = selpos + kWin;             // slots analysed this round
+    int* srows = alist + kWin;              // kWin * kRCap
     uint64_t* wideP = (uint64_t*)((char*)sm + L.wide);   // kWide pivot rows
     uint64_t* wideQ = wideP + kWide * g.RS;               // and their destabilizers
-    __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nsel, s_rsp[kWide];
+    uint64_t* wlm = (uint64_t*)((char*)sm + L.words);     // kWide x kRCap word masks
+    int* wlw = (int*)(wlm + kWide * kRCap);               // and their word indices
+    int* aff = (int*)((char*)sm + L.aff);                 // kAffCap x {code, flags, j}
+    __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nsel, s_na, s_aff, s_rsp[kWide], s_wln[kWide];
 
     ChainCtx c;
     c.g = g;
@@ -1159,10 +1176,17 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     while (s_nwin > 0 || s_tail < npend) {
         ++rounds;
         const int nwin = s_nwin;
-        // ---- analysis of entries not yet analysed (new, or touched by executed targets) ----
-        for (int t = wave; t < nwin; t += nwaves) {
-            const int sl = wpos[t];
-            if (stype[sl] != T_UNKNOWN) continue;
+        // ---- analysis: the first kAnalyze entries not yet analysed (new, or touched) ----
+        if (wave == 0) {
+            const bool un = lane < nwin && stype[wpos[lane]] == T_UNKNOWN;
+            const uint64_t m = __ballot(un);
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (un && rank < kAnalyze) alist[rank] = wpos[lane];
+            if (lane == 0) s_na = min(__popcll(m), kAnalyze);
+        }
+        __syncthreads();
+        for (int a_i = wave; a_i < s_na; a_i += nwaves) {
+            const int sl = alist[a_i];
             const int k = sk[sl];
             // all column words at once (NB <= 64 * kMaxBandsPerLane); pivot from the stabilizer half
             uint64_t cw[kMaxBandsPerLane];
@@ -1241,47 +1265,47 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         const int nw = s_nwin;
         if (nw == 0) break;
         // ---- selection: only analysed entries before the first unknown or big one ----
-        if (tid == 0) s_bar = nw;
-        __syncthreads();
-        for (int t = tid; t < nw; t += nt) {
-            const int ty = stype[wpos[t]];
-            if (ty == T_UNKNOWN || ty == T_BIG_RANDOM) atomicMin(&s_bar, t);
-            wstale[t] = 0;
+        if (wave == 0) {
+            const int ty = lane < nw ? stype[wpos[lane]] : T_UNKNOWN;
+            const uint64_t m = __ballot(ty == T_UNKNOWN || ty == T_BIG_RANDOM);
+            if (lane == 0) s_bar = m ? min(ctz64(m), nw) : nw;
         }
         __syncthreads();
         const int bar = s_bar;
-        // first owner of every row pair among the eligible entries
-        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
-            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
-            const int sl = wpos[t];
-            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
-            if (pair >= 0) atomicMin(&owner[pair], t);
+        // first owner of every row pair among the eligible entries (one wave per entry)
+        for (int t = wave; t < bar; t += nwaves) {
+            const int sl = wpos[t], cnt = scnt[sl];
+            for (int r = lane; r <= cnt; r += 64)
+                atomicMin(&owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]], t);
         }
-        for (int t = tid; t < nw; t += nt) wsel[t] = t < bar ? 1 : 0;
         __syncthreads();
         // an eligible entry runs iff it owns all its pairs
-        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
-            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
-            const int sl = wpos[t];
-            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
-            if (pair >= 0 && owner[pair] != t) wsel[t] = 0;
+        for (int t = wave; t < nw; t += nwaves) {
+            bool ok = t < bar;
+            if (ok) {
+                const int sl = wpos[t], cnt = scnt[sl];
+                for (int r = lane; r <= cnt; r += 64)
+                    if (owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]] != t) ok = false;
+            }
+            const uint64_t bad = __ballot(!ok);
+            if (lane == 0) wsel[t] = bad ? 0 : 1;
         }
         __syncthreads();
-        // entries sharing a pair with a selected one must be analysed again
-        for (int id = tid; id < nw * (kRCap + 1); id += nt) {
-            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
+        // entries sharing a pair with a selected one must be analysed again; big entries
+        // (incomplete row lists) whenever anything runs
+        for (int t = wave; t < nw; t += nwaves) {
             const int sl = wpos[t];
-            if (wsel[t] || stype[sl] != T_RANDOM) continue;
-            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
-            if (pair < 0) continue;
-            const int o = owner[pair];
-            if (o != INT_MAX && o != t && wsel[o]) wstale[t] = 1;
-        }
-        __syncthreads();
-        // big entries (incomplete row lists) are analysed again whenever anything runs
-        for (int t = tid; t < nw; t += nt) {
-            const int sl = wpos[t];
-            if (wstale[t] || (stype[sl] == T_BIG_RANDOM && bar > 0)) stype[sl] = T_UNKNOWN;
+            const int ty = stype[sl];
+            bool st = false;
+            if (!wsel[t] && ty == T_RANDOM) {
+                const int cnt = scnt[sl];
+                for (int r = lane; r <= cnt; r += 64) {
+                    const int o = owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]];
+                    if (o != INT_MAX && o != t && wsel[o]) st = true;
+                }
+            }
+            const uint64_t any = __ballot(st);
+            if (lane == 0 && (any || (ty == T_BIG_RANDOM && bar > 0))) stype[sl] = T_UNKNOWN;
         }
         if (wave == 0) {
             const bool sel = lane < bar && wsel[lane];
@@ -1289,6 +1313,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             if (sel) selpos[__popcll(m & ((1ull << lane) - 1ull))] = lane;
             if (lane == 0) s_nsel = __popcll(m);
         }
+        if (tid == 0) s_aff = 0;
         __syncthreads();
         const int nsel = s_nsel;
         // ---- execution ----
@@ -1301,7 +1326,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             // a dense update may touch anything: analyse every remaining entry again
             for (int t = tid + 1; t < nw; t += nt) stype[wpos[t]] = T_UNKNOWN;
         } else if (nsel <= kWide) {
-            // few targets: stage their pivot rows, spread their rowsum rows over all waves
+            // few targets: stage their pivot rows, spread their rowsums over all waves, and
+            // hand their column upkeep to the whole block
             for (int id = tid; id < nsel * g.RS; id += nt) {
                 const int j = id / g.RS, w = id - j * g.RS;
                 const int ip = spiv[wpos[selpos[j]]];
@@ -1311,6 +1337,30 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             if (tid < nsel) {
                 const int ip = spiv[wpos[selpos[tid]]];
                 s_rsp[tid] = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+            }
+            // word lists of the rowsum rows (rows are sorted): a run head starts a word
+            for (int j = 0; j < nsel; ++j) {
+                const int sl = wpos[selpos[j]], cnt = scnt[sl];
+                const int* rw = srows + sl * kRCap;
+                for (int r = tid; r < cnt; r += nt) {
+                    const int w = rw[r] >> 6;
+                    const bool head = r == 0 || (rw[r - 1] >> 6) != w;
+                    if (head) {
+                        // position = number of heads before r
+                        int pos = 0;
+                        for (int q = 1; q <= r; ++q) pos += ((rw[q] >> 6) != (rw[q - 1] >> 6)) ? 1 : 0;
+                        uint64_t m = 0;
+                        for (int q = r; q < cnt && (rw[q] >> 6) == w; ++q) m |= 1ull << (rw[q] & 63);
+                        wlw[j * kRCap + pos] = w;
+                        wlm[j * kRCap + pos] = m;
+                    }
+                    if (r == cnt - 1) {
+                        int nh = 1;
+                        for (int q = 1; q < cnt; ++q) nh += ((rw[q] >> 6) != (rw[q - 1] >> 6)) ? 1 : 0;
+                        s_wln[j] = nh;
+                    }
+                }
+                if (tid == 0 && cnt == 0) s_wln[j] = 0;
             }
             __syncthreads();
             for (int j = 0; j < nsel; ++j) {
@@ -1325,7 +1375,42 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
                 load_row_lane(wideP + wave * g.RS, g.Wc, lane, xp, zp);
                 load_row_lane(wideQ + wave * g.RS, g.Wc, lane, xq, zq);
-                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, xq, zq, srows + sl * kRCap, scnt[sl], lane);
+                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, xq, zq, srows + sl * kRCap,
+                                scnt[sl], lane, aff, &s_aff, wave);
+            }
+            __syncthreads();
+            // column upkeep of the batch: (entry, word) pairs over the block; slot u == 0 also
+            // sets the q / p bits of the entry
+            const int naff = min(s_aff, kAffCap);
+            int maxw = 0;
+            for (int j = 0; j < nsel; ++j) maxw = max(maxw, s_wln[j]);
+            for (int id = tid; id < naff * (maxw + 1); id += nt) {
+                const int e = id / (maxw + 1), u = id - e * (maxw + 1);
+                const int code = aff[3 * e], fl = aff[3 * e + 1], j = aff[3 * e + 2];
+                const bool xupd = code >= 0;
+                const int k2 = xupd ? code : -code - 2;
+                unsigned long long* X2 = (unsigned long long*)(c.X + k2);
+                unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
+                if (u < maxw) {
+                    if (u >= s_wln[j]) continue;
+                    const int w = wlw[j * kRCap + u];
+                    const unsigned long long m = wlm[j * kRCap + u];
+                    if (xupd && (fl & 1)) atomicXor(&X2[(size_t)w * K], m);
+                    if (c.zcols && (fl & 2)) atomicXor(&Z2[(size_t)w * K], m);
+                } else {
+                    const int ip = spiv[wpos[selpos[j]]];
+                    const int wq = ip >> 6;
+                    const unsigned long long bq = 1ull << (ip & 63);
+                    const size_t oq = (size_t)wq * K, op = (size_t)(g.Wr + wq) * K;
+                    if (xupd) {
+                        if (fl & 1) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~bq);
+                        atomicAnd(&X2[op], ~bq);
+                    }
+                    if (c.zcols) {
+                        if (fl & 2) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~bq);
+                        if (fl & 4) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~bq);
+                    }
+                }
             }
         } else {
             for (int j = wave; j < nsel; j += nwaves) {
@@ -1333,11 +1418,10 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 wave_random(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
             }
         }
-        for (int id = tid; id < bar * (kRCap + 1); id += nt) {
-            const int t = id / (kRCap + 1), r = id - t * (kRCap + 1);
-            const int sl = wpos[t];
-            const int pair = r < scnt[sl] ? srows[sl * kRCap + r] % g.NR : (r == kRCap ? spiv[sl] : -1);
-            if (pair >= 0) owner[pair] = INT_MAX;
+        for (int t = wave; t < bar; t += nwaves) {
+            const int sl = wpos[t], cnt = scnt[sl];
+            for (int r = lane; r <= cnt; r += 64)
+                owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]] = INT_MAX;
         }
         __syncthreads();
         // ---- remove executed entries (their slots become free) ----
