@@ -156,11 +156,12 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
                 void *dev_buf, uint64_t buf_bytes, void *hip_stream, uint8_t *out_bits,
                 float *elapsed_ms);
 
-/* Work counters accumulated by a context since creation (for bandwidth accounting):
- * counters[0] gate-ops x bands, [1] bands staged by the segment kernel, [2] deterministic
- * measurements, [3] stabilizer rows read by deterministic measurements, [4] random
- * measurements, [5] rows updated by rowsum, [6] measurements that turned deterministic
- * within a layer, [7] noise events.  ncounters <= 8.  Synchronizes the stream. */
+/* Work counters accumulated by a context since creation (for accounting and bandwidth
+ * figures): [0] rounds of the random-measurement chain, [1] chain rounds run by a whole block
+ * (targets touching many rows), [2] measurements deterministic at layer start, [3] stabilizer
+ * rows multiplied by deterministic reductions, [4] random measurements, [5] rows updated by
+ * rowsum, [6] measurements found deterministic inside the chain, [7] noise events.
+ * ncounters <= 8.  Synchronizes the stream. */
 int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 
 /* Per-kernel device timing with HIP events recorded on the context's stream around every

@@ -27,7 +27,7 @@ int fail(int code, const std::string& msg)
 constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
 constexpr int kSegThreads = 1024;
 constexpr int kChainThreads = 512;
-constexpr int kMCap = 32;                 // rows listed per deterministic measurement
+constexpr int kMCap = 256;                // rows listed per deterministic measurement
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
 
@@ -445,14 +445,14 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     (void)hipGetLastError();
 
     bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
-              hipMalloc((void**)&ctx->d_counters, 8 * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&ctx->d_counters, kNumCounters * kCounterStripes * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&ctx->d_tmap, (size_t)ctx->g.S * n * sizeof(int)) == hipSuccess &&
               hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
     if (!ok) {
         stab_destroy(ctx);
         return fail(STAB_ENOMEM, "device allocation failed");
     }
-    if (hipMemsetAsync(ctx->d_counters, 0, 8 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
+    if (hipMemsetAsync(ctx->d_counters, 0, kNumCounters * kCounterStripes * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_tmap, 0xFF, (size_t)ctx->g.S * n * sizeof(int), ctx->stream) != hipSuccess) {
         stab_destroy(ctx);
         return fail(STAB_EDEVICE, "memset failed");
@@ -622,7 +622,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                                 (unsigned)sp.noise_count);
                 TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
                     P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                    P->d_ev_base, P->d_ev_count)));
+                    P->d_ev_base, P->d_ev_count, ctx->d_counters)));
             }
             if (sp.item_count > 0 || sp.meas >= 0) {
                 SegArgs a{};
@@ -753,10 +753,14 @@ int stab_get_tableau(stab_ctx* ctx, int32_t shot, uint8_t* x, uint8_t* z, uint8_
 int stab_get_counters(stab_ctx* ctx, uint64_t* counters, int32_t ncounters)
 {
     if (!ctx || !counters || ncounters < 0 || ncounters > 8) return fail(STAB_EINVAL, "bad arguments");
-    unsigned long long c[8];
+    unsigned long long c[kNumCounters * kCounterStripes];
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     HIP_CHECK(ctx, hipMemcpy(c, ctx->d_counters, sizeof(c), hipMemcpyDeviceToHost));
-    for (int i = 0; i < ncounters; ++i) counters[i] = c[i];
+    for (int i = 0; i < ncounters; ++i) {
+        uint64_t v = 0;
+        for (int j = 0; j < kCounterStripes; ++j) v += c[i * kCounterStripes + j];
+        counters[i] = v;
+    }
     return STAB_OK;
 }
 

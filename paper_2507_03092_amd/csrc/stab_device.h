@@ -32,6 +32,15 @@ struct NoiseDesc {
     int bucket;            // event bucket (= item.w of the noise layer)
 };
 
+// Work counters are striped over this many addresses (by block) to keep atomics uncontended.
+constexpr int kCounterStripes = 32;
+constexpr int kNumCounters = 8;
+
+__device__ __forceinline__ void count_add(unsigned long long* counters, int idx, unsigned long long v)
+{
+    if (counters) atomicAdd(&counters[idx * kCounterStripes + (blockIdx.x & (kCounterStripes - 1))], v);
+}
+
 // Random-measurement chain: window of pending targets, rows a batched target may touch, and
 // the largest batch whose pivot rows are staged in LDS so all waves share its rowsums.
 constexpr int kWin = 64;

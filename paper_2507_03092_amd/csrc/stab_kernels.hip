@@ -163,7 +163,8 @@ constexpr int kNoiseLdsEvents = 2048;
 __global__ void __launch_bounds__(1024)
 k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int B, uint64_t seed,
              uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
-             const int* __restrict__ ev_base, int* __restrict__ ev_count)
+             const int* __restrict__ ev_base, int* __restrict__ ev_count,
+             unsigned long long* __restrict__ counters)
 {
     __shared__ uint2 sev[kNoiseLdsEvents];
     __shared__ int s_n, s_base;
@@ -205,6 +206,7 @@ k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int 
     }
     __syncthreads();
     const int n = min(s_n, kNoiseLdsEvents);
+    if (threadIdx.x == 0 && s_n) count_add(counters, 7, (unsigned long long)s_n);
     if (n == 0) return;
     if (threadIdx.x == 0) s_base = atomicAdd(&ev_count[d.bucket], n);
     __syncthreads();
@@ -520,41 +522,44 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
     const uint64_t* X = Xcol + (size_t)s * g.NB * K;
     const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
     const uint64_t* rsc = rs + (size_t)s * g.NB;
-    if (cnt <= mcap && cnt <= 64) {
-        // short list: all loads of a step issued together (row ids, then up to 4 rows at once)
-        const int myrow = lane < cnt ? mlist[((size_t)s * mcap + lane) * K + k] : 0;
-        const int rbit = lane < cnt ? (int)((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull) : 0;
+    if (cnt <= mcap) {
+        // rows listed: ids 64 at a time, row words 4 rows at a time, all loads of a batch in flight
         const uint64_t* base = tb + (size_t)g.NR * g.RS;
+        const int* ml = mlist + (size_t)s * mcap * K + k;
         uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
 #pragma unroll
         for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
-        int G = 0;
-        for (int c0 = 0; c0 < cnt; c0 += 4) {
-            uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
+        int G = 0, rsum = 0;
+        for (int c0 = 0; c0 < cnt; c0 += 64) {
+            const int nc = min(64, cnt - c0);
+            const int myrow = lane < nc ? ml[(size_t)(c0 + lane) * K] : 0;
+            rsum += wave_sum(lane < nc ? (int)((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull) : 0);
+            for (int u0 = 0; u0 < nc; u0 += 4) {
+                uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = __shfl(myrow, min(c0 + u, 63), 64);
-                const uint64_t* row = base + (size_t)i * g.RS;
+                for (int u = 0; u < 4; ++u) {
+                    const int i = __shfl(myrow, min(u0 + u, 63), 64);
+                    const uint64_t* row = base + (size_t)i * g.RS;
 #pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                    const int j = lane + 64 * t;
-                    const bool ok = c0 + u < cnt && j < g.Wc;
-                    rx[u][t] = ok ? row[j] : 0ull;
-                    rz[u][t] = ok ? row[g.Wc + j] : 0ull;
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        const int j = lane + 64 * t;
+                        const bool ok = u0 + u < nc && j < g.Wc;
+                        rx[u][t] = ok ? row[j] : 0ull;
+                        rz[u][t] = ok ? row[g.Wc + j] : 0ull;
+                    }
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                    G += gsum(rx[u][t], rz[u][t], sx[t], sz[t]);
-                    sx[t] ^= rx[u][t];
-                    sz[t] ^= rz[u][t];
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        G += gsum(rx[u][t], rz[u][t], sx[t], sz[t]);
+                        sx[t] ^= rx[u][t];
+                        sz[t] ^= rz[u][t];
+                    }
                 }
             }
         }
         G = wave_sum(G);
-        const int rsum = wave_sum(rbit);
         uint64_t xres = 0;
 #pragma unroll
         for (int t = 0; t < kMaxWordsPerLane; ++t) xres |= sx[t];
@@ -567,9 +572,13 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
             const int b = b0 + lane;
             const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b, g.bpc - 1)) * g.NB + g.Wr;
             int par = 0;
-            for (int c = 0; c < cnt; ++c) {
-                const int i = __shfl(myrow, c, 64);
-                par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
+            for (int c0 = 0; c0 < cnt; c0 += 64) {
+                const int nc = min(64, cnt - c0);
+                const int myrow = lane < nc ? ml[(size_t)(c0 + lane) * K] : 0;
+                for (int c = 0; c < nc; ++c) {
+                    const int i = __shfl(myrow, c, 64);
+                    par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
+                }
             }
             if (b < g.bpc) obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
         }
@@ -596,9 +605,9 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
             obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
         }
     }
-    if (lane == 0 && counters) {
-        atomicAdd(&counters[2], 1ull);
-        atomicAdd(&counters[3], (unsigned long long)cnt);
+    if (lane == 0) {
+        count_add(counters, want == -1 ? 2 : 6, 1ull);
+        count_add(counters, 3, (unsigned long long)cnt);
     }
 }
 
@@ -833,9 +842,9 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
     }
     // this target's x column is never read again
     if (lane == 0) c.tm[a] = c.zcols ? -(k + 2) : -1;
-    if (lane == 0 && c.counters) {
-        atomicAdd(&c.counters[4], 1ull);
-        atomicAdd(&c.counters[5], (unsigned long long)nrows);
+    if (lane == 0) {
+        count_add(c.counters, 4, 1ull);
+        count_add(c.counters, 5, (unsigned long long)nrows);
     }
 }
 
@@ -875,9 +884,9 @@ __device__ void wave_det(const ChainCtx& c, int k, const int* rows, int nrows, i
         for (int r = 0; r < nrows; ++r) par ^= (int)((rdb[rows[r] >> 6] >> (rows[r] & 63)) & 1ull);
         c.obuf[(size_t)gb * c.K + k] = (uint8_t)(shared ^ par);
     }
-    if (lane == 0 && c.counters) {
-        atomicAdd(&c.counters[6], 1ull);
-        atomicAdd(&c.counters[3], (unsigned long long)nrows);
+    if (lane == 0) {
+        count_add(c.counters, 6, 1ull);
+        count_add(c.counters, 3, (unsigned long long)nrows);
     }
 }
 
@@ -952,9 +961,9 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
             for (int w = 0; w < Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
             c.obuf[(size_t)gb * K + k] = (uint8_t)(shared ^ par);
         }
-        if (tid == 0 && c.counters) {
-            atomicAdd(&c.counters[6], 1ull);
-            atomicAdd(&c.counters[3], (unsigned long long)nrows);
+        if (tid == 0) {
+            count_add(c.counters, 6, 1ull);
+            count_add(c.counters, 3, (unsigned long long)nrows);
         }
         __syncthreads();
         return;
@@ -1010,9 +1019,9 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
             }
         }
     }
-    if (tid == 0 && c.counters) {
-        atomicAdd(&c.counters[4], 1ull);
-        atomicAdd(&c.counters[5], (unsigned long long)idx);
+    if (tid == 0) {
+        count_add(c.counters, 4, 1ull);
+        count_add(c.counters, 5, (unsigned long long)idx);
     }
     __syncthreads();
     // phase C: signs of the rowsum rows; target columns
@@ -1321,7 +1330,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             block_solo(c, sk[wpos[0]], sm, tid, nt);
             if (tid == 0) {
                 wsel[0] = 1;
-                if (counters) atomicAdd(&counters[1], 1ull);
+                count_add(counters, 1, 1ull);
             }
             // a dense update may touch anything: analyse every remaining entry again
             for (int t = tid + 1; t < nw; t += nt) stype[wpos[t]] = T_UNKNOWN;
@@ -1436,7 +1445,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         }
         __syncthreads();
     }
-    if (tid == 0 && counters) atomicAdd(&counters[0], (unsigned long long)rounds);
+    if (tid == 0) count_add(counters, 0, (unsigned long long)rounds);
     for (int k = tid; k < K; k += nt) tmw[tq[k]] = -1;
 }
 
