@@ -6,7 +6,12 @@ A step is one pass of the whole hot path over the workload: reset every shot to 
 every gate layer, noise channel and measurement layer of the circuit for all shots, and the
 measurement record copied to the host.  The value is whole-job throughput: shots * rounds / time.
 
-Usage: python bench.py [--workload surface_d25|surface_d71|surface_d3] [--steps K] [--warmup W]
+With --workload random_batch it times the uneven multi-circuit batch instead: 4096
+independent random layered Clifford circuits of n ~ U{64..2048} qubits run by one launch; a
+step resets and runs every circuit once, and the value is measurements/s over the batch.
+
+Usage: python bench.py [--workload surface_d25|surface_d71|surface_d3|random_batch]
+                       [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
@@ -23,17 +28,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
 METRIC = "syndrome rounds/sec & measurements/sec at d=25/71, batched vs plain, bit-exact"
 
-DEFAULTS = {  # steps, warmup, shots timed in the plain form
+DEFAULTS = {  # steps, warmup, shots (circuits) timed in the plain form
     "surface_d3": (20, 2, 200),
     "surface_d25": (10, 1, 10),
     "surface_d71": (3, 1, 2),
+    "random_batch": (3, 1, 64),
 }
+BATCH_METRIC = "measurements/sec of an uneven multi-circuit batch (random Clifford circuits), bit-exact"
 
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("stab_kernels.hip", "stab_api.hip", "stab_device.h"):
-        h.update(open(os.path.join(ROOT, "paper_2507_03092_amd", "csrc", f), "rb").read())
+    src = os.path.join(ROOT, "paper_2507_03092_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -73,6 +81,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.workload == "random_batch":
+        return bench_batch(args)
     steps0, warm0, plain0 = DEFAULTS[args.workload]
     steps = args.steps if args.steps is not None else steps0
     warmup = args.warmup if args.warmup is not None else warm0
@@ -192,6 +202,119 @@ def main() -> int:
         "measurements_per_s": round(meas_s, 1),
         "plain": plain,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items() if v[1] > 0},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+def bench_batch(args) -> int:
+    """The uneven multi-circuit batch: one persistent launch runs every circuit."""
+    import numpy as np
+    import torch
+
+    from paper_2507_03092_amd import circuits as Cc
+    from paper_2507_03092_amd import stab
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    steps0, warm0, plain0 = DEFAULTS["random_batch"]
+    steps = args.steps if args.steps is not None else steps0
+    warmup = args.warmup if args.warmup is not None else warm0
+    plain_n = args.plain_shots if args.plain_shots is not None else plain0
+    w = Cc.RANDOM_BATCH
+    g0 = time.perf_counter()
+    ns, circs = Cc.random_batch(w["ncirc"], w["n_lo"], w["n_hi"], w["layers"], w["seed"], w["meas_every"],
+                                w["meas_frac"])
+    nmeas = int(sum(c.num_measurements() for c in circs))
+    log(f"random_batch: {len(circs)} circuits, n {ns.min()}..{ns.max()}, {nmeas} measurements, "
+        f"generated in {time.perf_counter() - g0:.1f} s")
+    seed = w["seed"]
+    b = stab.Batch(ns, seed=seed)
+    prog = b.compile(circs)
+    for _ in range(warmup):
+        b.reset(seed)
+        b.execute(prog)
+    torch.cuda.synchronize()
+    c_before = b.counters().astype(np.int64)
+    kms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.reset(seed)
+        rec, ms = b.execute(prog, timed=True)
+        kms += ms
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c_after = b.counters().astype(np.int64)
+    ms_step = (t1 - t0) * 1000.0 / steps
+    meas_s = nmeas / ((t1 - t0) / steps)
+    log(f"batched: {ms_step:.2f} ms/step, {meas_s:.4e} meas/s, kernel {kms / steps:.2f} ms")
+    dc = (c_after - c_before) / steps
+    bytes_launch = float(dc[6] + dc[7])
+    k_avg_ms = kms / steps
+    achieved = bytes_launch / (k_avg_ms / 1000.0) / 1e9
+    roofline = {"kernel": "batch", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(k_avg_ms * 1000.0, 1),
+                "random_measurements": int(dc[4]), "deterministic_measurements": int(dc[2]),
+                "rowsum_rows": int(dc[5])}
+    b.close()
+
+    # plain: a sample of circuits, one launch each
+    plain = None
+    if not args.no_plain and plain_n > 0:
+        rng = np.random.default_rng(1)
+        pick = [int(c) for c in rng.choice(len(circs), size=min(plain_n, len(circs)), replace=False)]
+        batches = []
+        for c in pick:
+            bc = stab.Batch(ns[c:c + 1], seed=seed)
+            batches.append((bc, bc.compile([circs[c]]), c))
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for bc, pc, c in batches:
+            bc.execute(pc)
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        pm = sum(circs[c].num_measurements() for c in pick)
+        plain = {"meas_per_s": round(pm / (p1 - p0), 1), "circuits_timed": len(pick),
+                 "ms_per_circuit": round((p1 - p0) * 1000.0 / len(pick), 3)}
+        for bc, _, _ in batches:
+            bc.close()
+        log(f"plain: {plain}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import oracle as O
+
+        rng = np.random.default_rng(2)
+        small = np.nonzero(ns <= 512)[0]
+        pick = [int(c) for c in rng.choice(small, size=min(24, len(small)), replace=False)]
+        cores = O.threads()
+        c0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            outs = list(ex.map(lambda c: O.run(circs[c], 1, seed, c), pick))
+        c1 = time.perf_counter()
+        ok = all(np.array_equal(o[0], rec[c]) for o, c in zip(outs, pick))
+        pm = sum(circs[c].num_measurements() for c in pick)
+        cpu = {"value": round(pm / (c1 - c0), 1), "unit": "meas/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(pick)} circuits of the batch drawn at random among those with n <= 512 "
+                         f"(cheaper per measurement than the batch average), one circuit per host thread",
+               "seconds": round(c1 - c0, 2), "bit_exact_vs_gpu": bool(ok)}
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": BATCH_METRIC, "value": round(meas_s, 1), "unit": "meas/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "random_batch", "circuits": int(w["ncirc"]), "n_range": [w["n_lo"], w["n_hi"]],
+                   "layers": w["layers"], "measure_every": w["meas_every"], "measure_fraction": w["meas_frac"],
+                   "measurements": nmeas, "seed": seed, "form": "batched (one launch)"},
+        "circuits_per_s": round(len(circs) / ((t1 - t0) / steps), 2),
+        "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

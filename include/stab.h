@@ -174,6 +174,69 @@ int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 int stab_set_timing(stab_ctx *ctx, int32_t enable);
 int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t nkernels);
 
+/* ---------------------------------------------------------------------------------------
+ * Uneven multi-circuit batching.  A batch holds C independent circuits, circuit c on n[c]
+ * qubits with its own tableau and its own op stream, and runs all of them in one persistent
+ * launch (one workgroup per circuit, largest first).  This is the batched form of the
+ * paper's random-circuit benchmark (Sec. 4.3, random Clifford layers with interleaved
+ * measurements) and of the parallel sampling it names as future work (Sec. 6).
+ * Semantics per circuit are exactly those of a one-shot context with first_shot = c: RNG key
+ * (seed, c), counter (instruction index, target position), the index counting every
+ * instruction circuit c has executed since the batch was created or reset.
+ * ------------------------------------------------------------------------------------- */
+typedef struct stab_batch stab_batch;
+typedef struct stab_batch_program stab_batch_program;
+
+/* Device bytes for the tableaux of `ncirc` circuits of n[0..ncirc-1] qubits (each n[c] in
+ * [1, 8192]).  Errors: STAB_EINVAL (ncirc < 1, n NULL, n[c] < 1, bytes_out NULL),
+ * STAB_ERANGE (n[c] > 8192). */
+int stab_batch_bytes(int32_t ncirc, const int32_t *n, uint64_t *bytes_out);
+
+/* Create a batch of circuits in |0...0> on dev_buf (>= stab_batch_bytes bytes, 256-byte
+ * aligned, owned by the caller and kept alive until stab_batch_destroy).  Errors: as
+ * stab_batch_bytes, STAB_ENOMEM (buffer too small), STAB_EDEVICE. */
+int stab_batch_create(int32_t ncirc, const int32_t *n, uint64_t seed, void *dev_buf,
+                      uint64_t buf_bytes, void *hip_stream, stab_batch **out);
+
+/* Release the batch's own memory (never dev_buf).  NULL is ignored. */
+void stab_batch_destroy(stab_batch *batch);
+
+/* Put every circuit back in |0...0>, set the RNG seed and the instruction counters to 0. */
+int stab_batch_reset(stab_batch *batch, uint64_t seed);
+
+/* Compile the circuits' op streams (the stab_instr format above).  Circuit c's instructions
+ * are instrs[instr_off[c] .. instr_off[c+1]) and its targets targets[target_off[c] ..
+ * target_off[c+1]) (both offset arrays have ncirc + 1 entries, start at 0 and do not
+ * decrease).  Errors: STAB_EINVAL (malformed stream, naming the circuit and instruction),
+ * STAB_ERANGE, STAB_ENOMEM, STAB_EDEVICE. */
+int stab_batch_compile(stab_batch *batch, const stab_instr *instrs, const int64_t *instr_off,
+                       const int32_t *targets, const int64_t *target_off,
+                       stab_batch_program **out);
+
+/* Records (M/MR targets) circuit c writes, or -1 for a bad argument. */
+int64_t stab_batch_program_records(const stab_batch_program *prog, int32_t circuit);
+
+void stab_batch_program_destroy(stab_batch_program *prog);
+
+/* Run every circuit's program once from the batch's current state.  out_bits (host, may be
+ * NULL) receives the records: circuit c's bits LSB-first from byte sum_{c' < c}
+ * ceil(records(c') / 8).  elapsed_ms (may be NULL) receives the device time of the launch.
+ * Errors: STAB_EINVAL (program of another batch), STAB_ERANGE, STAB_ENOMEM, STAB_EDEVICE,
+ * STAB_EINTERNAL (device consistency check; the batch is then unusable). */
+int stab_batch_execute(stab_batch *batch, const stab_batch_program *prog, uint8_t *out_bits,
+                       float *elapsed_ms);
+
+/* Circuit c's tableau in the stab_get_tableau layout (x[2n][n], z[2n][n], r[2n]). */
+int stab_batch_get_tableau(stab_batch *batch, int32_t circuit, uint8_t *x, uint8_t *z, uint8_t *r);
+
+/* Work counters of the batch since creation: [2] deterministic measurements, [4] random
+ * measurements, [5] rows updated by rowsum or multiplied by deterministic reductions,
+ * [6] bytes the measurements must move (target columns at one 8-byte word per row, pivot
+ * row, rowsum rows read and written, row moves; multiplied rows read), [7] bytes of the
+ * band passes (every row read, and written when a gate changed x|z); the others stay 0.
+ * ncounters <= 8. */
+int stab_batch_get_counters(stab_batch *batch, uint64_t *counters, int32_t ncounters);
+
 /* Message of the last error on this thread ("" if none). */
 const char *stab_last_error(void);
 

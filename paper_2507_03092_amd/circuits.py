@@ -333,42 +333,103 @@ def random_clifford_measure(n: int, depth: int, seed: int, p_meas: float = 0.2,
     return c
 
 
-def random_layered_clifford(n: int, layers: int, seed: int, meas_every: int = 10,
-                            meas_frac: float = 0.1) -> Circuit:
+class PackedCircuit:
+    """An op stream already in array form (instruction records + int32 targets), for
+    generated workloads too large to build target by target."""
+
+    def __init__(self, n: int, instr: np.ndarray, targets: np.ndarray):
+        self.n = n
+        self.instr = np.ascontiguousarray(instr, dtype=INSTR_DTYPE)
+        self.targets = np.ascontiguousarray(targets, dtype=np.int32)
+        if int(self.instr["ntargets"].sum()) != len(self.targets):
+            raise ValueError("target count does not match the instructions")
+
+    def append(self, kind: int, targets=(), t=(0, 0, 0)) -> None:
+        tg = np.asarray(targets, dtype=np.int64).reshape(-1)
+        if kind in TWO_QUBIT and len(tg) % 2:
+            raise ValueError("two-qubit instruction needs an even target count")
+        if len(tg) and (tg.min() < 0 or tg.max() >= self.n):
+            raise ValueError(f"target out of range for n={self.n}")
+        rec = np.zeros(1, dtype=INSTR_DTYPE)
+        rec["kind"], rec["ntargets"] = kind, len(tg)
+        t = tuple(int(v) for v in t) + (0,) * (3 - len(t))
+        rec["t0"], rec["t1"], rec["t2"] = t
+        self.instr = np.concatenate([self.instr, rec])
+        self.targets = np.concatenate([self.targets, tg.astype(np.int32)])
+
+    def gate(self, kind, targets):
+        self.append(kind, targets)
+
+    def arrays(self) -> tuple[np.ndarray, np.ndarray]:
+        return self.instr, self.targets
+
+    def num_measurements(self) -> int:
+        rec = np.isin(self.instr["kind"], list(RECORDED))
+        return int(self.instr["ntargets"][rec].sum())
+
+    def __len__(self):
+        return len(self.instr)
+
+
+def random_layered_clifford(n: int, layers: int, seed, meas_every: int = 10,
+                            meas_frac: float = 0.1) -> PackedCircuit:
     """The batched random-Clifford workload: ``layers`` random perfect-matching layers over
-    {H, S, CX} (a pair gets CX with probability 0.5, else each qubit gets H, S or nothing),
-    and M on a random ``meas_frac`` subset every ``meas_every`` layers.  Noiseless."""
+    {H, S, CX} (a pair gets CX with probability 0.5, random orientation; otherwise each of
+    its qubits gets H, S or nothing with probability 1/3 each; with odd n the unmatched qubit
+    idles), and M on a random ``meas_frac`` subset (in random order) after every
+    ``meas_every``-th layer.  Noiseless."""
     rng = np.random.default_rng(seed)
-    c = Circuit(n=n)
+    h = n // 2
+    perm = np.argsort(rng.random((layers, n)), axis=1).astype(np.int32)
+    a, b = perm[:, 0:2 * h:2], perm[:, 1:2 * h:2]
+    cx = rng.random((layers, h)) < 0.5
+    flip = rng.random((layers, h)) < 0.5
+    ctrl, targ = np.where(flip, b, a), np.where(flip, a, b)
+    single = np.concatenate([a, b], axis=1)
+    free = np.concatenate([~cx, ~cx], axis=1)
+    k = rng.integers(0, 3, size=(layers, 2 * h))
+    hm, sm = free & (k == 0), free & (k == 1)
+    parts = [(H, single[hm], hm.sum(axis=1)), (S, single[sm], sm.sum(axis=1)),
+             (CX, np.stack([ctrl[cx], targ[cx]], axis=1).reshape(-1), 2 * cx.sum(axis=1))]
+    k_meas = max(1, int(round(meas_frac * n)))
+    mlayers = [li for li in range(layers) if (li + 1) % meas_every == 0]
+    meas = {li: rng.choice(n, size=k_meas, replace=False).astype(np.int32) for li in mlayers}
+    offs = [np.concatenate([[0], np.cumsum(cnt)]) for _, _, cnt in parts]
+    kinds, counts, chunks = [], [], []
     for li in range(layers):
-        perm = rng.permutation(n)
-        pairs, hs, ss = [], [], []
-        for i in range(0, n - 1, 2):
-            a, b = int(perm[i]), int(perm[i + 1])
-            if rng.random() < 0.5:
-                pairs += [a, b] if rng.random() < 0.5 else [b, a]
-            else:
-                for q in (a, b):
-                    k = int(rng.integers(0, 3))
-                    if k == 0:
-                        hs.append(q)
-                    elif k == 1:
-                        ss.append(q)
-        if hs:
-            c.gate(H, hs)
-        if ss:
-            c.gate(S, ss)
-        if pairs:
-            c.gate(CX, pairs)
-        if (li + 1) % meas_every == 0:
-            k = max(1, int(round(meas_frac * n)))
-            mq = [int(q) for q in rng.choice(n, size=k, replace=False)]
-            c.append(M, mq)
-    return c
+        for (kind, arr, cnt), off in zip(parts, offs):
+            if cnt[li]:
+                kinds.append(kind)
+                counts.append(int(cnt[li]))
+                chunks.append(arr[off[li]:off[li + 1]])
+        if li in meas:
+            kinds.append(M)
+            counts.append(k_meas)
+            chunks.append(meas[li])
+    instr = np.zeros(len(kinds), dtype=INSTR_DTYPE)
+    instr["kind"] = kinds
+    instr["ntargets"] = counts
+    tg = np.concatenate(chunks).astype(np.int32) if chunks else np.zeros(0, dtype=np.int32)
+    return PackedCircuit(n, instr, tg)
+
+
+def random_batch(ncirc: int, n_lo: int, n_hi: int, layers: int, seed: int, meas_every: int = 10,
+                 meas_frac: float = 0.1):
+    """Uneven batch of independent random layered Clifford circuits: sizes n ~ U{n_lo..n_hi}
+    drawn from ``seed``, circuit c generated from the seed pair (seed, c).
+    Returns (sizes, circuits)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, size=ncirc)
+    circs = [random_layered_clifford(int(ns[c]), layers, (seed, c), meas_every, meas_frac) for c in range(ncirc)]
+    return ns.astype(np.int32), circs
 
 
 # ---- the surface-code workloads -----------------------------------------------------------------
 IDLE_T1T2 = twirled_t1t2(1e-6, 100e-6, 100e-6)
+
+# uneven multi-circuit batch: 4096 random layered Clifford circuits, n ~ U{64..2048},
+# 200 layers, M on 10% of the qubits every 10 layers, noiseless
+RANDOM_BATCH = dict(ncirc=4096, n_lo=64, n_hi=2048, layers=200, seed=4, meas_every=10, meas_frac=0.1)
 
 WORKLOADS = {
     "surface_d3": dict(d=3, rounds=3, p=1e-3, idle=None, seed=1, shots=1000),

@@ -5,6 +5,7 @@
 // noise up to a measurement layer run in one segment kernel per 64-row band; a measurement
 // layer then runs classify -> deterministic batch -> in-order random chain -> reset/record.
 #include "stab_kernels.hip"
+#include "stab_batch.hip"
 #include "stab.h"
 
 #include <algorithm>
@@ -804,3 +805,6 @@ int stab_sample(const stab_instr* instrs, int32_t ninstr, const int32_t* targets
 }
 
 }  // extern "C"
+
+// multi-circuit batches
+#include "stab_batch_api.hip"

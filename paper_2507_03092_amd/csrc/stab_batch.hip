@@ -1,0 +1,582 @@
+// stab_batch.hip -- uneven multi-circuit batching: many independent circuits of different
+// sizes, each with its own tableau and its own op stream, run by ONE persistent launch.
+//
+// One block per circuit executes that circuit's whole program: runs of gate and noise layers
+// as band passes (64 rows staged in LDS and turned into qubit-major words, every layer of
+// the run applied there, written back once), and measurement instructions target by target
+// (Sec. 2.4: pivot = first stabilizer row with x at the qubit, rowsum from it (Appendix A.2)
+// for a random outcome, the product of the selected stabilizer rows for a deterministic
+// one).  Blocks are dispatched largest circuit first so the long ones start early.
+//
+// Randomness: Philox4x64-10 with key (seed, circuit index), counter (instruction index in the
+// circuit's stream, target position), the index counting every instruction the circuit has
+// executed since the batch was created or reset: circuit c draws exactly what a one-shot
+// context with first_shot = c draws for the same sequence of streams.
+//
+// Included by stab_api.hip (same translation unit: it shares the device helpers above).
+
+namespace stabdev {
+
+// Largest circuit of a batch: a lane owns at most two x words and two z words of a row.
+constexpr int kBatchMaxWc = 128;
+constexpr int kBatchThreads = 512;
+constexpr int kBatchWaves = kBatchThreads / 64;
+
+struct BatchCirc {
+    int n, Wc, RS, NR;          // NR = 64 * Wc rows per half; RS = 2 * Wc words per row
+    long long tab_off;          // first word of the tableau [2*NR][RS]
+    long long rs_off;           // first word of the sign vector [2*Wc]
+    int step_begin, step_count; // program steps
+    long long rec_bit_off;      // bit offset of the circuit's first record in the output
+};
+
+struct BatchMeas {
+    uint64_t instr;  // instruction index in the circuit's stream
+    int kind;        // STAB_KIND_M / MR / R
+    int tq;          // first target in the measurement target array
+    int K;           // targets
+    int rec;         // record index (within the circuit) of the first target; -1 for R
+};
+
+// Program step: (0, first gate, gates, modifies x|z) gate layer on disjoint qubits;
+// (1, noise descriptor, 0, 0) noise layer; (2, measurement descriptor, 0, 0).
+struct BatchArgs {
+    const BatchCirc* circ;
+    const int* order;           // block -> circuit
+    const int4* steps;
+    const uint2* gates;
+    const NoiseDesc* noise;
+    const int* noise_tg;
+    const BatchMeas* meas;
+    const int* meas_tg;
+    uint64_t* tab;
+    uint64_t* rs;
+    uint32_t* rec;              // packed record bits, zeroed before the launch
+    const uint64_t* ibase;      // per circuit: instructions it executed before this launch
+    uint64_t seed;
+    int* err;
+    unsigned long long* counters;
+};
+
+// LDS words (uint64) the batch kernel needs for a circuit with Wc column words.
+__host__ __device__ inline int batch_lds_words(int Wc)
+{
+    const int RS = 2 * Wc, NB = 2 * Wc;
+    const int seg = 64 * (RS + 1) + 16;
+    // signs, x-column bits, pivot row, per-wave (X, Z) partial products, 32 ints, row list
+    // (uint16, one entry per row)
+    const int meas = 2 * NB + RS + 2 * kBatchWaves * RS + 16 + (NB * 64 * 2 + 7) / 8;
+    return seg > meas ? seg : meas;
+}
+
+constexpr int kMK = 7, kMRK = 8, kRK = 9;   // measurement kinds (include/stab.h enum)
+
+// -------------------------------------------------------------------------------- gates ---
+__device__ __forceinline__ void batch_gate(uint64_t* T, int RSP, int Wc, uint2 gt, uint64_t& racc)
+{
+    const int kind = (int)(gt.x & 15u);
+    const int q0 = (int)(gt.x >> 4);
+    const int i0 = (q0 & 63) * RSP + (q0 >> 6);
+    const uint64_t x0 = T[i0], z0 = T[i0 + Wc];
+    switch (kind) {
+    case STAB_KIND_H:
+        racc ^= x0 & z0;
+        T[i0] = z0;
+        T[i0 + Wc] = x0;
+        break;
+    case STAB_KIND_S:
+        racc ^= x0 & z0;
+        T[i0 + Wc] = z0 ^ x0;
+        break;
+    case STAB_KIND_X: racc ^= z0; break;
+    case STAB_KIND_Y: racc ^= x0 ^ z0; break;
+    case STAB_KIND_Z: racc ^= x0; break;
+    case STAB_KIND_CX: {
+        const int q1 = (int)gt.y;
+        const int i1 = (q1 & 63) * RSP + (q1 >> 6);
+        const uint64_t x1 = T[i1], z1 = T[i1 + Wc];
+        racc ^= x0 & z1 & ~(x1 ^ z0);
+        T[i1] = x1 ^ x0;
+        T[i0 + Wc] = z0 ^ z1;
+    } break;
+    default: break;
+    }
+}
+
+// Noise unit u of descriptor d for circuit ci: XOR into racc the sign flips of the staged
+// band's rows (the rows the drawn Pauli anticommutes with).
+__device__ __forceinline__ void batch_noise(const uint64_t* T, int RSP, int Wc, const NoiseDesc& d,
+                                            const int* __restrict__ ntg, int u, uint64_t seed, int ci,
+                                            uint64_t ibase, uint64_t& racc)
+{
+    uint64_t u0, u1;
+    philox(ibase + d.instr, (uint64_t)u, seed, (uint64_t)ci, u0, u1);
+    int q[2], P[2], ne = 0;
+    if (d.kind == STAB_KIND_DEP1) {
+        if (u0 < d.t0) { q[ne] = ntg[d.toff + u]; P[ne++] = 1 + (int)__umul64hi(u1, 3ull); }
+    } else if (d.kind == STAB_KIND_DEP2) {
+        if (u0 < d.t0) {
+            const int k = 1 + (int)__umul64hi(u1, 15ull);
+            if (k >> 2) { q[ne] = ntg[d.toff + 2 * u]; P[ne++] = k >> 2; }
+            if (k & 3) { q[ne] = ntg[d.toff + 2 * u + 1]; P[ne++] = k & 3; }
+        }
+    } else {
+        const int p = (u0 < d.t0) ? 1 : (u0 < d.t1) ? 2 : (u0 < d.t2) ? 3 : 0;
+        if (p) { q[ne] = ntg[d.toff + u]; P[ne++] = p; }
+    }
+    for (int e = 0; e < ne; ++e) {
+        const int iq = (q[e] & 63) * RSP + (q[e] >> 6);
+        const uint64_t xq = T[iq], zq = T[iq + Wc];
+        racc ^= (P[e] == 1) ? zq : (P[e] == 3) ? xq : (xq ^ zq);
+    }
+}
+
+// One run of gate/noise steps [st, en) over every band of the circuit.
+__device__ void batch_segment(const BatchArgs& A, const BatchCirc& C, int ci, int st, int en,
+                              uint64_t* lds)
+{
+    const int tid = threadIdx.x, nt = kBatchThreads;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int RS = C.RS, RSP = C.RS + 1, Wc = C.Wc, NB = 2 * C.Wc;
+    uint64_t* T = lds;
+    uint64_t* red = lds + 64 * RSP;
+    uint64_t* tab = A.tab + C.tab_off;
+    uint64_t* rs = A.rs + C.rs_off;
+    int wb = 0;
+    for (int k = st; k < en; ++k) wb |= (A.steps[k].x == 0) ? A.steps[k].w : 0;
+    const int npairs = 32 * RS;
+    for (int band = 0; band < NB; ++band) {
+        uint64_t* gb = tab + (size_t)band * 64 * RS;
+        const ulonglong2* gb2 = (const ulonglong2*)gb;
+        for (int p0 = 0; p0 < npairs; p0 += 4 * nt) {
+            ulonglong2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * nt + tid;
+                if (p < npairs) v[u] = gb2[p];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * nt + tid;
+                if (p < npairs) {
+                    const int i = 2 * p;
+                    const int r = i / RS;
+                    const int c = i - r * RS;
+                    T[r * RSP + c] = v[u].x;
+                    T[r * RSP + c + 1] = v[u].y;
+                }
+            }
+        }
+        __syncthreads();
+        for (int c = wave; c < RS; c += kBatchWaves) {
+            const uint64_t v = transpose64(T[lane * RSP + c], lane);
+            T[lane * RSP + c] = v;
+        }
+        __syncthreads();
+        uint64_t racc = 0;
+        for (int k = st; k < en; ++k) {
+            const int4 s = A.steps[k];
+            if (s.x == 0) {
+                for (int gi = tid; gi < s.z; gi += nt) batch_gate(T, RSP, Wc, A.gates[s.y + gi], racc);
+            } else {
+                const NoiseDesc d = A.noise[s.y];
+                for (int u = tid; u < d.units; u += nt)
+                    batch_noise(T, RSP, Wc, d, A.noise_tg, u, A.seed, ci, A.ibase[ci], racc);
+            }
+            __syncthreads();
+        }
+        if (wb) {
+            for (int c = wave; c < RS; c += kBatchWaves) {
+                const uint64_t v = transpose64(T[lane * RSP + c], lane);
+                T[lane * RSP + c] = v;
+            }
+            __syncthreads();
+            ulonglong2* gw2 = (ulonglong2*)gb;
+            for (int p = tid; p < npairs; p += nt) {
+                const int i = 2 * p;
+                const int r = i / RS;
+                const int c = i - r * RS;
+                ulonglong2 v;
+                v.x = T[r * RSP + c];
+                v.y = T[r * RSP + c + 1];
+                gw2[p] = v;
+            }
+        }
+        racc = wave_xor(racc);
+        if (lane == 0) red[wave] = racc;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t t = 0;
+            for (int w = 0; w < kBatchWaves; ++w) t ^= red[w];
+            if (t) rs[band] ^= t;
+        }
+        __syncthreads();    // the next band reuses the LDS tile
+    }
+    if (tid == 0) count_add(A.counters, 7, (unsigned long long)NB * 64 * RS * 8 * (wb ? 2 : 1));
+}
+
+// -------------------------------------------------------------------------- measurement ---
+// Bit `bit` of word `word` of every row, as 64-row words (one per band), into out[0..NB).
+// With xor_into set the words are XORed into out (used to flip signs) instead of stored.
+__device__ __forceinline__ void batch_column(const uint64_t* __restrict__ tab, int RS, int NB,
+                                             int word, int bit, uint64_t* out, bool xor_into)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = wave; c0 < NB; c0 += 4 * kBatchWaves) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kBatchWaves;
+            v[u] = (c < NB) ? tab[(size_t)(64 * c + lane) * RS + word] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kBatchWaves;
+            const uint64_t m = __ballot((v[u] >> bit) & 1ull);
+            if (c < NB && lane == 0) {
+                if (xor_into) out[c] ^= m;
+                else out[c] = m;
+            }
+        }
+    }
+}
+
+// Rows whose bit is set in words [w0, w1) of bits, minus `skip` rows, listed in row order into
+// list (uint16) -- block-wide; returns the count (valid in every thread after the call).
+__device__ int batch_list(const uint64_t* bits, int w0, int w1, int skip0, int skip1,
+                          uint16_t* list, int* s_tot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int* wtot = s_tot + 1;
+    int total = 0;
+    for (int base = w0; base < w1; base += kBatchThreads) {
+        const int w = base + tid;
+        uint64_t m = 0;
+        if (w < w1) {
+            m = bits[w];
+            if ((skip0 >> 6) == w) m &= ~(1ull << (skip0 & 63));
+            if ((skip1 >> 6) == w) m &= ~(1ull << (skip1 & 63));
+        }
+        const int c = __popcll(m);
+        const int ex = wave_excl_scan(c, lane);
+        if (lane == 63) wtot[wave] = ex + c;
+        __syncthreads();
+        int off = total;
+        for (int v = 0; v < wave; ++v) off += wtot[v];
+        int t = 0;
+        for (int v = 0; v < kBatchWaves; ++v) t += wtot[v];
+        off += ex;
+        while (m) {
+            list[off++] = (uint16_t)(64 * w + ctz64(m));
+            m &= m - 1;
+        }
+        total += t;
+        __syncthreads();
+    }
+    return total;
+}
+
+// rowsum(row, p) for every listed row: x|z ^= pivot, sign from the g-sum (Appendix A.2).
+// Each wave takes kBatchRows rows at a time so their loads are in flight together; lane l
+// owns x words l, l + 64, ... (NW of them) and the matching z words.
+template <int NW>
+__device__ void batch_rowsum(const BatchCirc& C, uint64_t* __restrict__ tab, const uint64_t* prow,
+                             int rp, const uint16_t* list, int nlist, uint64_t* sg, int* err)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Wc = C.Wc, RS = C.RS;
+    uint64_t px[NW], pz[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        const int j = lane + 64 * t;
+        px[t] = (j < Wc) ? prow[j] : 0;
+        pz[t] = (j < Wc) ? prow[Wc + j] : 0;
+    }
+    constexpr int kBatchRows = (NW == 1) ? 6 : 2;   // rows in flight per wave (register budget)
+    for (int base = wave * kBatchRows; base < nlist; base += kBatchWaves * kBatchRows) {
+        const int cnt = min(kBatchRows, nlist - base);
+        uint64_t x[kBatchRows][NW], z[kBatchRows][NW];
+        int row[kBatchRows];
+#pragma unroll
+        for (int r = 0; r < kBatchRows; ++r) {
+            row[r] = (r < cnt) ? (int)list[base + r] : 0;
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+                const int j = lane + 64 * t;
+                x[r][t] = z[r][t] = 0;
+                if (r < cnt && j < Wc) {
+                    x[r][t] = tab[(size_t)row[r] * RS + j];
+                    z[r][t] = tab[(size_t)row[r] * RS + Wc + j];
+                }
+            }
+        }
+        // g-sums mod 4, eight bits per row, four rows per int
+        int pk[2] = {0, 0};
+        static_assert(kBatchRows <= 8, "two packed ints hold eight rows");
+#pragma unroll
+        for (int r = 0; r < kBatchRows; ++r) {
+            int G = 0;
+#pragma unroll
+            for (int t = 0; t < NW; ++t) G += gsum(px[t], pz[t], x[r][t], z[r][t]);
+            pk[r >> 2] += (G & 3) << (8 * (r & 3));
+        }
+        pk[0] = wave_sum(pk[0]);
+        pk[1] = wave_sum(pk[1]);
+#pragma unroll
+        for (int r = 0; r < kBatchRows; ++r) {
+            if (r < cnt) {
+#pragma unroll
+                for (int t = 0; t < NW; ++t) {
+                    const int j = lane + 64 * t;
+                    if (j < Wc) {
+                        tab[(size_t)row[r] * RS + j] = x[r][t] ^ px[t];
+                        tab[(size_t)row[r] * RS + Wc + j] = z[r][t] ^ pz[t];
+                    }
+                }
+                if (lane == 0) {
+                    const int G = (pk[r >> 2] >> (8 * (r & 3))) & 3;
+                    const int ri = (int)((sg[row[r] >> 6] >> (row[r] & 63)) & 1ull);
+                    const int e = (2 * ri + 2 * rp + G) & 3;
+                    if (e & 1) atomicOr(err, 1);
+                    if ((e >> 1) != ri) atomicXor((unsigned long long*)&sg[row[r] >> 6], 1ull << (row[r] & 63));
+                }
+            }
+        }
+    }
+}
+
+// Sign of the product of the listed stabilizer rows (destabilizer indices i -> row NR + i):
+// for Paulis P_k = (-1)^r_k i^|x_k & z_k| X^x_k Z^z_k the product carries
+// i^(sum_k (2 r_k + |x_k & z_k|) + 2 sum_{i<k} z_i . x_k); the rows commute, so waves reduce
+// contiguous chunks and the cross terms between chunks are added from their (X, Z) parities.
+// The result must be +-Z (X = 0 and an even exponent), else *err is set.  Block-wide.
+template <int NW>
+__device__ int batch_det(const BatchCirc& C, const uint64_t* __restrict__ tab, const uint16_t* list,
+                         int nlist, const uint64_t* sg, uint64_t* part, int* s_res, int* err)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Wc = C.Wc, RS = C.RS, NR = C.NR;
+    const int per = (nlist + kBatchWaves - 1) / kBatchWaves;
+    const int b0 = min(nlist, wave * per), b1 = min(nlist, b0 + per);
+    uint64_t X[NW], Z[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) X[t] = Z[t] = 0;
+    int e = 0, cross = 0;
+    for (int c0 = b0; c0 < b1; c0 += 4) {
+        uint64_t x[4][NW], z[4][NW];
+        int ii[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ii[r] = (c0 + r < b1) ? (int)list[c0 + r] : -1;
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+                const int j = lane + 64 * t;
+                x[r][t] = z[r][t] = 0;
+                if (ii[r] >= 0 && j < Wc) {
+                    x[r][t] = tab[(size_t)(NR + ii[r]) * RS + j];
+                    z[r][t] = tab[(size_t)(NR + ii[r]) * RS + Wc + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+                e += __popcll(x[r][t] & z[r][t]);
+                cross += __popcll(Z[t] & x[r][t]);
+                X[t] ^= x[r][t];
+                Z[t] ^= z[r][t];
+            }
+            if (ii[r] >= 0 && lane == 0) e += 2 * (int)((sg[(NR + ii[r]) >> 6] >> ((NR + ii[r]) & 63)) & 1ull);
+        }
+    }
+    // chunk parities for the cross terms between waves
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        const int j = lane + 64 * t;
+        if (j < Wc) {
+            part[(2 * wave) * Wc + j] = X[t];
+            part[(2 * wave + 1) * Wc + j] = Z[t];
+        }
+    }
+    int v = wave_sum((e & 3) + 2 * (cross & 1));
+    if (lane == 0) s_res[1 + wave] = v;
+    __syncthreads();
+    if (wave == 0) {
+        int cr = 0;
+        uint64_t xall = 0;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int j = lane + 64 * t;
+            if (j < Wc) {
+                uint64_t zp = 0, xa = 0;
+                for (int w = 0; w < kBatchWaves; ++w) {
+                    const uint64_t xw = part[(2 * w) * Wc + j];
+                    cr += __popcll(zp & xw);
+                    zp ^= part[(2 * w + 1) * Wc + j];
+                    xa ^= xw;
+                }
+                xall |= xa;
+            }
+        }
+        cr = wave_sum(cr & 1);
+        xall = wave_or(xall);
+        if (lane == 0) {
+            int tot = 2 * cr;
+            for (int w = 0; w < kBatchWaves; ++w) tot += s_res[1 + w];
+            tot &= 3;
+            if ((tot & 1) || xall) atomicOr(err, 1);
+            s_res[0] = tot >> 1;
+        }
+    }
+    __syncthreads();
+    return s_res[0];
+}
+
+// One M / MR / R instruction of circuit ci, target by target.
+template <int NW>
+__device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, const BatchMeas& md,
+                              uint64_t* lds)
+{
+    const int tid = threadIdx.x;
+    const int Wc = C.Wc, RS = C.RS, NR = C.NR, NB = 2 * C.Wc;
+    uint64_t* tab = A.tab + C.tab_off;
+    uint64_t* rs = A.rs + C.rs_off;
+    uint64_t* sg = lds;                      // NB sign words
+    uint64_t* colx = sg + NB;                // NB words: x bit of the target, per row
+    uint64_t* prow = colx + NB;              // RS words: pivot row
+    uint64_t* part = prow + RS;              // 2 * kBatchWaves * RS words
+    int* s_int = (int*)(part + 2 * kBatchWaves * RS);   // 32 ints: pivot, list and det scratch
+    uint16_t* list = (uint16_t*)(s_int + 32);          // 2 * NR entries
+
+    for (int w = tid; w < NB; w += kBatchThreads) sg[w] = rs[w];
+    __syncthreads();
+    int nrand = 0, ndet = 0;
+    long long nrows = 0, bytes = 0;
+    const long long row_b = (long long)RS * 8, col_b = (long long)2 * NR * 8;
+    for (int t = 0; t < md.K; ++t) {
+        const int a = A.meas_tg[md.tq + t];
+        batch_column(tab, RS, NB, a >> 6, a & 63, colx, false);
+        __syncthreads();
+        // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
+        if (tid < 64) {
+            int first = 0x7fffffff;
+            for (int w = Wc + tid; w < NB; w += 64)
+                if (colx[w]) first = min(first, 64 * w + ctz64(colx[w]));
+            first = wave_min(first);
+            if (tid == 0) s_int[0] = first;
+        }
+        __syncthreads();
+        const int p = s_int[0];
+        int outcome;
+        if (p != 0x7fffffff) {
+            uint64_t u0, u1;
+            philox(A.ibase[ci] + md.instr, (uint64_t)t, A.seed, (uint64_t)ci, u0, u1);
+            outcome = (int)(u0 >> 63);
+            for (int j = tid; j < RS; j += kBatchThreads) prow[j] = tab[(size_t)p * RS + j];
+            const int rp = (int)((sg[p >> 6] >> (p & 63)) & 1ull);
+            const int nl = batch_list(colx, 0, NB, p, p - NR, list, s_int + 1);
+            __syncthreads();    // prow staged
+            batch_rowsum<NW>(C, tab, prow, rp, list, nl, sg, A.err);
+            __syncthreads();
+            // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
+            const int d = p - NR;
+            for (int j = tid; j < RS; j += kBatchThreads) {
+                tab[(size_t)d * RS + j] = prow[j];
+                tab[(size_t)p * RS + j] = (j == Wc + (a >> 6)) ? (1ull << (a & 63)) : 0ull;
+            }
+            if (tid == 0) {
+                uint64_t wd = sg[d >> 6];
+                wd = (wd & ~(1ull << (d & 63))) | ((uint64_t)rp << (d & 63));
+                sg[d >> 6] = wd;
+                uint64_t wp = sg[p >> 6];
+                wp = (wp & ~(1ull << (p & 63))) | ((uint64_t)outcome << (p & 63));
+                sg[p >> 6] = wp;
+            }
+            ++nrand;
+            nrows += nl;
+            // column, pivot row, rowsum read+write, two row writes
+            bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
+        } else {
+            const int nl = batch_list(colx, 0, Wc, -1, -1, list, s_int + 1);
+            outcome = batch_det<NW>(C, tab, list, nl, sg, part, s_int + 10, A.err);
+            ++ndet;
+            nrows += nl;
+            bytes += col_b + nl * row_b;
+        }
+        __syncthreads();
+        if (md.kind != kRK && tid == 0 && outcome) {
+            const long long bit = C.rec_bit_off + md.rec + t;
+            atomicOr(&A.rec[bit >> 5], 1u << (bit & 31));
+        }
+        if (md.kind != kMK && outcome) {
+            // reset: apply X_a, i.e. flip the sign of every row with z at a
+            batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, sg, true);
+            __syncthreads();
+            bytes += col_b;
+        }
+    }
+    for (int w = tid; w < NB; w += kBatchThreads) rs[w] = sg[w];
+    if (tid == 0) {
+        count_add(A.counters, 4, (unsigned long long)nrand);
+        count_add(A.counters, 2, (unsigned long long)ndet);
+        count_add(A.counters, 5, (unsigned long long)nrows);
+        count_add(A.counters, 6, (unsigned long long)bytes);
+    }
+    __syncthreads();
+}
+
+// NW = x words per lane of a row: 1 when every circuit has at most 4096 qubits, else 2.
+// Register use is capped so two blocks share a compute unit.
+template <int NW>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4))) k_batch(BatchArgs A)
+{
+    extern __shared__ uint64_t lds[];
+    const int ci = A.order[blockIdx.x];
+    const BatchCirc C = A.circ[ci];
+    const int end = C.step_begin + C.step_count;
+    for (int st = C.step_begin; st < end;) {
+        const int4 s0 = A.steps[st];
+        if (s0.x == 2) {
+            const BatchMeas md = A.meas[s0.y];
+            batch_measure<NW>(A, C, ci, md, lds);
+            ++st;
+            continue;
+        }
+        int en = st + 1;
+        while (en < end && A.steps[en].x != 2) ++en;
+        batch_segment(A, C, ci, st, en, lds);
+        st = en;
+    }
+}
+
+// |0...0> for every circuit: block per circuit.
+__global__ void k_batch_init(const BatchCirc* __restrict__ circ, uint64_t* __restrict__ tab,
+                             uint64_t* __restrict__ rs)
+{
+    const BatchCirc C = circ[blockIdx.x];
+    uint64_t* t = tab + C.tab_off;
+    const long long words = (long long)2 * C.NR * C.RS;
+    for (long long idx = threadIdx.x; idx < words; idx += blockDim.x) {
+        const int row = (int)(idx / C.RS);
+        const int c = (int)(idx - (long long)row * C.RS);
+        uint64_t v = 0;
+        if (row < C.NR) {
+            if (row < C.n && c == (row >> 6)) v = 1ull << (row & 63);
+        } else {
+            const int i = row - C.NR;
+            if (i < C.n && c == C.Wc + (i >> 6)) v = 1ull << (i & 63);
+        }
+        t[idx] = v;
+    }
+    for (int w = threadIdx.x; w < 2 * C.Wc; w += blockDim.x) rs[C.rs_off + w] = 0;
+}
+
+__global__ void k_zero32(uint32_t* __restrict__ p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+}  // namespace stabdev

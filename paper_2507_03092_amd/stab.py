@@ -25,6 +25,9 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
            "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
            "stab_get_counters", "stab_set_timing", "stab_get_kernel_times", "stab_plan_describe",
+           "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
+           "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
+           "stab_batch_execute", "stab_batch_get_tableau", "stab_batch_get_counters",
            "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
@@ -68,6 +71,16 @@ def lib():
         "stab_set_timing": (C.c_int, [P, I32]),
         "stab_get_kernel_times": (C.c_int, [P, P, P, I32]),
         "stab_plan_describe": (C.c_int, [I32, I32, I32, P, I32, P, I64, P, I32]),
+        "stab_batch_bytes": (C.c_int, [I32, P, C.POINTER(U64)]),
+        "stab_batch_create": (C.c_int, [I32, P, U64, P, U64, P, C.POINTER(P)]),
+        "stab_batch_destroy": (None, [P]),
+        "stab_batch_reset": (C.c_int, [P, U64]),
+        "stab_batch_compile": (C.c_int, [P, P, P, P, P, C.POINTER(P)]),
+        "stab_batch_program_records": (I64, [P, I32]),
+        "stab_batch_program_destroy": (None, [P]),
+        "stab_batch_execute": (C.c_int, [P, P, P, C.POINTER(C.c_float)]),
+        "stab_batch_get_tableau": (C.c_int, [P, I32, P, P, P]),
+        "stab_batch_get_counters": (C.c_int, [P, P, I32]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -117,9 +130,12 @@ class Program:
         self.ctx, self.h, self.nrec, self.ninstr = ctx, handle, nrec, ninstr
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().stab_program_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.stab_program_destroy(self.h)
+        except Exception:   # interpreter shutdown
+            pass
+        self.h = None
 
 
 class Context:
@@ -224,3 +240,97 @@ def sample(circ: _circ.Circuit, shots: int, seed: int, mode="shared", device: st
                              seed, C.c_void_p(buf.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream),
                              _ptr(out), C.byref(ms)))
     return unpack_record(out[: shots * ((nrec + 7) // 8)], shots, nrec), ms.value
+
+
+# ------------------------------------------------------------------ multi-circuit batches ---
+def batch_bytes(ns) -> int:
+    n = np.ascontiguousarray(ns, dtype=np.int32)
+    out = C.c_uint64(0)
+    _check(lib().stab_batch_bytes(len(n), _ptr(n), C.byref(out)))
+    return out.value
+
+
+class BatchProgram:
+    def __init__(self, batch: "Batch", handle, nrec):
+        self.batch, self.h, self.nrec = batch, handle, nrec
+        self.rec_byte = np.concatenate([[0], np.cumsum((np.asarray(nrec, dtype=np.int64) + 7) // 8)])
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.stab_batch_program_destroy(self.h)
+        except Exception:   # interpreter shutdown
+            pass
+        self.h = None
+
+
+class Batch:
+    """Independent circuits of different sizes in one device buffer (stab_batch_create);
+    circuit c draws its randomness with key (seed, c)."""
+
+    def __init__(self, ns, seed: int = 0, device: str = "cuda:0"):
+        import torch
+
+        self.ns = np.ascontiguousarray(ns, dtype=np.int32)
+        nbytes = batch_bytes(self.ns)
+        self.device = torch.device(device)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p(None)
+        _check(lib().stab_batch_create(len(self.ns), _ptr(self.ns), seed, C.c_void_p(self.buf.data_ptr()), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().stab_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown
+            pass
+
+    def compile(self, circs) -> BatchProgram:
+        if len(circs) != len(self.ns):
+            raise ValueError("one circuit per batch slot")
+        arrs = [c.arrays() for c in circs]
+        instr = np.concatenate([a[0] for a in arrs]) if arrs else np.zeros(0, dtype=_circ.INSTR_DTYPE)
+        tg = np.concatenate([a[1] for a in arrs]).astype(np.int32)
+        ioff = np.concatenate([[0], np.cumsum([len(a[0]) for a in arrs])]).astype(np.int64)
+        toff = np.concatenate([[0], np.cumsum([len(a[1]) for a in arrs])]).astype(np.int64)
+        instr = np.ascontiguousarray(instr)
+        tg = np.ascontiguousarray(tg)
+        if len(tg) == 0:
+            tg = np.zeros(1, dtype=np.int32)
+        h = C.c_void_p(None)
+        _check(lib().stab_batch_compile(self.h, _ptr(instr), _ptr(ioff), _ptr(tg), _ptr(toff), C.byref(h)))
+        nrec = [int(lib().stab_batch_program_records(h, c)) for c in range(len(circs))]
+        return BatchProgram(self, h, nrec)
+
+    def execute(self, prog: BatchProgram, timed: bool = False):
+        """Run every circuit once; returns a list of per-circuit records (uint8 arrays)."""
+        total = int(prog.rec_byte[-1])
+        out = np.zeros(max(total, 1), dtype=np.uint8)
+        ms = C.c_float(0.0)
+        _check(lib().stab_batch_execute(self.h, prog.h, _ptr(out), C.byref(ms)))
+        recs = [np.unpackbits(out[prog.rec_byte[c]:prog.rec_byte[c + 1]], bitorder="little")[: prog.nrec[c]]
+                for c in range(len(prog.nrec))]
+        return (recs, ms.value) if timed else recs
+
+    def reset(self, seed: int) -> None:
+        _check(lib().stab_batch_reset(self.h, seed))
+
+    def get_tableau(self, c: int):
+        n = int(self.ns[c])
+        x = np.zeros((2 * n, n), dtype=np.uint8)
+        z = np.zeros((2 * n, n), dtype=np.uint8)
+        r = np.zeros(2 * n, dtype=np.uint8)
+        _check(lib().stab_batch_get_tableau(self.h, c, _ptr(x), _ptr(z), _ptr(r)))
+        return x, z, r
+
+    def counters(self) -> np.ndarray:
+        c = np.zeros(8, dtype=np.uint64)
+        _check(lib().stab_batch_get_counters(self.h, _ptr(c), 8))
+        return c

@@ -162,3 +162,68 @@ def test_plan_rejects_malformed_streams(L, bad):
                               tg.ctypes.data_as(C.c_void_p), len(tg), out.ctypes.data_as(C.c_void_p), 8)
     assert rc == stab.EINVAL
     assert L.stab_last_error()
+
+
+# ------------------------------------------------------------------ multi-circuit batches ---
+def _batch_bytes(ns):
+    a = lambda v: (v + 255) & ~255
+    tot = 0
+    for n in ns:
+        wc = (n + 63) // 64
+        tot += a(2 * 64 * wc * 2 * wc * 8)
+    for n in ns:
+        tot += a(2 * ((n + 63) // 64) * 8)
+    return tot
+
+
+@pytest.mark.parametrize("ns", [[1], [64, 65, 2048], [1, 8192], list(range(1, 300, 7))])
+def test_batch_bytes(L, ns):
+    assert stab.batch_bytes(ns) == _batch_bytes(ns)
+
+
+def test_batch_argument_errors_without_gpu(L):
+    out = C.c_uint64(0)
+    n = np.array([5, 0], dtype=np.int32)
+    assert L.stab_batch_bytes(2, n.ctypes.data_as(C.c_void_p), C.byref(out)) == stab.EINVAL
+    n = np.array([5, 8193], dtype=np.int32)
+    assert L.stab_batch_bytes(2, n.ctypes.data_as(C.c_void_p), C.byref(out)) == stab.ERANGE
+    assert L.stab_batch_bytes(0, n.ctypes.data_as(C.c_void_p), C.byref(out)) == stab.EINVAL
+    assert L.stab_batch_bytes(1, None, C.byref(out)) == stab.EINVAL
+    h = C.c_void_p(None)
+    n = np.array([5, 7], dtype=np.int32)
+    p = n.ctypes.data_as(C.c_void_p)
+    assert L.stab_batch_create(2, p, 0, None, 1 << 20, None, C.byref(h)) == stab.EINVAL
+    assert L.stab_batch_create(2, p, 0, C.c_void_p(0x1001), 1 << 20, None, C.byref(h)) == stab.EINVAL
+    assert L.stab_batch_create(2, p, 0, C.c_void_p(0x100000), 16, None, C.byref(h)) == stab.ENOMEM
+    assert L.stab_batch_create(2, p, 0, C.c_void_p(0x100000), 1 << 20, None, None) == stab.EINVAL
+    assert L.stab_batch_reset(None, 0) == stab.EINVAL
+    assert L.stab_batch_execute(None, None, None, None) == stab.EINVAL
+    assert L.stab_batch_get_tableau(None, 0, None, None, None) == stab.EINVAL
+    assert L.stab_batch_program_records(None, 0) == -1
+    L.stab_batch_destroy(None)
+    L.stab_batch_program_destroy(None)
+
+
+def test_random_batch_generator_shapes():
+    ns, circs = Cc.random_batch(6, 64, 300, layers=20, seed=4)
+    assert len(circs) == 6 and all(64 <= n <= 300 for n in ns)
+    for n, c in zip(ns, circs):
+        instr, tg = c.arrays()
+        assert c.n == n and int(instr["ntargets"].sum()) == len(tg)
+        assert c.num_measurements() == 2 * max(1, round(0.1 * n))
+        # every gate layer (H, S, CX between measurements) touches each qubit at most once
+        off = 0
+        seen = set()
+        for k, nt in zip(instr["kind"], instr["ntargets"]):
+            t = tg[off:off + nt]
+            off += nt
+            if k == Cc.M:
+                assert len(set(t.tolist())) == nt
+                continue
+            if k == Cc.H:
+                seen = set()
+            assert not (seen & set(t.tolist()))
+            seen |= set(t.tolist())
+    # deterministic in the seed
+    ns2, circs2 = Cc.random_batch(6, 64, 300, layers=20, seed=4)
+    assert np.array_equal(ns, ns2) and all(np.array_equal(a.targets, b.targets) for a, b in zip(circs, circs2))

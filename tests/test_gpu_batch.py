@@ -1,0 +1,157 @@
+"""GPU parity of the multi-circuit batch (stab_batch_*): every circuit of an uneven batch
+against the CPU oracle run on that circuit alone with first_shot = its index, bit for bit
+(records and, where cheap, the whole final tableau)."""
+from __future__ import annotations
+
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_03092_amd import circuits as Cc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def stab():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2507_03092_amd import stab as S
+
+    S.lib()
+    return S
+
+
+def _oracle_all(circs, seed, idx, want_tableau):
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        futs = {c: ex.submit(O.run, circs[c], 1, seed, c, want_tableau) for c in idx}
+        return {c: f.result() for c, f in futs.items()}
+
+
+def _check_batch(stab, circs, seed, tableau=True, idx=None):
+    ns = np.array([c.n for c in circs], dtype=np.int32)
+    say(f"batch of {len(circs)} circuits, n in [{ns.min()}, {ns.max()}], seed {seed}")
+    idx = list(range(len(circs))) if idx is None else list(idx)
+    want = _oracle_all(circs, seed, idx, tableau)
+    b = stab.Batch(ns, seed=seed)
+    prog = b.compile(circs)
+    got = b.execute(prog)
+    for c in idx:
+        w = want[c]
+        if tableau:
+            w, (tx, tz, tr) = w
+        assert np.array_equal(got[c], w[0]), f"circuit {c} (n={ns[c]}): record differs"
+        if tableau:
+            x, z, r = b.get_tableau(c)
+            assert np.array_equal(x, tx[0]), f"circuit {c}: x differs"
+            assert np.array_equal(z, tz[0]), f"circuit {c}: z differs"
+            assert np.array_equal(r, tr[0]), f"circuit {c}: signs differ"
+    return b, prog, got
+
+
+def test_batch_mixed_sizes_all_kinds(stab):
+    # every instruction kind, noise included, across the band/word boundaries
+    sizes = [1, 2, 5, 17, 63, 64, 65, 127, 130, 200, 257, 333]
+    circs = [Cc.random_clifford_measure(n, depth=10, seed=500 + n, p_meas=0.25, noise=0.02) for n in sizes]
+    _check_batch(stab, circs, seed=11)
+
+
+def test_batch_random_layered_dense(stab):
+    ns, circs = Cc.random_batch(40, 1, 600, layers=40, seed=21, meas_every=4, meas_frac=0.3)
+    _check_batch(stab, circs, seed=21)
+
+
+def test_batch_two_words_per_lane(stab):
+    # a circuit above 4096 qubits switches the kernel to two x words per lane
+    circs = [Cc.random_layered_clifford(4200, 20, (5, 0), meas_every=10, meas_frac=0.05),
+             Cc.random_clifford_measure(70, depth=8, seed=3, p_meas=0.3, noise=0.01),
+             Cc.random_layered_clifford(300, 30, (5, 2), meas_every=5, meas_frac=0.2)]
+    _check_batch(stab, circs, seed=5, tableau=False)
+
+
+def test_batch_surface_codes_with_noise(stab):
+    circs = [Cc.surface_code_memory(d, rounds, 5e-3, Cc.IDLE_T1T2 if d == 5 else None)[0]
+             for d, rounds in ((3, 3), (5, 5), (7, 3), (9, 2))]
+    _check_batch(stab, circs, seed=8)
+
+
+def test_batch_edge_streams(stab):
+    circs = []
+    c = Cc.Circuit(n=3)
+    circs.append(c)                              # empty stream
+    c = Cc.Circuit(n=4)
+    c.gate(Cc.H, [0, 1, 2, 3])
+    c.append(Cc.M, [0, 0, 1, 1, 2])              # repeated targets in one instruction
+    c.append(Cc.MR, [3, 3])
+    c.append(Cc.R, [0])
+    c.append(Cc.M, [0, 3])
+    circs.append(c)
+    c = Cc.Circuit(n=66)
+    c.tick()
+    c.gate(Cc.X, [65])
+    c.gate(Cc.CX, [65, 0, 0, 64])
+    c.append(Cc.M, [64, 0, 65])                  # deterministic outcomes across a word boundary
+    circs.append(c)
+    c = Cc.Circuit(n=129)
+    c.gate(Cc.H, [128])
+    c.gate(Cc.CX, [128, 0, 128, 64])
+    c.append(Cc.M, [0, 64, 128])                 # GHZ: one random, then two deterministic
+    c.gate(Cc.S, [5])
+    c.dep1(0.5, list(range(129)))
+    c.append(Cc.MR, list(range(129)))
+    circs.append(c)
+    _check_batch(stab, circs, seed=2)
+
+
+def test_batch_reset_and_reexecution(stab):
+    ns, circs = Cc.random_batch(16, 10, 300, layers=30, seed=3, meas_every=5, meas_frac=0.2)
+    b, prog, first = _check_batch(stab, circs, seed=3, tableau=False)
+    b.reset(3)
+    again = b.execute(prog)
+    assert all(np.array_equal(x, y) for x, y in zip(first, again))
+    # continuing without a reset equals the oracle on the stream run twice
+    cont = b.execute(prog)
+    for c in (0, 5, 11):
+        ins, tg = circs[c].arrays()
+        both = Cc.PackedCircuit(int(ns[c]), np.concatenate([ins, ins]), np.concatenate([tg, tg]))
+        w = O.run(both, 1, 3, c)[0]
+        assert np.array_equal(np.concatenate([first[c], cont[c]]), w), f"circuit {c}"
+    b.close()
+
+
+def test_batch_random_workload_full_size_sampled(stab):
+    """The 4096-circuit workload at full size, in the launch the benchmark times; the oracle
+    checks the records of a sample of circuits (the smallest ones and a few random ones of
+    moderate size), and every circuit's record length and outcome balance are checked."""
+    w = Cc.RANDOM_BATCH
+    ns, circs = Cc.random_batch(w["ncirc"], w["n_lo"], w["n_hi"], w["layers"], w["seed"], w["meas_every"],
+                                w["meas_frac"])
+    say(f"full batch generated: {len(circs)} circuits, {sum(len(c.targets) for c in circs)} targets")
+    b = stab.Batch(ns, seed=w["seed"])
+    prog = b.compile(circs)
+    got, ms = b.execute(prog, timed=True)
+    say(f"full batch executed in {ms:.1f} ms")
+    order = np.argsort(ns, kind="stable")
+    rng = np.random.default_rng(0)
+    mid = [int(c) for c in rng.choice(np.nonzero((ns > 200) & (ns < 420))[0], size=4, replace=False)]
+    idx = [int(c) for c in order[:8]] + mid
+    want = _oracle_all(circs, w["seed"], idx, False)
+    for c in idx:
+        assert np.array_equal(got[c], want[c][0]), f"circuit {c} (n={ns[c]}): record differs"
+    for c in range(len(circs)):
+        assert len(got[c]) == circs[c].num_measurements()
+    # most measurements of random dense circuits are random: outcomes near 50/50 overall
+    allbits = np.concatenate(got)
+    assert 0.45 < allbits.mean() < 0.55
+    b.close()
