@@ -70,8 +70,10 @@ typedef struct stab_instr {
 
 typedef struct stab_ctx stab_ctx;
 
-/* Largest qubit count this build supports (one 64-row band of the tableau must fit in the
- * 160 KB of LDS of one compute unit). */
+/* Largest qubit count this build supports: 10240 (160 64-bit words of x or z per row; the
+ * random-measurement kernel keeps a target's column, 2 * 160 band words, in the registers of
+ * one wave, and half a band of the tableau must fit in the 160 KB of LDS of one compute
+ * unit). */
 int32_t stab_max_qubits(void);
 
 /* Bytes of device memory a context needs in dev_buf for n qubits and `shots` shots in the

@@ -26,18 +26,19 @@ int fail(int code, const std::string& msg)
 }
 
 constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
-constexpr int kSegThreads = 1024;
+constexpr int kSegThreads = 512;
 constexpr int kChainThreads = 512;
 constexpr int kMCap = 256;                // rows listed per deterministic measurement
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
 
+// 32-bit words of the segment kernel's LDS for one half-band (before the per-shot accumulators)
 int seg_lds_words(int RS) { return 64 * (RS + 1) + kRedWords; }
 
 int max_qubits_for_lds(int lds_bytes)
 {
-    // 64 * (2*Wc + 1) + kRedWords words must fit
-    const int words = lds_bytes / 8 - kRedWords;
+    // a staged half-band, 64 * (2*Wc + 1) + kRedWords 32-bit words, must fit
+    const int words = lds_bytes / 4 - kRedWords;
     const int wc = (words / 64 - 1) / 2;
     // register-resident limits: column words per lane (deterministic wave), band words per lane
     // (chain analysis: 2 * wc <= 64 * kMaxBandsPerLane)
@@ -436,10 +437,10 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
         return fail(STAB_EDEVICE, "no HIP device");
     }
     ctx->max_lds = lds;
-    const int seg_bytes = seg_lds_words(ctx->g.RS) * 8;
+    const int seg_bytes = seg_lds_words(ctx->g.RS) * 4;
     if (seg_bytes > lds) {
         delete ctx;
-        return fail(STAB_ERANGE, "a 64-row band does not fit in this device's LDS");
+        return fail(STAB_ERANGE, "a half-band of the tableau does not fit in this device's LDS");
     }
     (void)hipFuncSetAttribute((const void*)k_segment, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -606,8 +607,11 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     uint8_t* record = (uint8_t*)ctx->record.p;
     const uint64_t base = ctx->instr_counter;
 
-    const int lds_rd = (seg_lds_words(g.RS) + g.bpc) * 8 <= ctx->max_lds ? 1 : 0;
-    const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 8;
+    // per-shot sign accumulators in LDS only where they keep two half-band blocks per compute
+    // unit (or where even one block without them would not get two)
+    const int seg_base = seg_lds_words(g.RS) * 4, seg_acc = (seg_lds_words(g.RS) + g.bpc) * 4;
+    const int lds_rd = (seg_acc <= ctx->max_lds / 2 || (seg_base > ctx->max_lds / 2 && seg_acc <= ctx->max_lds)) ? 1 : 0;
+    const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 4;
     const size_t chain_lds = (size_t)chain_lds_layout(g).total;
     if (chain_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
 
@@ -645,7 +649,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                 }
                 a.Xcol = Xcol;
                 a.Zcol = Zcol;
-                TIMED(ctx, 2, (k_segment<<<dim3(g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
+                TIMED(ctx, 2, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
                                   g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
         } else {

@@ -10,10 +10,11 @@
 //        masks into signs, so those go to rs, while noise, random outcomes and resets (the
 //        only shot-dependent parts) go to rd.
 //
-// A "band" is 64 consecutive rows.  The segment kernel stages one band in LDS, turns its
-// 64x64 bit tiles into qubit-major words (word = 64 rows of one qubit column), applies a
-// whole run of gate and noise layers there, extracts the columns the next measurement layer
-// needs and writes the band back.  Measurements then work on rows (rowsum, Appendix A.2).
+// A "band" is 64 consecutive rows.  The segment kernel stages half a band (32 rows) in LDS,
+// turns its 32x32 bit tiles into qubit-major 32-bit words (one bit per row of one qubit
+// column), applies a whole run of gate and noise layers there, extracts the columns the next
+// measurement layer needs and writes the rows back.  Measurements then work on rows (rowsum,
+// Appendix A.2).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -120,6 +121,29 @@ __device__ __forceinline__ int gsum(uint64_t x1, uint64_t z1, uint64_t x2, uint6
 
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
 
+// v from lane (lane ^ j), j in {1, 2, 4, 8, 16}, without the LDS crossbar: DPP quad permutes
+// and row mirrors for j <= 8 (xor 4 = half-mirror then quad xor 3; xor 8 = mirror then
+// half-mirror) and the gfx950 permlane16 swap for j = 16.  Every lane must be active.
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int j, int lane)
+{
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
+    case 4: {
+        const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, true);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, true);
+    }
+    case 8: {
+        const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, true);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x141, 0xF, 0xF, true);
+    }
+    default: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // init: |0...0> -- destabilizer i = +X_i, stabilizer i = +Z_i, all signs 0.
 // ------------------------------------------------------------------------------------------
@@ -214,8 +238,8 @@ k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// Segment kernel: grid (NB bands, S copies), 1024 threads.  See the file header.
-// Column j of the staged band: x word at T[(j & 63) * RSP + (j >> 6)], z word at + Wc.
+// Segment kernel helpers.  Column j of a staged half-band: x word at
+// T[(j & 63) * RSP + (j >> 6)], z word at + Wc (32-bit words, one bit per staged row).
 // ------------------------------------------------------------------------------------------
 constexpr int kSegPrefetch = 8;   // gates / events per thread prefetched into registers
 
@@ -250,12 +274,13 @@ __device__ __forceinline__ void fetch_item(const SegArgs& a, int it, int tid, in
     }
 }
 
-__device__ __forceinline__ void apply_gate(uint64_t* T, int RSP, int Wc, uint2 gt, uint64_t& racc)
+// A gate on the 32 staged rows: x word of qubit q at T[(q & 63) * RSP + (q >> 6)], z at + Wc.
+__device__ __forceinline__ void apply_gate(uint32_t* T, int RSP, int Wc, uint2 gt, uint32_t& racc)
 {
     const int kind = (int)(gt.x & 15u);
     const int q0 = (int)(gt.x >> 4);
     const int i0 = (q0 & 63) * RSP + (q0 >> 6);
-    const uint64_t x0 = T[i0], z0 = T[i0 + Wc];
+    const uint32_t x0 = T[i0], z0 = T[i0 + Wc];
     switch (kind) {
     case STAB_KIND_H:
         racc ^= x0 & z0;
@@ -272,7 +297,7 @@ __device__ __forceinline__ void apply_gate(uint64_t* T, int RSP, int Wc, uint2 g
     case STAB_KIND_CX: {
         const int q1 = (int)gt.y;
         const int i1 = (q1 & 63) * RSP + (q1 >> 6);
-        const uint64_t x1 = T[i1], z1 = T[i1 + Wc];
+        const uint32_t x1 = T[i1], z1 = T[i1 + Wc];
         racc ^= x0 & z1 & ~(x1 ^ z0);
         T[i1] = x1 ^ x0;
         T[i0 + Wc] = z0 ^ z1;
@@ -282,42 +307,73 @@ __device__ __forceinline__ void apply_gate(uint64_t* T, int RSP, int Wc, uint2 g
 }
 
 // Noise event {qubit | pauli << 28, shot}: flip the signs of the rows the Pauli anticommutes with.
-__device__ __forceinline__ void apply_event(const uint64_t* T, int RSP, int Wc, uint2 v, int s, int band,
-                                            const Geom& g, const SegArgs& a, uint64_t* rdacc,
-                                            uint64_t* rd)
+__device__ __forceinline__ void apply_event(const uint32_t* T, int RSP, int Wc, uint2 v, int s, int hb,
+                                            const Geom& g, const SegArgs& a, uint32_t* rdacc,
+                                            uint32_t* rd32)
 {
     const int sb = (int)v.y - s * g.bpc;
     if (sb < 0 || sb >= g.bpc) return;
     const int q = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
     const int iq = (q & 63) * RSP + (q >> 6);
-    const uint64_t xq = T[iq], zq = T[iq + Wc];
-    const uint64_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
+    const uint32_t xq = T[iq], zq = T[iq + Wc];
+    const uint32_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
     if (m) {
-        if (a.lds_rd) atomicXor((unsigned long long*)&rdacc[sb], (unsigned long long)m);
-        else atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + sb) * g.NB + band], (unsigned long long)m);
+        if (a.lds_rd) atomicXor(&rdacc[sb], m);
+        else atomicXor(&rd32[(size_t)(s * g.bpc + sb) * 2 * g.NB + hb], m);
     }
 }
 
-__global__ void __launch_bounds__(1024)
+// In-register transpose of the 32x32 bit matrix held by each half-wave, one row per lane
+// (bit c of lane r's word = element (r, c)); lanes 32..63 transpose their own matrix.
+__device__ __forceinline__ uint32_t transpose32(uint32_t v, int lane)
+{
+    const uint32_t masks[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const int j = 16 >> st;
+        const uint32_t m = masks[st];
+        const uint32_t o = lane_xor32(v, j, lane);
+        if (lane & j) {
+            v ^= ((o >> j) ^ v) & m;
+        } else {
+            v ^= (((v >> j) ^ o) & m) << j;
+        }
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Segment kernel: grid (2 * NB half-bands, S copies), 512 threads.  A block stages 32 rows
+// (half of a 64-row band) as 32-bit qubit-major words: row r's 64-bit word c is split into
+// its low half (columns 64c..64c+31, staged at lane r) and high half (lane 32 + r); each
+// half-wave then transposes its 32x32 tile, so afterwards lane L of tile c holds column
+// 64c + L for the 32 rows.  Two such blocks fit the LDS of one compute unit.  The block owns
+// the 32-bit half of every sign word and column-extract word of its band.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(512)
 k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
           uint64_t* __restrict__ rd, SegArgs a)
 {
-    extern __shared__ uint64_t lds[];
-    const int band = blockIdx.x, s = blockIdx.y;
+    extern __shared__ uint32_t lds32[];
+    const int hb = blockIdx.x;                   // half-band: band = hb >> 1, half = hb & 1
+    const int band = hb >> 1, half = hb & 1;
+    const int s = blockIdx.y;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int RS = g.RS, RSP = g.RS + 1, Wc = g.Wc;
-    uint64_t* T = lds;
-    uint64_t* red = lds + 64 * RSP;              // nwaves words
-    uint64_t* rdacc = red + 16;                  // bpc words when a.lds_rd
-    uint64_t* gb = tab + ((size_t)s * 2 * g.NR + (size_t)band * 64) * RS;
+    uint32_t* T = lds32;                         // 64 x RSP
+    uint32_t* red = lds32 + 64 * RSP;            // nwaves words
+    uint32_t* rdacc = red + 16;                  // bpc words when a.lds_rd
+    uint64_t* gb = tab + ((size_t)s * 2 * g.NR + (size_t)band * 64 + (size_t)half * 32) * RS;
+    uint32_t* rs32 = (uint32_t*)rs;
+    uint32_t* rd32 = (uint32_t*)rd;
 
-    // the first item's list is fetched while the band loads
     ItemBuf cur, nxt;
     fetch_item(a, 0, tid, nt, cur);
 
-    // band -> LDS: 16-byte loads (RS is even, so a pair never crosses a row), 8 in flight
-    const int npairs = 32 * RS;
+    // 32 rows -> LDS with 16-byte loads (RS is even, so a pair never crosses a row), 8 in
+    // flight; word (r, c) splits into T[r][c] (low half) and T[32 + r][c] (high half)
+    const int npairs = 16 * RS;
     const ulonglong2* gb2 = (const ulonglong2*)gb;
     for (int p0 = 0; p0 < npairs; p0 += 8 * nt) {
         ulonglong2 v[8];
@@ -333,8 +389,12 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
                 const int i = 2 * p;
                 const int r = i / RS;
                 const int c = i - r * RS;
-                T[r * RSP + c] = v[u].x;
-                T[r * RSP + c + 1] = v[u].y;
+                uint32_t* lo = T + r * RSP + c;
+                uint32_t* hi = lo + 32 * RSP;
+                lo[0] = (uint32_t)v[u].x;
+                lo[1] = (uint32_t)v[u].y;
+                hi[0] = (uint32_t)(v[u].x >> 32);
+                hi[1] = (uint32_t)(v[u].y >> 32);
             }
         }
     }
@@ -342,14 +402,13 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
         for (int b = tid; b < g.bpc; b += nt) rdacc[b] = 0;
     __syncthreads();
     for (int c = wave; c < RS; c += nwaves) {
-        uint64_t v = T[lane * RSP + c];
-        v = transpose64(v, lane);
+        uint32_t v = T[lane * RSP + c];
+        v = transpose32(v, lane);
         T[lane * RSP + c] = v;
     }
     __syncthreads();
 
-    // column j: x word at T[(j & 63) * RSP + (j >> 6)], z word at + Wc
-    uint64_t racc = 0;
+    uint32_t racc = 0;
     for (int it = 0; it < a.nitems; ++it) {
         fetch_item(a, it + 1, tid, nt, nxt);       // next item's list, in flight meanwhile
         if (cur.type == 0) {
@@ -361,29 +420,29 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
         } else {
 #pragma unroll
             for (int u = 0; u < kSegPrefetch; ++u)
-                if (tid + u * nt < cur.count) apply_event(T, RSP, Wc, cur.v[u], s, band, g, a, rdacc, rd);
+                if (tid + u * nt < cur.count) apply_event(T, RSP, Wc, cur.v[u], s, 2 * band + half, g, a, rdacc, rd32);
             for (int e = tid + kSegPrefetch * nt; e < cur.count; e += nt)
-                apply_event(T, RSP, Wc, cur.src[e], s, band, g, a, rdacc, rd);
+                apply_event(T, RSP, Wc, cur.src[e], s, 2 * band + half, g, a, rdacc, rd32);
         }
         __syncthreads();
         cur = nxt;
     }
 
     if (a.K > 0) {
-        uint64_t* Xc = a.Xcol + ((size_t)s * g.NB + band) * a.K;
-        uint64_t* Zc = a.Zcol + ((size_t)s * g.NB + band) * a.K;
+        uint32_t* Xc = (uint32_t*)(a.Xcol + ((size_t)s * g.NB + band) * a.K);
+        uint32_t* Zc = (uint32_t*)(a.Zcol + ((size_t)s * g.NB + band) * a.K);
         for (int k = tid; k < a.K; k += nt) {
             const int q = a.ext_q[k];
             const int iq = (q & 63) * RSP + (q >> 6);
-            Xc[k] = T[iq];
-            Zc[k] = T[iq + Wc];
+            Xc[2 * k + half] = T[iq];
+            Zc[2 * k + half] = T[iq + Wc];
         }
     }
     if (a.write_back) {
         __syncthreads();
         for (int c = wave; c < RS; c += nwaves) {
-            uint64_t v = T[lane * RSP + c];
-            v = transpose64(v, lane);
+            uint32_t v = T[lane * RSP + c];
+            v = transpose32(v, lane);
             T[lane * RSP + c] = v;
         }
         __syncthreads();
@@ -392,24 +451,28 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
             const int i = 2 * p;
             const int r = i / RS;
             const int c = i - r * RS;
+            const uint32_t* lo = T + r * RSP + c;
+            const uint32_t* hi = lo + 32 * RSP;
             ulonglong2 v;
-            v.x = T[r * RSP + c];
-            v.y = T[r * RSP + c + 1];
+            v.x = (uint64_t)lo[0] | ((uint64_t)hi[0] << 32);
+            v.y = (uint64_t)lo[1] | ((uint64_t)hi[1] << 32);
             gw2[p] = v;
         }
     }
-    racc = wave_xor(racc);
+    // sign contributions: XOR-reduce 32-bit masks
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) racc ^= (uint32_t)__shfl_xor((int)racc, m, 64);
     if (lane == 0) red[wave] = racc;
     __syncthreads();
     if (tid == 0) {
-        uint64_t t = 0;
+        uint32_t t = 0;
         for (int w = 0; w < nwaves; ++w) t ^= red[w];
-        if (t) rs[(size_t)s * g.NB + band] ^= t;
+        if (t) rs32[((size_t)s * g.NB + band) * 2 + half] ^= t;
     }
     if (a.lds_rd) {
         for (int b = tid; b < g.bpc; b += nt) {
-            const uint64_t v = rdacc[b];
-            if (v) rd[(size_t)(s * g.bpc + b) * g.NB + band] ^= v;
+            const uint32_t v = rdacc[b];
+            if (v) rd32[((size_t)(s * g.bpc + b) * g.NB + band) * 2 + half] ^= v;
         }
     }
 }

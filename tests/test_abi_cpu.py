@@ -49,8 +49,8 @@ def test_instruction_record_is_32_bytes():
 
 
 def test_max_qubits(L):
-    # one 64-row band (64 x (2*ceil(n/64) + 1) words plus 16 reduction words) in 160 KB of LDS
-    assert stab.max_qubits() == 159 * 64
+    # 2 * ceil(n/64) band words of a target column over one wave (5 per lane)
+    assert stab.max_qubits() == 160 * 64
 
 
 def _bytes(n, shots, mode):
@@ -65,7 +65,7 @@ def _bytes(n, shots, mode):
 
 
 @pytest.mark.parametrize("n,shots,mode", [(1, 1, 0), (17, 1000, 0), (1249, 100, 0), (1249, 100, 1),
-                                          (10081, 10, 0), (64, 3, 1), (65, 3, 1)])
+                                          (10081, 10, 0), (10240, 2, 0), (64, 3, 1), (65, 3, 1)])
 def test_tableau_bytes(L, n, shots, mode):
     assert stab.tableau_bytes(n, shots, mode) == _bytes(n, shots, mode)
 
