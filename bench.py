@@ -56,6 +56,20 @@ def seg_bytes_per_launch(n: int, shots: int, mode: str, K: int, write_back: bool
     return copies * nb * (band * (2 if write_back else 1) + 2 * K * 8)
 
 
+def load_pmc(workload: str, mode: str) -> dict:
+    """HBM bytes per launch of each kernel from the committed rocprofv3 counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE, scaled by what they read for a plain copy of known
+    size), if it was taken from the current kernel sources; else {}."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return {}
+    p = json.load(open(path))
+    if p.get("source_digest") != kernel_source_digest() or p.get("mode") != mode:
+        return {}
+    fs, ws = p["fetch_scale"], p["write_scale"]
+    return {k: (v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024.0 for k, v in p["kernels"].items()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +131,7 @@ def main() -> int:
         ctx.reset(seed)
         ctx.execute(prog)
     ctx.set_timing(True)
+    cnt0 = ctx.counters().astype(np.int64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -126,36 +141,48 @@ def main() -> int:
     t1 = time.perf_counter()
     ktimes = ctx.kernel_times()
     ctx.set_timing(False)
+    work = (ctx.counters().astype(np.int64) - cnt0) / steps     # per step
     ms_step = (t1 - t0) * 1000.0 / steps
     rounds_s = shots * rounds / ((t1 - t0) / steps)
     meas_s = shots * nmeas / ((t1 - t0) / steps)
     log(f"batched: {ms_step:.3f} ms/step, {rounds_s:.1f} rounds/s, {meas_s:.3e} meas/s")
 
-    # ---------------- roofline of the dominant kernel ----------------
+    # ---------------- rooflines: the dominant kernel, and the segment kernel ----------------
     per_step = {k: (v[0] / steps, v[1] / steps) for k, v in ktimes.items()}
     dom = max(per_step, key=lambda k: per_step[k][0])
-    roofline = None
-    launches = ktimes["segment"][1]
-    if launches:
+    wc = (n + 63) // 64
+    row_b, nb = 2 * wc * 8, 2 * wc
+    copies = 1 if args.mode == "shared" else shots
+    # algorithmic bytes per step of each kernel (see the design doc for the per-unit figures)
+    alg = {
         # surface-code stream: one segment per round (gates change x|z) plus the noise-only
         # segment before the final data readout; K = d*d-1 ancillas, then d*d data qubits
-        nseg_wb = rounds
-        tot = nseg_wb * seg_bytes_per_launch(n, shots, args.mode, d * d - 1, True) + \
-            seg_bytes_per_launch(n, shots, args.mode, d * d, False)
-        tot_steps = tot * steps
-        seg_ms = ktimes["segment"][0]
-        achieved = tot_steps / (seg_ms / 1000.0) / 1e9
-        traffic = None
-        pmc = os.path.join(ROOT, "profiles", f"segment_{args.workload}_pmc.json")
-        if os.path.exists(pmc):
-            p = json.load(open(pmc))
-            if p.get("source_digest") == kernel_source_digest() and p.get("mode") == args.mode:
-                traffic = p.get("bytes_per_launch")
-        roofline = {"kernel": "segment", "bound": "hbm", "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "bytes_per_launch": int(tot / (nseg_wb + 1)),
-                    "avg_launch_us": round(seg_ms * 1000.0 / launches, 2),
-                    "dominant_kernel": dom}
+        "segment": rounds * seg_bytes_per_launch(n, shots, args.mode, d * d - 1, True)
+        + seg_bytes_per_launch(n, shots, args.mode, d * d, False),
+        # per random measurement: its column (one word per band), the pivot row read, the
+        # replaced destabilizer and stabilizer rows written; per rowsum row a read and a write
+        "chain": work[4] * (nb * 8 + 3 * row_b) + work[5] * 2 * row_b,
+        # per deterministic measurement: its column and every multiplied stabilizer row read
+        "det": (work[2] + work[6]) * nb * 8 + work[3] * row_b,
+    }
+    pmc = load_pmc(args.workload, args.mode)
+
+    def roof(kernel):
+        ms, launches = per_step[kernel]
+        if not launches or kernel not in alg:
+            return None
+        per_launch = alg[kernel] / launches
+        achieved = per_launch / (ms / launches / 1000.0) / 1e9
+        t = pmc.get(kernel)
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": int(t) if t is not None else None, "bytes_per_launch": int(per_launch),
+                "avg_launch_us": round(ms * 1000.0 / launches, 2), "launches_per_step": launches}
+
+    roofline = roof(dom)
+    if roofline is not None:
+        roofline["share_of_step"] = round(per_step[dom][0] / (((t1 - t0) / steps) * 1000.0), 3)
+    roofline_segment = roof("segment")
 
     # ---------------- plain: one shot at a time ----------------
     plain = None
@@ -215,6 +242,11 @@ def main() -> int:
         "plain": plain,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items() if v[1] > 0},
         "roofline": roofline,
+        "roofline_segment": roofline_segment,
+        "work_per_step": {"random_measurements": int(work[4]), "rowsum_rows": int(work[5]),
+                          "deterministic_measurements": int(work[2] + work[6]),
+                          "multiplied_rows": int(work[3]), "chain_rounds": int(work[0]),
+                          "noise_events": int(work[7])},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
