@@ -159,9 +159,13 @@ def main() -> int:
         # segment before the final data readout; K = d*d-1 ancillas, then d*d data qubits
         "segment": rounds * seg_bytes_per_launch(n, shots, args.mode, d * d - 1, True)
         + seg_bytes_per_launch(n, shots, args.mode, d * d, False),
-        # per random measurement: its column (one word per band), the pivot row read, the
-        # replaced destabilizer and stabilizer rows written; per rowsum row a read and a write
-        "chain": work[4] * (nb * 8 + 3 * row_b) + work[5] * 2 * row_b,
+        # per random measurement: the stabilizer half of its column, the pivot row read, logged
+        # and replaced; per stabilizer rowsum row a read and a write
+        "chain": work[4] * (wc * 8 + 3 * row_b) + work[5] * 2 * row_b,
+        # per walked destabilizer a read and a write, per applied pivot its logged row read
+        "replay": work[9] * 2 * row_b + work[8] * row_b,
+        # the final tableau read and the columns of every target written (about d*d targets)
+        "extract": per_step.get("extract", (0, 0))[1] * seg_bytes_per_launch(n, shots, args.mode, d * d, False),
         # per deterministic measurement: its column and every multiplied stabilizer row read
         "det": (work[2] + work[6]) * nb * 8 + work[3] * row_b,
     }
@@ -244,6 +248,7 @@ def main() -> int:
         "roofline": roofline,
         "roofline_segment": roofline_segment,
         "work_per_step": {"random_measurements": int(work[4]), "rowsum_rows": int(work[5]),
+                          "replay_rowsum_rows": int(work[8]), "replay_walked_rows": int(work[9]),
                           "deterministic_measurements": int(work[2] + work[6]),
                           "multiplied_rows": int(work[3]), "chain_rounds": int(work[0]),
                           "noise_events": int(work[7])},

@@ -161,18 +161,20 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
 /* Work counters accumulated by a context since creation (for accounting and bandwidth
  * figures): [0] rounds of the random-measurement chain, [1] chain rounds run by a whole block
  * (targets touching many rows), [2] measurements deterministic at layer start, [3] stabilizer
- * rows multiplied by deterministic reductions, [4] random measurements, [5] rows updated by
- * rowsum, [6] measurements found deterministic inside the chain, [7] noise events.
- * ncounters <= 8.  Synchronizes the stream. */
+ * rows multiplied by deterministic reductions, [4] random measurements, [5] stabilizer rows
+ * updated by rowsum, [6] measurements found deterministic inside the chain, [7] noise events,
+ * [8] destabilizer rows updated by rowsum (replay), [9] destabilizer rows the replay walked.
+ * ncounters <= 10.  Synchronizes the stream. */
 int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 
 /* Per-kernel device timing with HIP events recorded on the context's stream around every
  * launch.  stab_set_timing(ctx, 1) clears the totals and starts timing; 0 stops it.
  * stab_get_kernel_times writes, for each kernel id, the summed milliseconds and the number of
  * launches since timing started.  Kernel ids: 0 init, 1 noise draw, 2 segment (gates + noise
- * + column extraction), 3 classify, 4 deterministic batch, 5 random chain, 6 reset/record,
- * 7 record packing.  nkernels <= 8. */
-#define STAB_NUM_KERNELS 8
+ * + column extraction), 3 classify, 4 deterministic batch, 5 random chain (stabilizer rows),
+ * 6 reset/record, 7 record packing, 8 destabilizer replay, 9 column extraction after a layer
+ * with random outcomes.  nkernels <= 10. */
+#define STAB_NUM_KERNELS 10
 int stab_set_timing(stab_ctx *ctx, int32_t enable);
 int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t nkernels);
 
@@ -236,7 +238,7 @@ int stab_batch_get_tableau(stab_batch *batch, int32_t circuit, uint8_t *x, uint8
  * [6] bytes the measurements must move (target columns at one 8-byte word per row, pivot
  * row, rowsum rows read and written, row moves; multiplied rows read), [7] bytes of the
  * band passes (every row read, and written when a gate changed x|z); the others stay 0.
- * ncounters <= 8. */
+ * ncounters <= 10. */
 int stab_batch_get_counters(stab_batch *batch, uint64_t *counters, int32_t ncounters);
 
 /* Message of the last error on this thread ("" if none). */

@@ -31,6 +31,8 @@ constexpr int kChainThreads = 512;
 constexpr int kMCap = 256;                // rows listed per deterministic measurement
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
+constexpr int kReplayThreads = 512;
+constexpr int kNumKernels = 10;           // timing ids (include/stab.h)
 
 // 32-bit words of the segment kernel's LDS for one half-band (before the per-shot accumulators)
 int seg_lds_words(int RS) { return 64 * (RS + 1) + kRedWords; }
@@ -97,14 +99,15 @@ struct stab_ctx {
     unsigned long long* d_counters = nullptr;
     int* d_tmap = nullptr;
     DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed, pend;
+    DevBuf plog_p, plog_row, plog_rs, plog_rd, ran;   // pivot log of the random chain
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing (stab_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> evpool;
     std::vector<int> evkind;      // kernel id of each recorded pair
     size_t evused = 0;            // events used in the current execution
-    double kms[8] = {0};
-    unsigned long long klaunch[8] = {0};
+    double kms[kNumKernels] = {0};
+    unsigned long long klaunch[kNumKernels] = {0};
 };
 
 namespace {
@@ -473,8 +476,9 @@ void stab_destroy(stab_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount,
-                      &ctx->obuf, &ctx->events, &ctx->record, &ctx->packed, &ctx->pend};
+    DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount, &ctx->obuf,
+                      &ctx->events, &ctx->record, &ctx->packed, &ctx->pend, &ctx->plog_p,
+                      &ctx->plog_row, &ctx->plog_rs, &ctx->plog_rd, &ctx->ran};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
@@ -595,7 +599,10 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         (rc = ensure(ctx->mlist, (size_t)g.S * kMCap * K * 4)) || (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
         (rc = ensure(ctx->events, (size_t)std::max<long long>(P->ev_cap_max, 1) * 8)) ||
         (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
-        (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))))
+        (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))) ||
+        (rc = ensure(ctx->plog_p, (size_t)g.S * K * 4)) || (rc = ensure(ctx->plog_rs, (size_t)g.S * K * 4)) ||
+        (rc = ensure(ctx->plog_row, (size_t)g.S * K * g.RS * 8)) ||
+        (rc = ensure(ctx->plog_rd, (size_t)g.S * K * ((g.bpc + 63) / 64) * 8)) || (rc = ensure(ctx->ran, 4)))
         return rc;
     uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
     uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
@@ -614,6 +621,13 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 4;
     const size_t chain_lds = (size_t)chain_lds_layout(g).total;
     if (chain_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
+    const size_t replay_lds = (size_t)(kReplayThreads / 64) * ((g.bpc + 63) / 64) * 8 + K * 4;
+    if (replay_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the replay kernel");
+    int* plog_p = (int*)ctx->plog_p.p;
+    int* plog_rs = (int*)ctx->plog_rs.p;
+    uint64_t* plog_row = (uint64_t*)ctx->plog_row.p;
+    uint64_t* plog_rd = (uint64_t*)ctx->plog_rd.p;
+    int* ran = (int*)ctx->ran.p;
 
     HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     if (P->nnoise > 0)
@@ -659,10 +673,35 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 0)));
             TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
                                                                  mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -1)));
+            HIP_CHECK(ctx, hipMemsetAsync(ran, 0, sizeof(int), ctx->stream));
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               ctx->d_tmap, (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
-                              m.pos_base, m.kind != STAB_M ? 1 : 0, obuf, ctx->d_err, ctx->d_counters)));
+                              m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, obuf, ctx->d_err,
+                              ctx->d_counters)));
+            // destabilizer updates of the run targets, then fresh columns of the final tableau
+            // (skipped on the device when nothing ran)
+            TIMED(ctx, 8, (k_replay<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
+                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
+                              plog_rs, plog_rd, ctx->d_err, ctx->d_counters)));
+            {
+                SegArgs a{};
+                a.items = P->d_items;
+                a.nitems = 0;
+                a.gates = P->d_gates;
+                a.events = events;
+                a.ev_count = P->d_ev_count;
+                a.ev_base = P->d_ev_base;
+                a.write_back = 0;
+                a.lds_rd = 0;
+                a.ext_q = P->d_mtq + m.tq_begin;
+                a.K = K2;
+                a.Xcol = Xcol;
+                a.Zcol = Zcol;
+                a.gate = ran;
+                TIMED(ctx, 9, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, (size_t)seg_lds_words(g.RS) * 4,
+                                           ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
+            }
             // targets the chain found deterministic: reduced in parallel on the final tableau
             TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
             TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
@@ -757,7 +796,7 @@ int stab_get_tableau(stab_ctx* ctx, int32_t shot, uint8_t* x, uint8_t* z, uint8_
 
 int stab_get_counters(stab_ctx* ctx, uint64_t* counters, int32_t ncounters)
 {
-    if (!ctx || !counters || ncounters < 0 || ncounters > 8) return fail(STAB_EINVAL, "bad arguments");
+    if (!ctx || !counters || ncounters < 0 || ncounters > kNumCounters) return fail(STAB_EINVAL, "bad arguments");
     unsigned long long c[kNumCounters * kCounterStripes];
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     HIP_CHECK(ctx, hipMemcpy(c, ctx->d_counters, sizeof(c), hipMemcpyDeviceToHost));
@@ -776,7 +815,7 @@ int stab_set_timing(stab_ctx* ctx, int32_t enable)
     ctx->timing = enable != 0;
     ctx->evkind.clear();
     ctx->evused = 0;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < kNumKernels; ++i) {
         ctx->kms[i] = 0.0;
         ctx->klaunch[i] = 0;
     }
@@ -785,7 +824,7 @@ int stab_set_timing(stab_ctx* ctx, int32_t enable)
 
 int stab_get_kernel_times(stab_ctx* ctx, double* ms, uint64_t* launches, int32_t nkernels)
 {
-    if (!ctx || nkernels < 0 || nkernels > 8) return fail(STAB_EINVAL, "bad arguments");
+    if (!ctx || nkernels < 0 || nkernels > kNumKernels) return fail(STAB_EINVAL, "bad arguments");
     for (int i = 0; i < nkernels; ++i) {
         if (ms) ms[i] = ctx->kms[i];
         if (launches) launches[i] = ctx->klaunch[i];

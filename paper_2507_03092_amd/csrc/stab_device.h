@@ -34,7 +34,7 @@ struct NoiseDesc {
 
 // Work counters are striped over this many addresses (by block) to keep atomics uncontended.
 constexpr int kCounterStripes = 32;
-constexpr int kNumCounters = 8;
+constexpr int kNumCounters = 10;
 
 __device__ __forceinline__ void count_add(unsigned long long* counters, int idx, unsigned long long v)
 {
@@ -53,7 +53,7 @@ constexpr int kAffCap = 1024;    // column-upkeep work list of a wide batch
 struct ChainLds {
     int solo;    // block-solo buffers: 2 rows, 2 band masks, per-shot pivot signs, word list
     int owner;   // NR ints: first window target owning each row pair
-    int wide;    // kWide x 2 rows (pivot row and its destabilizer) of the batch
+    int wide;    // kWide pivot rows of the batch
     int words;   // kWide x kRCap (word, mask) lists of the batch's rowsum rows
     int aff;     // kAffCap column-upkeep entries {code, flags, batch index}
     int win;     // window arrays: 9 x kWin ints + kWin x kRCap row indices
@@ -69,7 +69,7 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
     L.solo = 0;
     L.owner = align16i((2 * g.RS + 2 * g.NB + nrdw) * 8 + g.NB * 4);
     L.wide = L.owner + align16i(g.NR * 4);
-    L.words = L.wide + kWide * 2 * g.RS * 8;
+    L.words = L.wide + kWide * g.RS * 8;
     L.aff = L.words + kWide * kRCap * 12;
     L.win = L.aff + kAffCap * 12;
     L.total = L.win + (9 * kWin + kWin * kRCap) * 4;
@@ -89,6 +89,7 @@ struct SegArgs {
     int K;
     uint64_t* Xcol;        // [S][NB][K]
     uint64_t* Zcol;
+    const int* gate;       // if set and *gate == 0 the launch does nothing
 };
 
 }  // namespace stabdev

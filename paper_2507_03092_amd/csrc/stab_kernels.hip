@@ -67,6 +67,13 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
     return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const int lo = __shfl((int)(uint32_t)v, src, 64);
+    const int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
 #pragma unroll
@@ -354,6 +361,7 @@ __global__ void __launch_bounds__(512)
 k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
           uint64_t* __restrict__ rd, SegArgs a)
 {
+    if (a.gate && *a.gate == 0) return;   // an extraction pass with nothing to refresh
     extern __shared__ uint32_t lds32[];
     const int hb = blockIdx.x;                   // half-band: band = hb >> 1, half = hb & 1
     const int band = hb >> 1, half = hb & 1;
@@ -679,20 +687,28 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
 //
 // Sequential semantics (Sec. 2.4): targets are measured in op order; each may have turned
 // deterministic because of an earlier one in the same layer.  A random one: pivot p = first
-// stabilizer with x at the qubit; rowsum(i, p) for every other row i with x at the qubit (the
-// pivot's destabilizer q is skipped: it is overwritten next); q <- old row p; p <- Z_a with
-// the outcome as sign.  A deterministic one reads the stabilizers selected by the
-// destabilizers with x at the qubit.
+// stabilizer with x at the qubit; rowsum(i, p) for every other row i with x at the qubit; the
+// pivot's destabilizer q <- old row p (its own rowsum is overwritten); p <- Z_a with the
+// outcome as sign.  A deterministic one reads the stabilizers selected by the destabilizers
+// with x at the qubit.
 //
-// Batching: the block looks at a window of the next pending targets.  A target's "pairs" are
-// the row indices (mod NR, so a destabilizer and its stabilizer count as one) it reads or
-// writes.  Target t of the window runs now iff none of its pairs belongs to an earlier window
-// target (run or deferred).  Such targets touch disjoint rows, and every later target whose
-// inputs an earlier one could change shares a pair with it, so running them at once gives
-// exactly the sequential result; shared words (signs, target columns) are updated with XOR,
-// AND and OR atomics on distinct bits.  A target touching more than kRCap rows runs alone,
-// with the whole block.  Xcol/Zcol of all the layer's targets are kept equal to the current
-// tableau's columns (Zcol is what the end-of-layer reset needs).
+// Split of the work.  Nothing a later target of the layer decides on (its pivot, its row
+// list, its outcome) depends on destabilizer rows, so this kernel runs the stabilizer half
+// only and logs each executed target's old pivot row with its signs; k_replay then applies
+// the destabilizer updates (rowsums and the q <- p moves) in op order, one wave per touched
+// destabilizer, all rows in parallel.  Targets that turn deterministic are marked and
+// reduced after the layer on the final tableau.
+//
+// Batching: the block looks at a window of the next pending targets.  A target's stabilizer
+// rows are its pivot and the other stabilizers with x at its qubit.  Target t of the window
+// runs now iff none of its stabilizer rows belongs to an earlier window target (run or
+// deferred).  Such targets touch disjoint rows, and every later target whose inputs an
+// earlier one could change shares a row with it (the earlier pivot would have x at the later
+// qubit), so running them at once gives exactly the sequential result; shared words (signs,
+// target columns) are updated with XOR, AND and OR atomics on distinct bits.  A target
+// touching more than kRCap rows runs alone, with the whole block.  The stabilizer half of
+// Xcol is kept equal to the current tableau's x columns of the pending targets; the whole of
+// Xcol/Zcol is extracted again after the replay.
 // ------------------------------------------------------------------------------------------
 enum { T_RANDOM = 0, T_DET = 1, T_BIG_RANDOM = 2, T_BIG_DET = 3, T_UNKNOWN = 4, T_DEAD = 5 };
 
@@ -723,8 +739,14 @@ struct ChainCtx {
     uint64_t* Z;
     int K, s;
     const int* tq;
-    int* tm;                 // qubit -> column-upkeep code (see random_epilogue)
-    int zcols;               // 1 when the layer resets, so z columns are needed
+    int* tm;                 // qubit -> pending target whose x column is kept, or -1
+    int* cl;                 // this copy's target classes (-2 marks "deterministic now")
+    int* lp;                 // pivot log: stabilizer index of target k's pivot (-1: not run)
+    uint64_t* lrow;          // old pivot row of target k (RS words)
+    int* lrs;                // its shared sign
+    uint64_t* lrd;           // its per-shot signs (nrdw words, bit b = shot b of the copy)
+    int nrdw;
+    int* ran;                // set to 1 when any random target of the layer runs
     uint64_t seed, first_shot, instr;
     int pos_base;
     uint8_t* obuf;
@@ -789,122 +811,113 @@ __device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_
     }
 }
 
-// The rest of a random measurement, one wave: per-shot signs and outcomes, the columns of the
-// layer's targets touched by rows p or q, the pivot's signs, and the row moves q <- p,
-// p <- Z_a.  xp..zq: the old rows p and q (lane owns column words lane + 64 t).  rows[] is
-// sorted, so runs in one 64-row word are applied as one word mask.
-// Column upkeep follows tmap: k >= 0 keeps both columns of target k, -(k+2) only its z column
-// (needed by the end-of-layer reset), -1 neither (nothing reads them again).
-// When `aff` is given (wide batches), the per-target column work is appended there as
-// {code, flags, batch index j} for the whole block to apply; it is done in-wave otherwise or
-// when the list is full.
+// The rest of a random measurement, one wave: per-shot signs of the rowsum rows and the
+// outcomes, the pending targets' x columns at the rowsum rows and at p, the pivot log entry
+// (old row p with its signs, for the destabilizer replay) and p <- Z_a.  xp, zp: the old row p
+// (lane owns column words lane + 64 t).  rows[] (stabilizer rows) is sorted, so runs in one
+// 64-row word are applied as one word mask.  Column upkeep follows tmap (k >= 0: the pending
+// target whose x column is kept).  When `aff` is given (wide batches), the per-target column
+// work is appended there as {target, 0, batch index j} for the whole block to apply; it is
+// done in-wave otherwise or when the list is full.
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
-                                const uint64_t* zp, const uint64_t* xq, const uint64_t* zq,
-                                const int* rows, int nrows, int lane, int* aff = nullptr,
-                                int* aff_n = nullptr, int j = 0)
+                                const uint64_t* zp, const int* rows, int nrows, int lane,
+                                int* aff = nullptr, int* aff_n = nullptr, int j = 0)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
     const int a = c.tq[k];
     uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
-    uint64_t* gq = c.tb + (size_t)ip * RS;
     const int wq = ip >> 6;
     const uint64_t bq = 1ull << (ip & 63);
+    uint64_t* lrow = c.lrow + (size_t)k * RS;
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t;
+        if (cw < Wc) {
+            lrow[cw] = xp[t];
+            lrow[Wc + cw] = zp[t];
+        }
+    }
     if (lane == 0) {
-        atomicAnd((unsigned long long*)&c.rs[wq], ~(unsigned long long)bq);
-        if (rsp) atomicOr((unsigned long long*)&c.rs[wq], (unsigned long long)bq);
+        c.lrs[k] = rsp;
+        c.lp[k] = ip;
+        *c.ran = 1;
         atomicAnd((unsigned long long*)&c.rs[Wr + wq], ~(unsigned long long)bq);
     }
-    for (int b = lane; b < g.bpc; b += 64) {
-        const int gb = c.s * g.bpc + b;
-        uint64_t* rdb = c.rd + (size_t)gb * NB;
-        const uint64_t rdp = (rdb[Wr + wq] >> (ip & 63)) & 1ull;
-        if (rdp) {
-            uint64_t m = 0;
-            int wc = -1;
-            for (int r = 0; r < nrows; ++r) {
-                const int w = rows[r] >> 6;
-                if (w != wc) {
-                    if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
-                    wc = w;
-                    m = 0;
+    for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+        const int b = b0 + lane;
+        bool rdp = false;
+        if (b < g.bpc) {
+            const int gb = c.s * g.bpc + b;
+            uint64_t* rdb = c.rd + (size_t)gb * NB;
+            rdp = ((rdb[Wr + wq] >> (ip & 63)) & 1ull) != 0;
+            if (rdp) {
+                uint64_t m = 0;
+                int wc = -1;
+                for (int r = 0; r < nrows; ++r) {
+                    const int w = rows[r] >> 6;
+                    if (w != wc) {
+                        if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
+                        wc = w;
+                        m = 0;
+                    }
+                    m |= 1ull << (rows[r] & 63);
                 }
-                m |= 1ull << (rows[r] & 63);
+                if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
             }
-            if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
+            const int out = outcome_bit(c, k, gb);
+            atomicAnd((unsigned long long*)&rdb[Wr + wq], ~(unsigned long long)bq);
+            if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
+            c.obuf[(size_t)gb * K + k] = (uint8_t)out;
         }
-        const int out = outcome_bit(c, k, gb);
-        atomicAnd((unsigned long long*)&rdb[wq], ~(unsigned long long)bq);
-        if (rdp) atomicOr((unsigned long long*)&rdb[wq], (unsigned long long)bq);
-        atomicAnd((unsigned long long*)&rdb[Wr + wq], ~(unsigned long long)bq);
-        if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
-        c.obuf[(size_t)gb * K + k] = (uint8_t)out;
+        const uint64_t m = __ballot(rdp);
+        if (lane == 0) c.lrd[(size_t)k * c.nrdw + (b0 >> 6)] = m;
     }
+    // x columns of pending targets: rows with x at the pivot's qubits flip there; p's x clears
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) {
         const int cw = lane + 64 * t;
         if (cw >= Wc) continue;
-        uint64_t bits = xp[t] | zp[t] | xq[t] | zq[t];
+        uint64_t bits = xp[t];
         while (bits) {
             const int bit = ctz64(bits);
             bits &= bits - 1;
-            const int qb = cw * 64 + bit;
-            const int code = c.tm[qb];
-            if (code == -1) continue;
-            const bool xupd = code >= 0;
-            const int k2 = xupd ? code : -code - 2;
-            const bool xpb = (xp[t] >> bit) & 1ull, zpb = (zp[t] >> bit) & 1ull;
+            const int k2 = c.tm[cw * 64 + bit];
+            if (k2 < 0) continue;
             if (aff) {
                 const int slot = atomicAdd(aff_n, 1);
                 if (slot < kAffCap) {
-                    aff[3 * slot] = code;
-                    aff[3 * slot + 1] = (xpb ? 1 : 0) | (zpb ? 2 : 0) | (qb == a ? 4 : 0);
+                    aff[3 * slot] = k2;
+                    aff[3 * slot + 1] = 0;
                     aff[3 * slot + 2] = j;
                     continue;
                 }
             }
             unsigned long long* X2 = (unsigned long long*)(c.X + k2);
-            unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
-            const bool dx = xupd && xpb, dz = c.zcols && zpb;
-            if (dx || dz) {
-                uint64_t m = 0;
-                int wc = -1;
-                for (int r = 0; r <= nrows; ++r) {
-                    const int w = r < nrows ? rows[r] >> 6 : -2;
-                    if (w != wc) {
-                        if (m) {
-                            if (dx) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
-                            if (dz) atomicXor(&Z2[(size_t)wc * K], (unsigned long long)m);
-                        }
-                        wc = w;
-                        m = 0;
-                    }
-                    if (r < nrows) m |= 1ull << (rows[r] & 63);
+            uint64_t m = 0;
+            int wc = -1;
+            for (int r = 0; r <= nrows; ++r) {
+                const int w = r < nrows ? rows[r] >> 6 : -2;
+                if (w != wc) {
+                    if (m) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
+                    wc = w;
+                    m = 0;
                 }
+                if (r < nrows) m |= 1ull << (rows[r] & 63);
             }
-            const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
-            if (xupd) {
-                if (xpb) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~(unsigned long long)bq);
-                atomicAnd(&X2[op], ~(unsigned long long)bq);
-            }
-            if (c.zcols) {
-                if (zpb) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~(unsigned long long)bq);
-                if (qb == a) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~(unsigned long long)bq);
-            }
+            atomicAnd(&X2[(size_t)(Wr + wq) * K], ~(unsigned long long)bq);
         }
     }
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t) {
         const int cw = lane + 64 * t;
         if (cw < Wc) {
-            gq[cw] = xp[t];
-            gq[Wc + cw] = zp[t];
             gp[cw] = 0ull;
             gp[Wc + cw] = (cw == (a >> 6)) ? (1ull << (a & 63)) : 0ull;
         }
     }
     // this target's x column is never read again
-    if (lane == 0) c.tm[a] = c.zcols ? -(k + 2) : -1;
+    if (lane == 0) c.tm[a] = -1;
     if (lane == 0) {
         count_add(c.counters, 4, 1ull);
         count_add(c.counters, 5, (unsigned long long)nrows);
@@ -927,52 +940,34 @@ __device__ __forceinline__ void load_row_lane(const uint64_t* row, int Wc, int l
 __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
 {
     const Geom& g = c.g;
-    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
+    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
     load_row_lane(c.tb + (size_t)(g.NR + ip) * g.RS, g.Wc, lane, xp, zp);
-    load_row_lane(c.tb + (size_t)ip * g.RS, g.Wc, lane, xq, zq);
     const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
     rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
-    random_epilogue(c, k, ip, rsp, xp, zp, xq, zq, rows, nrows, lane);
+    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane);
 }
 
-// One wave: a target that turned deterministic; rows = destabilizer indices with x at it.
-__device__ void wave_det(const ChainCtx& c, int k, const int* rows, int nrows, int lane)
-{
-    const Geom& g = c.g;
-    const int shared = det_wave_shared(g, c.tb, c.rs, lane, nrows, [&](int r) { return rows[r]; }, c.err);
-    for (int b = lane; b < g.bpc; b += 64) {
-        const int gb = c.s * g.bpc + b;
-        const uint64_t* rdb = c.rd + (size_t)gb * g.NB + g.Wr;
-        int par = 0;
-        for (int r = 0; r < nrows; ++r) par ^= (int)((rdb[rows[r] >> 6] >> (rows[r] & 63)) & 1ull);
-        c.obuf[(size_t)gb * c.K + k] = (uint8_t)(shared ^ par);
-    }
-    if (lane == 0) {
-        count_add(c.counters, 6, 1ull);
-        count_add(c.counters, 3, (unsigned long long)nrows);
-    }
-}
-
-// Whole block: one target with many rows (dense tableaux).  Called by every thread.
+// Whole block: one target with many stabilizer rows (dense tableaux).  Called by every thread.
 __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int nt)
 {
     const Geom& g = c.g;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
-    const int nrdw = (g.bpc + 63) >> 6;
+    const int nrdw = c.nrdw;
     uint64_t* rowp = sm;
-    uint64_t* rowq = rowp + RS;
-    uint64_t* sM = rowq + RS;
-    uint64_t* sC = sM + NB;
-    uint64_t* sRdp = sC + NB;
+    uint64_t* sM = rowp + RS;      // stabilizer words w = 0..Wr-1 (rows NR + 64 w ...)
+    uint64_t* sC = sM + Wr;
+    uint64_t* sRdp = sC + Wr;
     int* nz = (int*)(sRdp + nrdw);
-    __shared__ int s_piv, s_nnz, s_rsp, s_bad, s_G[16];
+    __shared__ int s_piv, s_nnz, s_rsp;
     const int a = c.tq[k];
     uint64_t* X = c.X;
-    uint64_t* Z = c.Z;
     uint64_t* tb = c.tb;
 
-    if (tid == 0) { s_piv = INT_MAX; s_nnz = 0; s_bad = 0; }
+    if (tid == 0) {
+        s_piv = INT_MAX;
+        s_nnz = 0;
+    }
     __syncthreads();
     for (int w = tid; w < Wr; w += nt) {
         const uint64_t v = X[(size_t)(Wr + w) * K + k];
@@ -981,68 +976,19 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
     __syncthreads();
     const int ip = s_piv;
     if (ip == INT_MAX) {
-        // deterministic: thread t owns column word t (Wc <= blockDim.x)
-        uint64_t sx = 0, sz = 0;
-        int G = 0, rsum = 0, nrows = 0;
-        const uint64_t* base = tb + (size_t)g.NR * RS;
-        for (int w = 0; w < Wr; ++w) {
-            uint64_t v = X[(size_t)w * K + k];
-            while (v) {
-                const int i = w * 64 + ctz64(v);
-                v &= v - 1;
-                ++nrows;
-                if (tid < Wc) {
-                    const uint64_t* row = base + (size_t)i * RS;
-                    const uint64_t x1 = row[tid], z1 = row[Wc + tid];
-                    G += gsum(x1, z1, sx, sz);
-                    sx ^= x1;
-                    sz ^= z1;
-                }
-                rsum += (int)((c.rs[Wr + (i >> 6)] >> (i & 63)) & 1ull);
-            }
-        }
-        G = wave_sum(G);
-        const uint64_t xr = wave_or(sx);
-        if (lane == 0) {
-            s_G[wave] = G;
-            if (xr) atomicOr(&s_bad, 1);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int tot = 0;
-            for (int w = 0; w < nwaves; ++w) tot += s_G[w];
-            const int e = (2 * rsum + tot) & 3;
-            if ((e & 1) || s_bad) atomicOr(c.err, 2);
-            s_piv = e >> 1;
-        }
-        __syncthreads();
-        const int shared = s_piv;
-        for (int b = tid; b < g.bpc; b += nt) {
-            const int gb = c.s * g.bpc + b;
-            const uint64_t* rdb = c.rd + (size_t)gb * NB + Wr;
-            int par = 0;
-            for (int w = 0; w < Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
-            c.obuf[(size_t)gb * K + k] = (uint8_t)(shared ^ par);
-        }
-        if (tid == 0) {
-            count_add(c.counters, 6, 1ull);
-            count_add(c.counters, 3, (unsigned long long)nrows);
-        }
+        // deterministic now: reduced after the layer on the final tableau
+        if (tid == 0) c.cl[k] = -2;
         __syncthreads();
         return;
     }
-    // random, phase A: gather
+    // gather the pivot row and the stabilizer rows with x at the qubit
     const int wq = ip >> 6;
     const uint64_t bq = 1ull << (ip & 63);
     uint64_t* gp = tb + (size_t)(g.NR + ip) * RS;
-    uint64_t* gq = tb + (size_t)ip * RS;
-    for (int j = tid; j < RS; j += nt) {
-        rowp[j] = gp[j];
-        rowq[j] = gq[j];
-    }
-    for (int w = tid; w < NB; w += nt) {
-        uint64_t v = X[(size_t)w * K + k];
-        if (w == wq || w == Wr + wq) v &= ~bq;
+    for (int j = tid; j < RS; j += nt) rowp[j] = gp[j];
+    for (int w = tid; w < Wr; w += nt) {
+        uint64_t v = X[(size_t)(Wr + w) * K + k];
+        if (w == wq) v &= ~bq;
         sM[w] = v;
         sC[w] = 0;
         if (v) nz[atomicAdd(&s_nnz, 1)] = w;
@@ -1050,7 +996,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
     for (int t = tid; t < nrdw; t += nt) sRdp[t] = 0;
     if (tid == 0) s_rsp = (int)((c.rs[Wr + wq] >> (ip & 63)) & 1ull);
     __syncthreads();
-    // phase B: per-shot pivot signs; rowsum(i, p), one row per wave at a time
+    // per-shot pivot signs; rowsum(i, p), one row per wave at a time
     for (int b = tid; b < g.bpc; b += nt) {
         const uint64_t bit = (c.rd[(size_t)(c.s * g.bpc + b) * NB + Wr + wq] >> (ip & 63)) & 1ull;
         if (bit) atomicOr((unsigned long long*)&sRdp[b >> 6], 1ull << (b & 63));
@@ -1064,8 +1010,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
             const int bit = ctz64(v);
             v &= v - 1;
             if ((idx++ % nwaves) != wave) continue;
-            const int i = w * 64 + bit;
-            uint64_t* row = tb + (size_t)i * RS;
+            uint64_t* row = tb + (size_t)(g.NR + w * 64 + bit) * RS;
             int G = 0;
             for (int j = lane; j < Wc; j += 64) {
                 const uint64_t xp = rowp[j], zp = rowp[Wc + j];
@@ -1087,68 +1032,52 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
         count_add(c.counters, 5, (unsigned long long)idx);
     }
     __syncthreads();
-    // phase C: signs of the rowsum rows; target columns
+    // signs of the rowsum rows, pending targets' x columns, the pivot log
     const int rsp = s_rsp;
     for (int t = tid; t < nnz; t += nt) {
         const int w = nz[t];
-        c.rs[w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
+        c.rs[Wr + w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
     }
     for (int id = tid; id < nnz * g.bpc; id += nt) {
         const int b = id / nnz, t = id - b * nnz;
         if ((sRdp[b >> 6] >> (b & 63)) & 1ull) {
             const int w = nz[t];
-            c.rd[(size_t)(c.s * g.bpc + b) * NB + w] ^= sM[w];
+            c.rd[(size_t)(c.s * g.bpc + b) * NB + Wr + w] ^= sM[w];
         }
     }
     for (int j = tid; j < Wc; j += nt) {
-        uint64_t bits = rowp[j] | rowp[Wc + j] | rowq[j] | rowq[Wc + j];
+        uint64_t bits = rowp[j];
         while (bits) {
             const int bit = ctz64(bits);
             bits &= bits - 1;
-            const int qb = j * 64 + bit;
-            const int code = c.tm[qb];
-            if (code == -1) continue;
-            const bool xupd = code >= 0;
-            const int k2 = xupd ? code : -code - 2;
-            const uint64_t xpb = (rowp[j] >> bit) & 1ull, zpb = (rowp[Wc + j] >> bit) & 1ull;
+            const int k2 = c.tm[j * 64 + bit];
+            if (k2 < 0) continue;
             uint64_t* X2 = X + k2;
-            uint64_t* Z2 = Z + k2;
-            if (xupd && xpb)
-                for (int t = 0; t < nnz; ++t) X2[(size_t)nz[t] * K] ^= sM[nz[t]];
-            if (c.zcols && zpb)
-                for (int t = 0; t < nnz; ++t) Z2[(size_t)nz[t] * K] ^= sM[nz[t]];
-            const size_t oq = (size_t)wq * K, op = (size_t)(Wr + wq) * K;
-            if (xupd) {
-                X2[oq] = (X2[oq] & ~bq) | (xpb ? bq : 0ull);
-                X2[op] &= ~bq;
-            }
-            if (c.zcols) {
-                Z2[oq] = (Z2[oq] & ~bq) | (zpb ? bq : 0ull);
-                Z2[op] = (Z2[op] & ~bq) | (qb == a ? bq : 0ull);
-            }
+            for (int t = 0; t < nnz; ++t) X2[(size_t)(Wr + nz[t]) * K] ^= sM[nz[t]];
+            X2[(size_t)(Wr + wq) * K] &= ~bq;
         }
     }
-    __syncthreads();
-    // phase D: row moves, the pivot's signs and the outcome
-    const int za = Wc + (a >> 6);
-    for (int j = tid; j < RS; j += nt) {
-        gq[j] = rowp[j];
-        gp[j] = (j == za) ? (1ull << (a & 63)) : 0ull;
-    }
+    uint64_t* lrow = c.lrow + (size_t)k * RS;
+    for (int j = tid; j < RS; j += nt) lrow[j] = rowp[j];
+    for (int t = tid; t < nrdw; t += nt) c.lrd[(size_t)k * nrdw + t] = sRdp[t];
     if (tid == 0) {
-        c.rs[wq] = (c.rs[wq] & ~bq) | (rsp ? bq : 0ull);
-        c.rs[Wr + wq] &= ~bq;
+        c.lrs[k] = rsp;
+        c.lp[k] = ip;
+        *c.ran = 1;
     }
+    __syncthreads();
+    // p <- Z_a with the outcome as its sign
+    const int za = Wc + (a >> 6);
+    for (int j = tid; j < RS; j += nt) gp[j] = (j == za) ? (1ull << (a & 63)) : 0ull;
+    if (tid == 0) c.rs[Wr + wq] &= ~bq;
     for (int b = tid; b < g.bpc; b += nt) {
         const int gb = c.s * g.bpc + b;
         const int out = outcome_bit(c, k, gb);
         uint64_t* rdb = c.rd + (size_t)gb * NB;
-        const uint64_t rdp = (sRdp[b >> 6] >> (b & 63)) & 1ull;
-        rdb[wq] = (rdb[wq] & ~bq) | (rdp ? bq : 0ull);
         rdb[Wr + wq] = (rdb[Wr + wq] & ~bq) | (out ? bq : 0ull);
         c.obuf[(size_t)gb * K + k] = (uint8_t)out;
     }
-    if (tid == 0) c.tm[a] = c.zcols ? -(k + 2) : -1;
+    if (tid == 0) c.tm[a] = -1;
     __syncthreads();
 }
 
@@ -1157,8 +1086,9 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
         int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
         int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
-        int zcols, uint8_t* __restrict__ obuf, int* __restrict__ err,
-        unsigned long long* __restrict__ counters)
+        int* __restrict__ plog_p, uint64_t* __restrict__ plog_row, int* __restrict__ plog_rs,
+        uint64_t* __restrict__ plog_rd, int* __restrict__ ran, uint8_t* __restrict__ obuf,
+        int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t sm[];
     const int s = blockIdx.x;
@@ -1178,7 +1108,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* alist = selpos + kWin;             // slots analysed this round
     int* srows = alist + kWin;              // kWin * kRCap
     uint64_t* wideP = (uint64_t*)((char*)sm + L.wide);   // kWide pivot rows
-    uint64_t* wideQ = wideP + kWide * g.RS;               // and their destabilizers
     uint64_t* wlm = (uint64_t*)((char*)sm + L.words);     // kWide x kRCap word masks
     int* wlw = (int*)(wlm + kWide * kRCap);               // and their word indices
     int* aff = (int*)((char*)sm + L.aff);                 // kAffCap x {code, flags, j}
@@ -1195,7 +1124,13 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.s = s;
     c.tq = tq;
     c.tm = tmap + (size_t)s * g.n;
-    c.zcols = zcols;
+    c.cl = cls + (size_t)s * K;
+    c.nrdw = (g.bpc + 63) >> 6;
+    c.lp = plog_p + (size_t)s * K;
+    c.lrow = plog_row + (size_t)s * K * g.RS;
+    c.lrs = plog_rs + (size_t)s * K;
+    c.lrd = plog_rd + (size_t)s * K * c.nrdw;
+    c.ran = ran;
     c.seed = seed;
     c.first_shot = first_shot;
     c.instr = instr;
@@ -1207,6 +1142,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* tmw = tmap + (size_t)s * g.n;
     int* cl = cls + (size_t)s * K;
 
+    // no target of this layer has run yet (the replay reads the log)
+    for (int k = tid; k < K; k += nt) c.lp[k] = -1;
     // pending list: random-at-start targets in op order (stable compaction)
     int base = 0;
     for (int k0 = 0; k0 < K; k0 += nt) {
@@ -1227,9 +1164,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     }
     const int npend = base;
     if (npend == 0) return;
-    // column upkeep codes: pending random targets need both columns; the others only z, and
-    // only when the layer resets
-    for (int k = tid; k < K; k += nt) tmw[tq[k]] = cl[k] >= 0 ? k : (zcols ? -(k + 2) : -1);
+    // column upkeep: the x columns of pending random targets
+    for (int k = tid; k < K; k += nt) tmw[tq[k]] = cl[k] >= 0 ? k : -1;
     for (int i = tid; i < g.NR; i += nt) owner[i] = INT_MAX;
     const int w0 = min(kWin, npend);
     for (int t = tid; t < w0; t += nt) {
@@ -1285,11 +1221,12 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int pw = pv >> 6;
             const uint64_t pb = 1ull << (pv & 63);
             int cnt = 0;
+            // the other stabilizer rows with x at the qubit
 #pragma unroll
             for (int u = 0; u < kMaxBandsPerLane; ++u) {
                 const int w = lane + 64 * u;
-                uint64_t v = cw[u];
-                if (w == pw || w == g.Wr + pw) v &= ~pb;
+                uint64_t v = w >= g.Wr ? cw[u] : 0ull;
+                if (w == g.Wr + pw) v &= ~pb;
                 const int pc = __popcll(v);
                 int off = cnt + wave_excl_scan(pc, lane);
                 while (v) {
@@ -1404,7 +1341,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 const int j = id / g.RS, w = id - j * g.RS;
                 const int ip = spiv[wpos[selpos[j]]];
                 wideP[j * g.RS + w] = c.tb[(size_t)(g.NR + ip) * g.RS + w];
-                wideQ[j * g.RS + w] = c.tb[(size_t)ip * g.RS + w];
             }
             if (tid < nsel) {
                 const int ip = spiv[wpos[selpos[tid]]];
@@ -1444,44 +1380,27 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             }
             if (wave < nsel) {
                 const int sl = wpos[selpos[wave]];
-                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane], xq[kMaxWordsPerLane], zq[kMaxWordsPerLane];
+                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
                 load_row_lane(wideP + wave * g.RS, g.Wc, lane, xp, zp);
-                load_row_lane(wideQ + wave * g.RS, g.Wc, lane, xq, zq);
-                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, xq, zq, srows + sl * kRCap,
-                                scnt[sl], lane, aff, &s_aff, wave);
+                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, srows + sl * kRCap, scnt[sl], lane,
+                                aff, &s_aff, wave);
             }
             __syncthreads();
-            // column upkeep of the batch: (entry, word) pairs over the block; slot u == 0 also
-            // sets the q / p bits of the entry
+            // column upkeep of the batch: (entry, word) pairs over the block; the extra slot
+            // u == maxw clears the pivot's bit
             const int naff = min(s_aff, kAffCap);
             int maxw = 0;
             for (int j = 0; j < nsel; ++j) maxw = max(maxw, s_wln[j]);
             for (int id = tid; id < naff * (maxw + 1); id += nt) {
                 const int e = id / (maxw + 1), u = id - e * (maxw + 1);
-                const int code = aff[3 * e], fl = aff[3 * e + 1], j = aff[3 * e + 2];
-                const bool xupd = code >= 0;
-                const int k2 = xupd ? code : -code - 2;
+                const int k2 = aff[3 * e], j = aff[3 * e + 2];
                 unsigned long long* X2 = (unsigned long long*)(c.X + k2);
-                unsigned long long* Z2 = (unsigned long long*)(c.Z + k2);
                 if (u < maxw) {
                     if (u >= s_wln[j]) continue;
-                    const int w = wlw[j * kRCap + u];
-                    const unsigned long long m = wlm[j * kRCap + u];
-                    if (xupd && (fl & 1)) atomicXor(&X2[(size_t)w * K], m);
-                    if (c.zcols && (fl & 2)) atomicXor(&Z2[(size_t)w * K], m);
+                    atomicXor(&X2[(size_t)wlw[j * kRCap + u] * K], (unsigned long long)wlm[j * kRCap + u]);
                 } else {
                     const int ip = spiv[wpos[selpos[j]]];
-                    const int wq = ip >> 6;
-                    const unsigned long long bq = 1ull << (ip & 63);
-                    const size_t oq = (size_t)wq * K, op = (size_t)(g.Wr + wq) * K;
-                    if (xupd) {
-                        if (fl & 1) atomicOr(&X2[oq], bq); else atomicAnd(&X2[oq], ~bq);
-                        atomicAnd(&X2[op], ~bq);
-                    }
-                    if (c.zcols) {
-                        if (fl & 2) atomicOr(&Z2[oq], bq); else atomicAnd(&Z2[oq], ~bq);
-                        if (fl & 4) atomicOr(&Z2[op], bq); else atomicAnd(&Z2[op], ~bq);
-                    }
+                    atomicAnd(&X2[(size_t)(g.Wr + (ip >> 6)) * K], ~(1ull << (ip & 63)));
                 }
             }
         } else {
@@ -1510,6 +1429,167 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     }
     if (tid == 0) count_add(counters, 0, (unsigned long long)rounds);
     for (int k = tid; k < K; k += nt) tmw[tq[k]] = -1;
+}
+
+// ------------------------------------------------------------------------------------------
+// Destabilizer replay of a measurement layer: grid (Wr destabilizer bands, S copies), 512
+// threads.  In op order, every target the chain ran did, to each destabilizer D with x at its
+// qubit, rowsum(D, P) with its old pivot row P (sign r_D <- r_D ^ r_P ^ (i-power / 2), the
+// per-shot parts XOR), and replaced its pivot's own destabilizer by P.  The pivots are logged,
+// so each destabilizer is replayed on its own: a wave holds D in registers and walks the
+// targets 64 at a time, testing D's x bit at each target's qubit (and whether D is that
+// target's pivot partner) with one ballot, applying the hits in order and testing again after
+// each.  Only rows with x at some run target at layer start, or partners, can be touched
+// (a row that is never touched keeps its x bits), so only those are walked.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(512)
+k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
+         const uint64_t* __restrict__ Xcol, int K, const int* __restrict__ tq,
+         const int* __restrict__ plog_p, const uint64_t* __restrict__ plog_row,
+         const int* __restrict__ plog_rs, const uint64_t* __restrict__ plog_rd,
+         int* __restrict__ err, unsigned long long* __restrict__ counters)
+{
+    extern __shared__ uint64_t rsm[];
+    const int band = blockIdx.x, s = blockIdx.y;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int Wc = g.Wc, RS = g.RS, NB = g.NB;
+    const int nrdw = (g.bpc + 63) >> 6;
+    uint64_t* acc = rsm;                           // nwaves x nrdw per-shot sign deltas
+    int* rk = (int*)(rsm + (size_t)nwaves * nrdw); // run targets in op order (K entries)
+    __shared__ int s_cnt[16];
+    __shared__ unsigned long long s_cand;
+    const int* lp = plog_p + (size_t)s * K;
+    const uint64_t* X = Xcol + (size_t)s * NB * K + (size_t)band * K;   // this band's destabilizer words
+    uint64_t* tb = tab + (size_t)s * 2 * g.NR * RS;
+    uint64_t* rsc = rs + (size_t)s * NB;
+
+    // run targets, in op order (stable compaction)
+    int R = 0;
+    for (int k0 = 0; k0 < K; k0 += nt) {
+        const int k = k0 + tid;
+        const bool f = k < K && lp[k] >= 0;
+        const uint64_t m = __ballot(f);
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) before += s_cnt[w];
+            total += s_cnt[w];
+        }
+        if (f) rk[R + before + rank] = k;
+        R += total;
+        __syncthreads();
+    }
+    if (R == 0) return;
+    // candidate rows of the band
+    if (tid == 0) s_cand = 0;
+    __syncthreads();
+    uint64_t cand = 0;
+    for (int j = tid; j < R; j += nt) {
+        const int k = rk[j];
+        cand |= X[k];
+        const int p = lp[k];
+        if ((p >> 6) == band) cand |= 1ull << (p & 63);
+    }
+    cand = wave_or(cand);
+    if (lane == 0 && cand) atomicOr(&s_cand, (unsigned long long)cand);
+    __syncthreads();
+    uint64_t* myacc = acc + (size_t)wave * nrdw;
+    uint64_t rem = s_cand;
+    int idx = 0, applied = 0;
+    while (rem) {
+        const int r = ctz64(rem);
+        rem &= rem - 1;
+        if ((idx++ % nwaves) != wave) continue;
+        const int i = band * 64 + r;                   // destabilizer index
+        uint64_t* row = tb + (size_t)i * RS;
+        uint64_t x[kMaxWordsPerLane], z[kMaxWordsPerLane];
+        load_row_lane(row, Wc, lane, x, z);
+        int sh = (int)((rsc[band] >> r) & 1ull);
+        const int sh0 = sh;
+        for (int u = lane; u < nrdw; u += 64) myacc[u] = 0;
+        bool mod = false;
+        for (int j0 = 0; j0 < R; j0 += 64) {
+            const int jj = j0 + lane;
+            int k = 0, a = 0, p = -1;
+            if (jj < R) {
+                k = rk[jj];
+                a = tq[k];
+                p = lp[k];
+            }
+            int from = 0;
+            while (true) {
+                // D's x bit at each target's qubit (word a >> 6 lives in lane (a >> 6) & 63)
+                const int wa = a >> 6, src = wa & 63, slot = wa >> 6;
+                uint64_t v = 0;
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    const uint64_t o = shfl_u64(x[t], src);
+                    if (slot == t) v = o;
+                }
+                const bool hit = jj < R && lane >= from && ((((v >> (a & 63)) & 1ull) != 0) || p == i);
+                const uint64_t hm = __ballot(hit);
+                if (!hm) break;
+                const int l = ctz64(hm);
+                const int kk = __shfl(k, l, 64), pk = __shfl(p, l, 64);
+                const uint64_t* P = plog_row + ((size_t)s * K + kk) * RS;
+                const uint64_t* Pd = plog_rd + ((size_t)s * K + kk) * nrdw;
+                uint64_t px[kMaxWordsPerLane], pz[kMaxWordsPerLane];
+                load_row_lane(P, Wc, lane, px, pz);
+                const int rsp = plog_rs[(size_t)s * K + kk];
+                if (pk == i) {
+                    // the pivot's own destabilizer: replaced by the old pivot row
+#pragma unroll
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        x[t] = px[t];
+                        z[t] = pz[t];
+                    }
+                    sh = rsp;
+                    for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+                        const int b = b0 + lane;
+                        const bool cur = b < g.bpc && ((rd[(size_t)(s * g.bpc + b) * NB + band] >> r) & 1ull);
+                        const uint64_t m = __ballot(cur);
+                        if (lane == 0) myacc[b0 >> 6] = m ^ Pd[b0 >> 6];
+                    }
+                } else {
+                    int G = 0;
+#pragma unroll
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        G += gsum(px[t], pz[t], x[t], z[t]);
+                        x[t] ^= px[t];
+                        z[t] ^= pz[t];
+                    }
+                    G = wave_sum(G);
+                    if (lane == 0 && (G & 1)) atomicOr(err, 8);
+                    sh ^= rsp ^ ((G >> 1) & 1);
+                    for (int u = lane; u < nrdw; u += 64) myacc[u] ^= Pd[u];
+                    ++applied;
+                }
+                mod = true;
+                from = l + 1;
+            }
+        }
+        if (mod) {
+#pragma unroll
+            for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                const int cw = lane + 64 * t;
+                if (cw < Wc) {
+                    row[cw] = x[t];
+                    row[Wc + cw] = z[t];
+                }
+            }
+            if (lane == 0 && sh != sh0) atomicXor((unsigned long long*)&rsc[band], 1ull << r);
+            for (int b = lane; b < g.bpc; b += 64)
+                if ((myacc[b >> 6] >> (b & 63)) & 1ull)
+                    atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + b) * NB + band], 1ull << r);
+        }
+    }
+    if (lane == 0 && idx) {
+        if (applied) count_add(counters, 8, (unsigned long long)applied);
+        if (wave == 0) count_add(counters, 9, (unsigned long long)idx);
+    }
 }
 
 // ------------------------------------------------------------------------------------------

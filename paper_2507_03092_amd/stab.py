@@ -31,7 +31,8 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
-KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack")
+KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack", "replay",
+           "extract")
 
 
 class StabError(RuntimeError):
@@ -214,14 +215,14 @@ class Context:
 
     def kernel_times(self) -> dict:
         """{kernel name: (total ms, launches)} since set_timing(True)."""
-        ms = np.zeros(8, dtype=np.float64)
-        n = np.zeros(8, dtype=np.uint64)
-        _check(lib().stab_get_kernel_times(self.h, _ptr(ms), _ptr(n), 8))
+        ms = np.zeros(len(KERNELS), dtype=np.float64)
+        n = np.zeros(len(KERNELS), dtype=np.uint64)
+        _check(lib().stab_get_kernel_times(self.h, _ptr(ms), _ptr(n), len(KERNELS)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def counters(self) -> np.ndarray:
-        c = np.zeros(8, dtype=np.uint64)
-        _check(lib().stab_get_counters(self.h, _ptr(c), 8))
+        c = np.zeros(10, dtype=np.uint64)
+        _check(lib().stab_get_counters(self.h, _ptr(c), 10))
         return c
 
 
