@@ -182,7 +182,7 @@ int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t
  * Uneven multi-circuit batching.  A batch holds C independent circuits, circuit c on n[c]
  * qubits with its own tableau and its own op stream, and runs all of them in one persistent
  * launch (one workgroup per circuit, largest first).  This is the batched form of the
- * paper's random-circuit benchmark (Sec. 4.3, random Clifford layers with interleaved
+ * paper's wide random-circuit benchmark (Sec. 4.1, random Clifford layers with interleaved
  * measurements) and of the parallel sampling it names as future work (Sec. 6).
  * Semantics per circuit are exactly those of a one-shot context with first_shot = c: RNG key
  * (seed, c), counter (instruction index, target position), the index counting every
