@@ -168,14 +168,16 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
 int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 
 /* Per-kernel device timing with HIP events recorded on the context's stream around every
- * launch.  stab_set_timing(ctx, 1) clears the totals and starts timing; 0 stops it.
+ * launch of the selected kernels.  stab_set_timing(ctx, mask) clears the totals and times the
+ * kernel ids whose bit is set in mask (0 stops timing; (1 << STAB_NUM_KERNELS) - 1 times all;
+ * each timed launch costs two event records on the stream).
  * stab_get_kernel_times writes, for each kernel id, the summed milliseconds and the number of
  * launches since timing started.  Kernel ids: 0 init, 1 noise draw, 2 segment (gates + noise
  * + column extraction), 3 classify, 4 deterministic batch, 5 random chain (stabilizer rows),
  * 6 reset/record, 7 record packing, 8 destabilizer replay, 9 column extraction after a layer
  * with random outcomes.  nkernels <= 10. */
 #define STAB_NUM_KERNELS 10
-int stab_set_timing(stab_ctx *ctx, int32_t enable);
+int stab_set_timing(stab_ctx *ctx, int32_t kernel_mask);
 int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t nkernels);
 
 /* ---------------------------------------------------------------------------------------

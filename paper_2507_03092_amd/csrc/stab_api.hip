@@ -103,6 +103,7 @@ struct stab_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing (stab_set_timing)
     bool timing = false;
+    uint32_t tmask = 0;           // kernel ids timed (bit k = kernel k)
     std::vector<hipEvent_t> evpool;
     std::vector<int> evkind;      // kernel id of each recorded pair
     size_t evused = 0;            // events used in the current execution
@@ -187,10 +188,11 @@ int ensure(DevBuf& b, size_t bytes)
 
 bool valid_kind(uint32_t k) { return k <= STAB_PAULI1; }
 
-// Timing brackets: tstart() before a launch, tstop(kind) after it (no-ops unless timing).
-int tstart(stab_ctx* ctx)
+// Timing brackets: tstart(kind) before a launch, tstop(kind) after it (no-ops unless that
+// kernel id is timed).
+int tstart(stab_ctx* ctx, int kind)
 {
-    if (!ctx->timing) return STAB_OK;
+    if (!((ctx->tmask >> kind) & 1u)) return STAB_OK;
     if (ctx->evused + 2 > ctx->evpool.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
@@ -204,7 +206,7 @@ int tstart(stab_ctx* ctx)
 
 int tstop(stab_ctx* ctx, int kind)
 {
-    if (!ctx->timing) return STAB_OK;
+    if (!((ctx->tmask >> kind) & 1u)) return STAB_OK;
     HIP_CHECK(ctx, hipEventRecord(ctx->evpool[ctx->evused + 1], ctx->stream));
     ctx->evkind.push_back(kind);
     ctx->evused += 2;
@@ -227,7 +229,7 @@ int tcollect(stab_ctx* ctx)
 
 #define TIMED(ctx, kind, launch)                 \
     do {                                         \
-        int rc_ = tstart(ctx);                   \
+        int rc_ = tstart(ctx, kind);             \
         if (rc_) return rc_;                     \
         launch;                                  \
         HIP_CHECK(ctx, hipGetLastError());       \
@@ -808,11 +810,12 @@ int stab_get_counters(stab_ctx* ctx, uint64_t* counters, int32_t ncounters)
     return STAB_OK;
 }
 
-int stab_set_timing(stab_ctx* ctx, int32_t enable)
+int stab_set_timing(stab_ctx* ctx, int32_t kernel_mask)
 {
     if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->timing = enable != 0;
+    ctx->tmask = (uint32_t)kernel_mask & ((1u << kNumKernels) - 1u);
+    ctx->timing = ctx->tmask != 0;
     ctx->evkind.clear();
     ctx->evused = 0;
     for (int i = 0; i < kNumKernels; ++i) {

@@ -210,8 +210,15 @@ class Context:
     def reset(self, seed: int, first_shot: int = 0) -> None:
         _check(lib().stab_reset(self.h, seed, first_shot))
 
-    def set_timing(self, enable: bool) -> None:
-        _check(lib().stab_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable: bool, kernels=None) -> None:
+        """Time every kernel (kernels=None) or the named ones, with HIP events on the stream."""
+        if not enable:
+            mask = 0
+        elif kernels is None:
+            mask = (1 << len(KERNELS)) - 1
+        else:
+            mask = sum(1 << KERNELS.index(k) for k in kernels)
+        _check(lib().stab_set_timing(self.h, mask))
 
     def kernel_times(self) -> dict:
         """{kernel name: (total ms, launches)} since set_timing(True)."""
