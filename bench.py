@@ -33,7 +33,12 @@ DEFAULTS = {  # steps, warmup, shots (circuits) timed in the plain form
     "surface_d25": (10, 1, 10),
     "surface_d71": (3, 1, 2),
     "random_batch": (3, 1, 64),
+    "commute": (20, 2, 0),
 }
+COMMUTE_METRIC = "Pauli-string pairs/sec, group-wise and qubit-wise commutation matrices, bit-exact"
+# int32 VALU operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the fp32 vector
+# figure of 157.3 TFLOP/s counts a fused multiply-add as two and packs two fp32 per lane)
+VALU_INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BATCH_METRIC = "measurements/sec of an uneven multi-circuit batch (random Clifford circuits), bit-exact"
 
 
@@ -109,6 +114,8 @@ def main() -> int:
         return 0
     if args.workload == "random_batch":
         return bench_batch(args)
+    if args.workload == "commute":
+        return bench_commute(args)
     steps0, warm0, plain0 = DEFAULTS[args.workload]
     steps = args.steps if args.steps is not None else steps0
     warmup = args.warmup if args.warmup is not None else warm0
@@ -370,6 +377,85 @@ def bench_batch(args) -> int:
                    "measurements": nmeas, "seed": seed, "form": "batched (one launch)"},
         "circuits_per_s": round(len(circs) / ((t1 - t0) / steps), 2),
         "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+def bench_commute(args) -> int:
+    """Pairwise commutation of 32768 Pauli strings on 256 qubits against themselves."""
+    import numpy as np
+    import torch
+
+    from paper_2507_03092_amd import circuits as Cc
+    from paper_2507_03092_amd import stab
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    steps0, warm0, _ = DEFAULTS["commute"]
+    steps = args.steps if args.steps is not None else steps0
+    warmup = args.warmup if args.warmup is not None else warm0
+    w = Cc.COMMUTE
+    m, n = w["m"], w["n"]
+    x, z = Cc.random_paulis(m, n, w["seed"])
+    P = torch.from_numpy(stab.pack_paulis(x, z).view(np.int64)).cuda()
+    nbw = (m + 63) // 64
+    gc = torch.empty((m, nbw), dtype=torch.int64, device="cuda")
+    qw = torch.empty_like(gc)
+    L = stab.lib()
+    stream = torch.cuda.current_stream()
+    import ctypes as C
+
+    def launch():
+        stab._check(L.stab_commute(C.c_void_p(P.data_ptr()), m, C.c_void_p(P.data_ptr()), m, n,
+                                   C.c_void_p(gc.data_ptr()), C.c_void_p(qw.data_ptr()),
+                                   C.c_void_p(stream.cuda_stream)))
+
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms = e0.elapsed_time(e1) / steps
+    ms_step = (t1 - t0) * 1000.0 / steps
+    pairs = float(m) * m
+    W = (n + 63) // 64
+    ops = pairs * W * 10          # per pair and 64-bit word: 2 AND, 3 XOR/OR on 32-bit halves x 2
+    achieved = ops / (k_ms / 1000.0) / 1e12
+    log(f"commute: {ms_step:.3f} ms/step, kernel {k_ms:.3f} ms, {pairs / (ms_step / 1000.0):.4e} pairs/s")
+    roofline = {"kernel": "commute", "bound": "alu", "achieved": round(achieved, 2),
+                "peak": round(VALU_INT32_PEAK_TOPS, 2), "unit": "Tops/s (int32 VALU)",
+                "frac": round(achieved / VALU_INT32_PEAK_TOPS, 4), "traffic": None,
+                "ops_per_launch": int(ops), "avg_launch_us": round(k_ms * 1000.0, 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import commute as OC
+
+        rows = np.random.default_rng(0).choice(m, size=256, replace=False)
+        c0 = time.perf_counter()
+        wg, wq = OC.commute_matrix(x[rows], z[rows], x, z)
+        c1 = time.perf_counter()
+        g = gc.cpu().numpy().view(np.uint64)[rows]
+        bits = np.unpackbits(g.view(np.uint8).reshape(len(rows), nbw * 8), axis=1, bitorder="little")[:, :m]
+        cpu = {"value": round(len(rows) * m / (c1 - c0), 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": "256 random strings against all 32768 (numpy integer matrix products)",
+               "seconds": round(c1 - c0, 2), "bit_exact_vs_gpu": bool(np.array_equal(bits, wg))}
+        log(f"cpu baseline: {cpu}")
+    line = {
+        "metric": COMMUTE_METRIC, "value": round(pairs / (ms_step / 1000.0), 1), "unit": "pairs/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "commute", "strings": m, "qubits": n, "seed": w["seed"],
+                   "identity_probability": 0.25},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -243,6 +243,20 @@ int stab_batch_get_tableau(stab_batch *batch, int32_t circuit, uint8_t *x, uint8
  * ncounters <= 10. */
 int stab_batch_get_counters(stab_batch *batch, uint64_t *counters, int32_t ncounters);
 
+/* Pairwise commutation of Pauli strings, the grouping check of Sec. 3.2: strings A_i
+ * (i < na) and B_j (j < nb) on n qubits, each stored like a tableau row (ceil(n/64) uint64
+ * x-words, then as many z-words; bit q%64 of word q/64 is qubit q), device memory.  Writes,
+ * packed 64 columns per uint64 word, out[i][j / 64] bit j % 64:
+ *   gc  (group-wise): 1 iff A_i and B_j anticommute, i.e. the parity of
+ *       sum_q (xA_q zB_q + zA_q xB_q) is odd;
+ *   qwc (qubit-wise): 1 iff some qubit's single-qubit factors anticommute.
+ * gc and qwc are device arrays [na][ceil(nb/64)] (either may be NULL, not both); padding bits
+ * of a row's last word are 0.  Asynchronous on hip_stream; nothing is allocated.  Errors:
+ * STAB_EINVAL (NULL or misaligned arrays, n < 1, negative counts), STAB_ERANGE
+ * (na > 65535 * 64), STAB_EDEVICE (launch failure). */
+int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, int32_t n,
+                 uint64_t *gc, uint64_t *qwc, void *hip_stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char *stab_last_error(void);
 

@@ -424,6 +424,22 @@ def random_batch(ncirc: int, n_lo: int, n_hi: int, layers: int, seed: int, meas_
     return ns.astype(np.int32), circs
 
 
+# ---- Pauli strings (the grouping check) ---------------------------------------------------------------
+def random_paulis(m: int, n: int, seed, p_identity: float = 0.25):
+    """m random Pauli strings on n qubits as 0/1 arrays (x, z) [m, n]: each qubit is I with
+    probability p_identity, else X, Y or Z with equal probability."""
+    rng = np.random.default_rng(seed)
+    ident = rng.random((m, n)) < p_identity
+    k = rng.integers(1, 4, size=(m, n))          # 1 X, 2 Z, 3 Y
+    x = ((k & 1) == 1) & ~ident
+    z = ((k & 2) == 2) & ~ident
+    return x.astype(np.uint8), z.astype(np.uint8)
+
+
+# Pauli-string commutation workload: 32768 strings against themselves on 256 qubits
+COMMUTE = dict(m=32768, n=256, seed=6)
+
+
 # ---- the surface-code workloads -----------------------------------------------------------------
 IDLE_T1T2 = twirled_t1t2(1e-6, 100e-6, 100e-6)
 

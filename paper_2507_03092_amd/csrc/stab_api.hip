@@ -6,6 +6,7 @@
 // layer then runs classify -> deterministic batch -> in-order random chain -> reset/record.
 #include "stab_kernels.hip"
 #include "stab_batch.hip"
+#include "stab_commute.hip"
 #include "stab.h"
 
 #include <algorithm>
@@ -851,6 +852,26 @@ int stab_sample(const stab_instr* instrs, int32_t ninstr, const int32_t* targets
 }
 
 }  // extern "C"
+
+// Pauli-string commutation (Sec. 3.2)
+extern "C" int stab_commute(const uint64_t* A, int32_t na, const uint64_t* B, int32_t nb, int32_t n,
+                            uint64_t* gc, uint64_t* qwc, void* hip_stream)
+{
+    if (na < 0 || nb < 0 || n < 1) return fail(STAB_EINVAL, "need n >= 1 and na, nb >= 0");
+    if ((na > 0 && !A) || (nb > 0 && !B)) return fail(STAB_EINVAL, "string array is NULL");
+    if (!gc && !qwc) return fail(STAB_EINVAL, "both outputs are NULL");
+    if (((uintptr_t)A | (uintptr_t)B | (uintptr_t)gc | (uintptr_t)qwc) & 7u)
+        return fail(STAB_EINVAL, "arrays must be 8-byte aligned");
+    if (na == 0 || nb == 0) return STAB_OK;
+    const int W = (n + 63) / 64;
+    const long long rows = ((long long)na + kCommRows - 1) / kCommRows;
+    if (rows > 65535) return fail(STAB_ERANGE, "too many strings in A (at most 65535 * 64)");
+    const dim3 grid((unsigned)((nb + 63) / 64), (unsigned)rows);
+    k_commute<<<grid, kCommThreads, 0, (hipStream_t)hip_stream>>>(A, na, B, nb, W, gc, qwc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(STAB_EDEVICE, std::string("k_commute: ") + hipGetErrorString(e));
+    return STAB_OK;
+}
 
 // multi-circuit batches
 #include "stab_batch_api.hip"

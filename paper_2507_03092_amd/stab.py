@@ -28,7 +28,7 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
            "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
            "stab_batch_execute", "stab_batch_get_tableau", "stab_batch_get_counters",
-           "stab_last_error")
+           "stab_commute", "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
 KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack", "replay",
@@ -82,6 +82,7 @@ def lib():
         "stab_batch_execute": (C.c_int, [P, P, P, C.POINTER(C.c_float)]),
         "stab_batch_get_tableau": (C.c_int, [P, I32, P, P, P]),
         "stab_batch_get_counters": (C.c_int, [P, P, I32]),
+        "stab_commute": (C.c_int, [P, I32, P, I32, I32, P, P, P]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -342,3 +343,42 @@ class Batch:
         c = np.zeros(8, dtype=np.uint64)
         _check(lib().stab_batch_get_counters(self.h, _ptr(c), 8))
         return c
+
+
+# ------------------------------------------------------------------ Pauli commutation ---
+def pack_paulis(x: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """[m, n] 0/1 x and z bits -> [m, 2*ceil(n/64)] uint64 rows (x words, then z words)."""
+    m, n = x.shape
+    W = (n + 63) // 64
+
+    def words(bits):
+        pad = np.zeros((m, W * 64), dtype=np.uint8)
+        pad[:, :n] = bits
+        return np.packbits(pad.reshape(m, W, 64), axis=2, bitorder="little").reshape(m, W, 8).view("<u8")[:, :, 0]
+
+    return np.ascontiguousarray(np.concatenate([words(x), words(z)], axis=1))
+
+
+def commute(A, B, n: int, device: str = "cuda:0", qubitwise: bool = True):
+    """stab_commute on packed strings (numpy [na, 2W] or device tensors).  Returns
+    (gc, qwc) as [na, nb] uint8 numpy arrays (qwc None unless qubitwise)."""
+    import torch
+
+    dev = torch.device(device)
+    tA = A if isinstance(A, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(A).view(np.int64)).to(dev)
+    tB = B if isinstance(B, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(B).view(np.int64)).to(dev)
+    na, nb = tA.shape[0], tB.shape[0]
+    nbw = (nb + 63) // 64
+    gc = torch.empty((na, nbw), dtype=torch.int64, device=dev)
+    qw = torch.empty((na, nbw), dtype=torch.int64, device=dev) if qubitwise else None
+    stream = torch.cuda.current_stream(dev)
+    _check(lib().stab_commute(C.c_void_p(tA.data_ptr()), na, C.c_void_p(tB.data_ptr()), nb, n,
+                              C.c_void_p(gc.data_ptr()), C.c_void_p(qw.data_ptr() if qw is not None else 0),
+                              C.c_void_p(stream.cuda_stream)))
+
+    def unpack(t):
+        h = t.cpu().numpy().view(np.uint64)
+        bits = np.unpackbits(h.view(np.uint8).reshape(na, nbw * 8), axis=1, bitorder="little")
+        return bits[:, :nb]
+
+    return unpack(gc), (unpack(qw) if qw is not None else None)

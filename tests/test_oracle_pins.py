@@ -531,3 +531,62 @@ def test_draw_format_exact():
         for q in range(3):
             want.append(_numpy_block(seed, shot, 6, q)[0] >> 63)
         assert list(rec[shot]) == want, shot
+
+
+# ------------------------------------------------------------ Pauli-string commutation ---
+from oracle import commute as OC
+
+_PAULI_XZ = {"I": (0, 0), "X": (1, 0), "Z": (0, 1), "Y": (1, 1)}
+_PAULI_M = {"I": np.eye(2, dtype=complex), "X": np.array([[0, 1], [1, 0]], dtype=complex),
+            "Y": np.array([[0, -1j], [1j, 0]]), "Z": np.array([[1, 0], [0, -1]], dtype=complex)}
+
+
+def _string_matrix(s):
+    m = np.eye(1, dtype=complex)
+    for c in s:
+        m = np.kron(m, _PAULI_M[c])
+    return m
+
+
+def _xz(strings):
+    x = np.array([[_PAULI_XZ[c][0] for c in s] for s in strings], dtype=np.uint8)
+    z = np.array([[_PAULI_XZ[c][1] for c in s] for s in strings], dtype=np.uint8)
+    return x, z
+
+
+def test_commute_single_qubit_table_against_matrices():
+    labels = "IXYZ"
+    x, z = _xz(list(labels))
+    gc, qwc = OC.commute_matrix(x, z, x, z)
+    for i, a in enumerate(labels):
+        for j, b in enumerate(labels):
+            A, B = _PAULI_M[a], _PAULI_M[b]
+            anti = np.allclose(A @ B, -(B @ A))
+            assert gc[i, j] == anti and qwc[i, j] == anti, (a, b)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_commute_random_strings_against_matrices(n):
+    rng = np.random.default_rng(40 + n)
+    strings = ["".join(rng.choice(list("IXYZ"), size=n)) for _ in range(24)]
+    x, z = _xz(strings)
+    gc, qwc = OC.commute_matrix(x, z, x, z)
+    for i, a in enumerate(strings):
+        for j, b in enumerate(strings):
+            A, B = _string_matrix(a), _string_matrix(b)
+            anti = np.allclose(A @ B, -(B @ A))
+            assert (not anti) == np.allclose(A @ B, B @ A) or anti
+            assert gc[i, j] == anti, (a, b)
+            q_anti = any(np.allclose(_PAULI_M[p] @ _PAULI_M[q], -(_PAULI_M[q] @ _PAULI_M[p])) for p, q in zip(a, b))
+            assert qwc[i, j] == q_anti, (a, b)
+
+
+def test_commute_group_parity_is_sum_of_qubit_terms():
+    rng = np.random.default_rng(5)
+    ax, az = rng.integers(0, 2, (30, 70), dtype=np.uint8), rng.integers(0, 2, (30, 70), dtype=np.uint8)
+    bx, bz = rng.integers(0, 2, (20, 70), dtype=np.uint8), rng.integers(0, 2, (20, 70), dtype=np.uint8)
+    gc, qwc = OC.commute_matrix(ax, az, bx, bz)
+    for i in range(30):
+        for j in range(20):
+            per_q = (ax[i] & bz[j]) ^ (az[i] & bx[j])
+            assert gc[i, j] == per_q.sum() % 2 and qwc[i, j] == (per_q.sum() > 0)
