@@ -31,6 +31,11 @@
  *     PAULI1: X iff u0 < t0, else Y iff u0 < t1, else Z iff u0 < t2 (cumulative thresholds)
  *     M/MR/R: a random outcome is u0 >> 63; MR and R then apply X if the outcome is 1 and R
  *             records nothing.  Records hold 1 bit per M/MR target (1 = eigenvalue -1).
+ *     T1T2:   exact relaxation (T1) then dephasing (T2) for T1 >= T2 (Sec. 4.2), as a mixture
+ *             of stochastic Clifford+reset operations: reset iff u0 < t0 (a Z measurement
+ *             whose random outcome is u1 >> 63, then X if it is 1; nothing recorded), else Z
+ *             iff u0 < t1, else nothing.  It changes x|z shot by shot, so only the batch calls
+ *             (one tableau per circuit) accept it; stab_compile/stab_run reject it.
  */
 #ifndef LIBSTAB_ABI_H_
 #define LIBSTAB_ABI_H_
@@ -52,7 +57,8 @@ extern "C" {
 /* instruction kinds */
 enum {
     STAB_TICK = 0, STAB_H = 1, STAB_S = 2, STAB_X = 3, STAB_Y = 4, STAB_Z = 5, STAB_CX = 6,
-    STAB_M = 7, STAB_MR = 8, STAB_R = 9, STAB_DEP1 = 10, STAB_DEP2 = 11, STAB_PAULI1 = 12
+    STAB_M = 7, STAB_MR = 8, STAB_R = 9, STAB_DEP1 = 10, STAB_DEP2 = 11, STAB_PAULI1 = 12,
+    STAB_T1T2 = 13
 };
 
 /* One instruction (32 bytes, no implicit padding). */

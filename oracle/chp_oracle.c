@@ -26,6 +26,8 @@
  *   - X, Y, Z gates ("derived" Cliffords, Sec. 2.4): sign flips r ^= z, r ^= x^z, r ^= x.
  *   - Initial state |0...0>: destabilizer i = +X_i, stabilizer i = +Z_i.
  *   - Reset (MR, R): measure, then apply X when the outcome is 1.
+ *   - T1T2 (exact relaxation + dephasing, Sec. 4.2): per target, reset with probability t0
+ *     (its measurement outcome, if random, is u1 >> 63), else Z with probability t1 - t0.
  *   - rowsum with an odd phase sum leaves r_h unchanged (it only happens for the destabilizer
  *     of the pivot, which is overwritten right after).
  *
@@ -39,7 +41,7 @@
 
 /* instruction kinds of the op-stream format */
 enum { K_TICK = 0, K_H, K_S, K_X, K_Y, K_Z, K_CX, K_M, K_MR, K_R, K_DEP1, K_DEP2, K_PAULI1,
-       K_COUNT };
+       K_T1T2, K_COUNT };
 
 typedef struct {
     uint32_t kind;
@@ -318,6 +320,19 @@ long oracle_exec(otab *t, const oinstr *ins, long ninstr, const int32_t *targets
                 if (u[0] < ins[k].t0) pauli(t, tg[q], 1);
                 else if (u[0] < ins[k].t1) pauli(t, tg[q], 2);
                 else if (u[0] < ins[k].t2) pauli(t, tg[q], 3);
+            }
+            break;
+        case K_T1T2:
+            /* relaxation then dephasing as a mixture: reset with probability t0, Z with
+             * probability t1 - t0, else nothing; the reset's measurement draws u1 >> 63 */
+            for (uint32_t q = 0; q < nt; ++q) {
+                draw(seed, shot, idx, q, u);
+                if (u[0] < ins[k].t0) {
+                    int was_random = 0;
+                    if (measure(t, tg[q], (int)(u[1] >> 63), &was_random)) pauli(t, tg[q], 1);
+                } else if (u[0] < ins[k].t1) {
+                    pauli(t, tg[q], 3);
+                }
             }
             break;
         default: return -1;

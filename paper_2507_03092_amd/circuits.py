@@ -39,11 +39,11 @@ from fractions import Fraction
 import numpy as np
 
 # ---- instruction kinds (numeric codes are part of the input format) -----------------------------
-TICK, H, S, X, Y, Z, CX, M, MR, R, DEP1, DEP2, PAULI1 = range(13)
+TICK, H, S, X, Y, Z, CX, M, MR, R, DEP1, DEP2, PAULI1, T1T2 = range(14)
 
 KIND_NAMES = {
     TICK: "TICK", H: "H", S: "S", X: "X", Y: "Y", Z: "Z", CX: "CX", M: "M", MR: "MR", R: "R",
-    DEP1: "DEP1", DEP2: "DEP2", PAULI1: "PAULI1",
+    DEP1: "DEP1", DEP2: "DEP2", PAULI1: "PAULI1", T1T2: "T1T2",
 }
 NAME_TO_KIND = {v: k for k, v in KIND_NAMES.items()}
 TWO_QUBIT = (CX, DEP2)
@@ -80,7 +80,7 @@ def twirled_t1t2(t: float, t1: float, t2: float) -> tuple[float, float, float]:
     """Pauli-twirl of amplitude damping (T1) followed by pure dephasing (T2) for a duration t.
 
     The paper builds stochastic Pauli channels by Pauli twirling (Stabilizer Noise Modeling,
-    Sec. 2.6).  For relaxation with gamma = 1 - exp(-t/T1) and total coherence decay
+    Sec. 2.7).  For relaxation with gamma = 1 - exp(-t/T1) and total coherence decay
     exp(-t/T2), the twirled channel is p_x = p_y = gamma/4 and p_z = (1 - exp(-t/T2))/2 - gamma/4.
     (Requires T2 <= 2 T1.)
     """
@@ -90,6 +90,30 @@ def twirled_t1t2(t: float, t1: float, t2: float) -> tuple[float, float, float]:
     if pz < 0:
         raise ValueError("T2 > 2*T1 is unphysical")
     return px, py, pz
+
+
+def t1t2_composite(t: float, t1: float, t2: float) -> tuple[float, float]:
+    """Relaxation for a duration t (amplitude damping, gamma = 1 - exp(-t/T1)) followed by
+    dephasing to a total coherence decay exp(-t/T2), written as a mixture of stochastic
+    Clifford+reset operations (Sec. 2.7 and Sec. 4.2: the composite distribution, positive
+    when T1 >= T2).  A qubit channel is fixed by its action on the Bloch vector; this one maps
+    (x, y, z) to (e2 x, e2 y, e1 z + 1 - e1) with e1 = exp(-t/T1), e2 = exp(-t/T2).  The
+    mixture a*I + b*Z(.)Z + c*Reset maps it to ((a - b) x, (a - b) y, (a + b) z + c), so
+    c = 1 - e1 and b = (e1 - e2) / 2.  Returns (c, b): the reset and Z probabilities."""
+    if t < 0 or t1 <= 0 or t2 <= 0:
+        raise ValueError("need t >= 0 and positive T1, T2")
+    if t2 > t1:
+        raise ValueError("T2 > T1: the composite distribution has a negative weight")
+    e1, e2 = math.exp(-t / t1), math.exp(-t / t2)
+    return 1.0 - e1, (e1 - e2) / 2.0
+
+
+def t1t2_thresholds(t: float, t1: float, t2: float) -> tuple[int, int, int]:
+    """Cumulative thresholds (reset, reset + Z, 0) of a T1T2 instruction, exact in rational
+    arithmetic from the float64 probabilities."""
+    c, b = t1t2_composite(t, t1, t2)
+    fc, fb = Fraction(c), Fraction(b)
+    return (min(math.floor(fc * TWO64), TWO64 - 1), min(math.floor((fc + fb) * TWO64), TWO64 - 1), 0)
 
 
 @dataclass
@@ -127,6 +151,9 @@ class Circuit:
 
     def pauli1(self, px, py, pz, targets):
         self.append(PAULI1, targets, pauli1_thresholds(px, py, pz))
+
+    def t1t2(self, t, t1, t2, targets):
+        self.append(T1T2, targets, t1t2_thresholds(t, t1, t2))
 
     def tick(self):
         self.append(TICK, ())
@@ -221,14 +248,15 @@ def rotated_layout(d: int) -> SurfaceLayout:
                          logical_z=[dq(0, c) for c in range(d)])
 
 
-def surface_code_memory(d: int, rounds: int, p: float = 0.0,
-                        idle: tuple | None = None) -> tuple[Circuit, SurfaceLayout]:
+def surface_code_memory(d: int, rounds: int, p: float = 0.0, idle: tuple | None = None,
+                        idle_exact: tuple | None = None) -> tuple[Circuit, SurfaceLayout]:
     """Rotated surface-code Z-memory experiment (the paper's QEC workload, Sec. 4.1).
 
     Each round: H on X ancillas, four CNOT layers, H on X ancillas, MR on every ancilla.
     With p > 0, DEP1(p) follows each H and DEP2(p) each CNOT pair.  With ``idle=(px,py,pz)``
-    a PAULI1 channel acts on every qubit after each of the seven layers of a round.  After the
-    last round every data qubit is measured (M).  All qubits start in |0>.
+    a PAULI1 channel acts on every qubit after each of the seven layers of a round; with
+    ``idle_exact=(t, T1, T2)`` the exact relaxation/dephasing composite (T1T2) acts there
+    instead.  After the last round every data qubit is measured (M).  All qubits start in |0>.
     """
     lay = rotated_layout(d)
     c = Circuit(n=lay.n)
@@ -237,6 +265,8 @@ def surface_code_memory(d: int, rounds: int, p: float = 0.0,
     def idle_noise():
         if idle is not None:
             c.pauli1(*idle, allq)
+        if idle_exact is not None:
+            c.t1t2(*idle_exact, allq)
 
     for _ in range(rounds):
         c.tick()
@@ -451,6 +481,9 @@ WORKLOADS = {
     "surface_d3": dict(d=3, rounds=3, p=1e-3, idle=None, seed=1, shots=1000),
     "surface_d25": dict(d=25, rounds=25, p=1e-3, idle=None, seed=2, shots=100),
     "surface_d71": dict(d=71, rounds=71, p=1e-3, idle=IDLE_T1T2, seed=3, shots=10),
+    # the exact (not twirled) T1/T2 idle: per-shot tableaux, run as a batch of shots
+    "surface_d25_t1t2": dict(d=25, rounds=25, p=1e-3, idle=None, idle_exact=(1e-6, 100e-6, 100e-6),
+                             seed=7, shots=100),
 }
 
 
@@ -458,5 +491,5 @@ def workload(name: str, rounds: int | None = None):
     """(circuit, layout, seed, shots) for a named surface-code workload."""
     w = WORKLOADS[name]
     r = w["rounds"] if rounds is None else rounds
-    circ, lay = surface_code_memory(w["d"], r, w["p"], w["idle"])
+    circ, lay = surface_code_memory(w["d"], r, w["p"], w["idle"], w.get("idle_exact"))
     return circ, lay, w["seed"], w["shots"]

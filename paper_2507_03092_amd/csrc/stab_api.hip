@@ -187,7 +187,7 @@ int ensure(DevBuf& b, size_t bytes)
         }                                                                                      \
     } while (0)
 
-bool valid_kind(uint32_t k) { return k <= STAB_PAULI1; }
+bool valid_kind(uint32_t k) { return k <= STAB_T1T2; }
 
 // Timing brackets: tstart(kind) before a launch, tstop(kind) after it (no-ops unless that
 // kernel id is timed).
@@ -292,6 +292,9 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
         switch (kind) {
         case STAB_TICK:
             break;
+        case STAB_T1T2:
+            return fail(STAB_EINVAL, "instruction " + std::to_string(k) +
+                                         ": T1T2 resets change x|z shot by shot; run it with stab_batch_*");
         case STAB_H: case STAB_S: case STAB_X: case STAB_Y: case STAB_Z:
             for (uint32_t q = 0; q < nt; ++q) {
                 if (stamp[t[q]] == layer_id) close_layer();

@@ -32,10 +32,11 @@ struct BatchCirc {
 
 struct BatchMeas {
     uint64_t instr;  // instruction index in the circuit's stream
-    int kind;        // STAB_KIND_M / MR / R
+    uint64_t t0, t1; // T1T2 thresholds: reset iff u0 < t0, else Z iff u0 < t1
+    int kind;        // M, MR, R or T1T2
     int tq;          // first target in the measurement target array
     int K;           // targets
-    int rec;         // record index (within the circuit) of the first target; -1 for R
+    int rec;         // record index (within the circuit) of the first target; -1 if none
 };
 
 // Program step: (0, first gate, gates, modifies x|z) gate layer on disjoint qubits;
@@ -69,7 +70,7 @@ __host__ __device__ inline int batch_lds_words(int Wc)
     return seg > meas ? seg : meas;
 }
 
-constexpr int kMK = 7, kMRK = 8, kRK = 9;   // measurement kinds (include/stab.h enum)
+constexpr int kMK = 7, kMRK = 8, kRK = 9, kT1T2K = 13;   // kinds (include/stab.h enum)
 
 // -------------------------------------------------------------------------------- gates ---
 __device__ __forceinline__ void batch_gate(uint64_t* T, int RSP, int Wc, uint2 gt, uint64_t& racc)
@@ -292,7 +293,7 @@ __device__ void batch_rowsum(const BatchCirc& C, uint64_t* __restrict__ tab, con
         px[t] = (j < Wc) ? prow[j] : 0;
         pz[t] = (j < Wc) ? prow[Wc + j] : 0;
     }
-    constexpr int kBatchRows = (NW == 1) ? 6 : 2;   // rows in flight per wave (register budget)
+    constexpr int kBatchRows = (NW == 1) ? 4 : 2;   // rows in flight per wave (register budget)
     for (int base = wave * kBatchRows; base < nlist; base += kBatchWaves * kBatchRows) {
         const int cnt = min(kBatchRows, nlist - base);
         uint64_t x[kBatchRows][NW], z[kBatchRows][NW];
@@ -433,7 +434,10 @@ __device__ int batch_det(const BatchCirc& C, const uint64_t* __restrict__ tab, c
     return s_res[0];
 }
 
-// One M / MR / R instruction of circuit ci, target by target.
+// One M / MR / R instruction of circuit ci, target by target.  A T1T2 instruction runs here
+// too: per target a Philox draw picks reset (u0 < t0: a measurement whose random outcome is
+// u1 >> 63, then X if it is 1), Z (u0 < t1: sign flip of every row with x at the qubit) or
+// nothing.
 template <int NW>
 __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, const BatchMeas& md,
                               uint64_t* lds)
@@ -454,66 +458,113 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
     int nrand = 0, ndet = 0;
     long long nrows = 0, bytes = 0;
     const long long row_b = (long long)RS * 8, col_b = (long long)2 * NR * 8;
-    for (int t = 0; t < md.K; ++t) {
-        const int a = A.meas_tg[md.tq + t];
-        batch_column(tab, RS, NB, a >> 6, a & 63, colx, false);
-        __syncthreads();
-        // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
-        if (tid < 64) {
-            int first = 0x7fffffff;
-            for (int w = Wc + tid; w < NB; w += 64)
-                if (colx[w]) first = min(first, 64 * w + ctz64(colx[w]));
-            first = wave_min(first);
-            if (tid == 0) s_int[0] = first;
-        }
-        __syncthreads();
-        const int p = s_int[0];
-        int outcome;
-        if (p != 0x7fffffff) {
-            uint64_t u0, u1;
-            philox(A.ibase[ci] + md.instr, (uint64_t)t, A.seed, (uint64_t)ci, u0, u1);
-            outcome = (int)(u0 >> 63);
-            for (int j = tid; j < RS; j += kBatchThreads) prow[j] = tab[(size_t)p * RS + j];
-            const int rp = (int)((sg[p >> 6] >> (p & 63)) & 1ull);
-            const int nl = batch_list(colx, 0, NB, p, p - NR, list, s_int + 1);
-            __syncthreads();    // prow staged
-            batch_rowsum<NW>(C, tab, prow, rp, list, nl, sg, A.err);
-            __syncthreads();
-            // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
-            const int d = p - NR;
-            for (int j = tid; j < RS; j += kBatchThreads) {
-                tab[(size_t)d * RS + j] = prow[j];
-                tab[(size_t)p * RS + j] = (j == Wc + (a >> 6)) ? (1ull << (a & 63)) : 0ull;
+    const bool stoch = md.kind == kT1T2K;
+    uint64_t* s_ev = (uint64_t*)(s_int + 24);           // a T1T2 chunk: reset, Z, outcome masks
+    for (int c0 = 0; c0 < md.K; c0 += 64) {
+        const int cn = min(64, md.K - c0);
+        const uint64_t live = cn == 64 ? ~0ull : ((1ull << cn) - 1ull);
+        uint64_t ev_meas = live, ev_z = 0, ev_bits = 0;  // M / MR / R: every target, in order
+        if (stoch) {
+            // draws do not depend on the tableau: one wave draws 64 targets at once
+            if (tid < 64) {
+                int act = 0, rb = 0;
+                if (tid < cn) {
+                    uint64_t u0, u1;
+                    philox(A.ibase[ci] + md.instr, (uint64_t)(c0 + tid), A.seed, (uint64_t)ci, u0, u1);
+                    act = u0 < md.t0 ? 1 : (u0 < md.t1 ? 2 : 0);
+                    rb = (int)(u1 >> 63);
+                }
+                const uint64_t m1 = __ballot(act == 1), m2 = __ballot(act == 2), mb = __ballot(rb);
+                if (tid == 0) {
+                    s_ev[0] = m1;
+                    s_ev[1] = m2;
+                    s_ev[2] = mb;
+                }
             }
-            if (tid == 0) {
-                uint64_t wd = sg[d >> 6];
-                wd = (wd & ~(1ull << (d & 63))) | ((uint64_t)rp << (d & 63));
-                sg[d >> 6] = wd;
-                uint64_t wp = sg[p >> 6];
-                wp = (wp & ~(1ull << (p & 63))) | ((uint64_t)outcome << (p & 63));
-                sg[p >> 6] = wp;
-            }
-            ++nrand;
-            nrows += nl;
-            // column, pivot row, rowsum read+write, two row writes
-            bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
-        } else {
-            const int nl = batch_list(colx, 0, Wc, -1, -1, list, s_int + 1);
-            outcome = batch_det<NW>(C, tab, list, nl, sg, part, s_int + 10, A.err);
-            ++ndet;
-            nrows += nl;
-            bytes += col_b + nl * row_b;
-        }
-        __syncthreads();
-        if (md.kind != kRK && tid == 0 && outcome) {
-            const long long bit = C.rec_bit_off + md.rec + t;
-            atomicOr(&A.rec[bit >> 5], 1u << (bit & 31));
-        }
-        if (md.kind != kMK && outcome) {
-            // reset: apply X_a, i.e. flip the sign of every row with z at a
-            batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, sg, true);
             __syncthreads();
-            bytes += col_b;
+            ev_meas = s_ev[0];
+            ev_z = s_ev[1];
+            ev_bits = s_ev[2];
+            __syncthreads();
+        }
+        uint64_t evm = (ev_meas | ev_z) & live;
+        while (evm) {
+            const int bit = ctz64(evm);
+            evm &= evm - 1;
+            const int t = c0 + bit;
+            const int a = A.meas_tg[md.tq + t];
+            if ((ev_z >> bit) & 1ull) {
+                // Z on the qubit: flip the sign of every row with x at it
+                batch_column(tab, RS, NB, a >> 6, a & 63, sg, true);
+                __syncthreads();
+                bytes += col_b;
+                continue;
+            }
+            int rand_bit;
+            if (stoch) {
+                rand_bit = (int)((ev_bits >> bit) & 1ull);
+            } else {
+                uint64_t u0, u1;
+                philox(A.ibase[ci] + md.instr, (uint64_t)t, A.seed, (uint64_t)ci, u0, u1);
+                rand_bit = (int)(u0 >> 63);
+            }
+            batch_column(tab, RS, NB, a >> 6, a & 63, colx, false);
+            __syncthreads();
+            // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
+            if (tid < 64) {
+                int first = 0x7fffffff;
+                for (int w = Wc + tid; w < NB; w += 64)
+                    if (colx[w]) first = min(first, 64 * w + ctz64(colx[w]));
+                first = wave_min(first);
+                if (tid == 0) s_int[0] = first;
+            }
+            __syncthreads();
+            const int p = s_int[0];
+            int outcome;
+            if (p != 0x7fffffff) {
+                outcome = rand_bit;
+                for (int j = tid; j < RS; j += kBatchThreads) prow[j] = tab[(size_t)p * RS + j];
+                const int rp = (int)((sg[p >> 6] >> (p & 63)) & 1ull);
+                const int nl = batch_list(colx, 0, NB, p, p - NR, list, s_int + 1);
+                __syncthreads();    // prow staged
+                batch_rowsum<NW>(C, tab, prow, rp, list, nl, sg, A.err);
+                __syncthreads();
+                // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
+                const int d = p - NR;
+                for (int j = tid; j < RS; j += kBatchThreads) {
+                    tab[(size_t)d * RS + j] = prow[j];
+                    tab[(size_t)p * RS + j] = (j == Wc + (a >> 6)) ? (1ull << (a & 63)) : 0ull;
+                }
+                if (tid == 0) {
+                    uint64_t wd = sg[d >> 6];
+                    wd = (wd & ~(1ull << (d & 63))) | ((uint64_t)rp << (d & 63));
+                    sg[d >> 6] = wd;
+                    uint64_t wp = sg[p >> 6];
+                    wp = (wp & ~(1ull << (p & 63))) | ((uint64_t)outcome << (p & 63));
+                    sg[p >> 6] = wp;
+                }
+                ++nrand;
+                nrows += nl;
+                // column, pivot row, rowsum read+write, two row writes
+                bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
+            } else {
+                const int nl = batch_list(colx, 0, Wc, -1, -1, list, s_int + 1);
+                outcome = batch_det<NW>(C, tab, list, nl, sg, part, s_int + 10, A.err);
+                ++ndet;
+                nrows += nl;
+                bytes += col_b + nl * row_b;
+            }
+            __syncthreads();
+            if (md.rec >= 0 && tid == 0 && outcome) {
+                const long long rb = C.rec_bit_off + md.rec + t;
+                atomicOr(&A.rec[rb >> 5], 1u << (rb & 31));
+            }
+            if (md.kind != kMK && outcome) {
+                // reset: apply X_a, i.e. flip the sign of every row with z at a
+                batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, sg, true);
+                __syncthreads();
+                bytes += col_b;
+            }
         }
     }
     for (int w = tid; w < NB; w += kBatchThreads) rs[w] = sg[w];

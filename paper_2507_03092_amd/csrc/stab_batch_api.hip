@@ -156,16 +156,21 @@ int batch_compile_one(int c, int n, const stab_instr* ins, int64_t ninstr, const
             steps.push_back(make_int4(1, (int)noise.size(), 0, 0));
             noise.push_back(d);
         } break;
-        case STAB_M: case STAB_MR: case STAB_R: {
+        case STAB_M: case STAB_MR: case STAB_R: case STAB_T1T2: {
             close_layer();
             if (nt == 0) break;
+            if (kind == STAB_T1T2 && ins[k].t1 < ins[k].t0)
+                return fail(STAB_EINVAL, where + std::to_string(k) + ": T1T2 thresholds must not decrease");
             BatchMeas m{};
             m.instr = (uint64_t)k;
+            m.t0 = ins[k].t0;
+            m.t1 = ins[k].t1;
             m.kind = (int)kind;
             m.tq = (int)meas_tg.size();
             m.K = (int)nt;
-            m.rec = (kind == STAB_R) ? -1 : (int)nrec;
-            if (kind != STAB_R) nrec += nt;
+            const bool recorded = kind == STAB_M || kind == STAB_MR;
+            m.rec = recorded ? (int)nrec : -1;
+            if (recorded) nrec += nt;
             meas_tg.insert(meas_tg.end(), t, t + nt);
             steps.push_back(make_int4(2, (int)meas.size(), 0, 0));
             meas.push_back(m);

@@ -227,3 +227,11 @@ def test_random_batch_generator_shapes():
     # deterministic in the seed
     ns2, circs2 = Cc.random_batch(6, 64, 300, layers=20, seed=4)
     assert np.array_equal(ns, ns2) and all(np.array_equal(a.targets, b.targets) for a, b in zip(circs, circs2))
+
+
+def test_single_context_rejects_t1t2(L):
+    c = Cc.Circuit(n=3)
+    c.t1t2(1e-6, 100e-6, 100e-6, [0, 1])
+    with pytest.raises(stab.StabError) as e:
+        stab.plan_describe(c)
+    assert e.value.code == stab.EINVAL and "batch" in str(e.value)

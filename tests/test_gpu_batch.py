@@ -155,3 +155,39 @@ def test_batch_random_workload_full_size_sampled(stab):
     allbits = np.concatenate(got)
     assert 0.45 < allbits.mean() < 0.55
     b.close()
+
+
+def _concat(n, parts):
+    ins = np.concatenate([p.arrays()[0] for p in parts])
+    tg = np.concatenate([p.arrays()[1] for p in parts]).astype(np.int32)
+    return Cc.PackedCircuit(n, ins, tg)
+
+
+def test_batch_exact_t1t2_random_circuits(stab):
+    # random Clifford layers with measurements, and a strong exact T1/T2 channel on every qubit
+    # between blocks (reset ~18 %, Z ~6 % per qubit)
+    circs = []
+    for n in (3, 40, 65, 130):
+        parts = []
+        for blk in range(4):
+            parts.append(Cc.random_layered_clifford(n, 6, (9, n, blk), meas_every=3, meas_frac=0.2))
+            t = Cc.Circuit(n=n)
+            t.t1t2(20e-6, 100e-6, 60e-6, list(range(n)))
+            parts.append(t)
+        m = Cc.Circuit(n=n)
+        m.append(Cc.M, list(range(n)))
+        parts.append(m)
+        circs.append(_concat(n, parts))
+    _check_batch(stab, circs, seed=12)
+
+
+def test_batch_surface_code_exact_t1t2_shots(stab):
+    # shots of one circuit as a batch: circuit c is shot c of the oracle's run
+    circ, lay = Cc.surface_code_memory(5, 3, 2e-3, None, (5e-6, 100e-6, 80e-6))
+    shots = 24
+    want = O.run(circ, shots, 31)
+    b = stab.Batch(np.full(shots, circ.n, dtype=np.int32), seed=31)
+    got = b.execute(b.compile([circ] * shots))
+    for s in range(shots):
+        assert np.array_equal(got[s], want[s]), f"shot {s}"
+    b.close()

@@ -590,3 +590,83 @@ def test_commute_group_parity_is_sum_of_qubit_terms():
         for j in range(20):
             per_q = (ax[i] & bz[j]) ^ (az[i] & bx[j])
             assert gc[i, j] == per_q.sum() % 2 and qwc[i, j] == (per_q.sum() > 0)
+
+
+# ------------------------------------------------------- exact T1/T2 composite (T1T2) ---
+def _ptm(channel):
+    """Pauli transfer matrix R[i][j] = Tr(P_i channel(P_j)) / 2 of a single-qubit channel."""
+    P = [_PAULI_M[c] for c in "IXYZ"]
+    return np.array([[np.trace(P[i] @ channel(P[j])).real / 2 for j in range(4)] for i in range(4)])
+
+
+@pytest.mark.parametrize("t,T1,T2", [(1e-6, 100e-6, 100e-6), (20e-6, 100e-6, 60e-6), (50e-6, 80e-6, 30e-6)])
+def test_t1t2_composite_equals_relaxation_then_dephasing(t, T1, T2):
+    gamma = 1 - np.exp(-t / T1)
+    # amplitude damping, then pure dephasing taking the coherence from e^{-t/2T1} to e^{-t/T2}
+    k_ad = [np.array([[1, 0], [0, np.sqrt(1 - gamma)]]), np.array([[0, np.sqrt(gamma)], [0, 0]])]
+    keep = np.exp(-t / T2) / np.exp(-t / (2 * T1))
+    lam = 1 - keep ** 2
+    k_pd = [np.array([[1, 0], [0, np.sqrt(1 - lam)]]), np.array([[0, 0], [0, np.sqrt(lam)]])]
+
+    def physical(rho):
+        r = sum(k @ rho @ k.conj().T for k in k_ad)
+        return sum(k @ r @ k.conj().T for k in k_pd)
+
+    c, b = Cc.t1t2_composite(t, T1, T2)
+    a = 1 - b - c
+    Zm = _PAULI_M["Z"]
+    ket0 = np.array([[1, 0], [0, 0]], dtype=complex)
+
+    def mixture(rho):
+        return a * rho + b * (Zm @ rho @ Zm) + c * ket0 * np.trace(rho)
+
+    assert min(a, b, c) >= 0
+    assert np.allclose(_ptm(physical), _ptm(mixture), atol=1e-12)
+
+
+def test_t1t2_negative_weight_is_rejected():
+    with pytest.raises(ValueError):
+        Cc.t1t2_composite(1e-6, 50e-6, 80e-6)
+
+
+def test_t1t2_thresholds_are_cumulative_and_exact():
+    t0, t1, t2 = Cc.t1t2_thresholds(20e-6, 100e-6, 60e-6)
+    c, b = Cc.t1t2_composite(20e-6, 100e-6, 60e-6)
+    assert t2 == 0 and t0 <= t1
+    assert abs(t0 / 2 ** 64 - c) < 1e-15 and abs((t1 - t0) / 2 ** 64 - b) < 1e-15
+
+
+def test_t1t2_oracle_extremes():
+    c = Cc.Circuit(n=2)
+    c.gate(Cc.H, [0])
+    c.append(Cc.T1T2, [0], (2 ** 64 - 1, 2 ** 64 - 1, 0))     # always reset
+    c.append(Cc.M, [0])
+    assert not O.run(c, 64, seed=1).any()
+    c = Cc.Circuit(n=2)
+    c.gate(Cc.H, [0])
+    c.append(Cc.T1T2, [0], (0, 2 ** 64 - 1, 0))               # always Z: |+> -> |->
+    c.gate(Cc.H, [0])
+    c.append(Cc.M, [0])
+    assert O.run(c, 64, seed=1).all()
+
+
+def test_t1t2_oracle_statistics():
+    t, T1, T2 = 30e-6, 100e-6, 50e-6
+    shots = 4000
+    # |1>: relaxation to |0> with probability 1 - e^{-t/T1}
+    c = Cc.Circuit(n=1)
+    c.gate(Cc.X, [0])
+    c.t1t2(t, T1, T2, [0])
+    c.append(Cc.M, [0])
+    p1 = O.run(c, shots, seed=3).mean()
+    e1 = np.exp(-t / T1)
+    assert abs(p1 - e1) < 4 * np.sqrt(e1 * (1 - e1) / shots)
+    # |+>: <X> decays as e^{-t/T2}, so P(+) = (1 + e^{-t/T2}) / 2
+    c = Cc.Circuit(n=1)
+    c.gate(Cc.H, [0])
+    c.t1t2(t, T1, T2, [0])
+    c.gate(Cc.H, [0])
+    c.append(Cc.M, [0])
+    p0 = 1 - O.run(c, shots, seed=4).mean()
+    want = (1 + np.exp(-t / T2)) / 2
+    assert abs(p0 - want) < 4 * np.sqrt(want * (1 - want) / shots)
