@@ -35,6 +35,7 @@ DEFAULTS = {  # steps, warmup, shots (circuits) timed in the plain form
     "random_batch": (3, 1, 64),
     "commute": (20, 2, 0),
     "surface_d25_t1t2": (3, 1, 0),
+    "serve": (1, 0, 0),
 }
 COMMUTE_METRIC = "Pauli-string pairs/sec, group-wise and qubit-wise commutation matrices, bit-exact"
 # int32 VALU operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the fp32 vector
@@ -86,6 +87,9 @@ def main() -> int:
     ap.add_argument("--plain-shots", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="arrival window of the serving workload (the full recipe is 60 s)")
+    ap.add_argument("--serve-rate", type=float, default=None, help="arrival rate of the serving workload (1/s)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte "
                          "counters of a profiler against a known size) and exit")
@@ -119,6 +123,8 @@ def main() -> int:
         return bench_commute(args)
     if args.workload == "surface_d25_t1t2":
         return bench_exact_noise(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     steps0, warm0, plain0 = DEFAULTS[args.workload]
     steps = args.steps if args.steps is not None else steps0
     warmup = args.warmup if args.warmup is not None else warm0
@@ -381,6 +387,100 @@ def bench_batch(args) -> int:
         "circuits_per_s": round(len(circs) / ((t1 - t0) / steps), 2),
         "plain": plain,
         "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Continuous batching: Poisson arrivals of surface-code memory requests (d ~ U{3,...,31},
+    d rounds, shots ~ U{1..100}) served by one server; latency from arrival to records."""
+    import numpy as np
+    import torch
+
+    from paper_2507_03092_amd import circuits as Cc
+    from paper_2507_03092_amd import stab
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    w = dict(Cc.SERVING)
+    rate = args.serve_rate if args.serve_rate is not None else w["rate"]
+    times, ds, shots, seeds = Cc.serving_requests(rate, args.serve_seconds, w["seed"], w["d_lo"], w["d_hi"],
+                                                  w["shots_hi"])
+    m = len(times)
+    circs = {int(d): Cc.surface_code_memory(int(d), int(d), w["p"])[0] for d in np.unique(ds)}
+    arena = 32 << 30
+    srv = stab.Server(arena)
+    prog = {d: srv.program(c) for d, c in circs.items()}
+    log(f"serve: {m} requests over {args.serve_seconds} s at {rate}/s, arena {arena >> 30} GiB")
+    torch.cuda.synchronize()
+    arrival, lat, done_work = {}, [], 0
+    i = 0
+    steps = 0
+    resident_sum = 0
+    t0 = time.perf_counter()
+    drain_limit = args.serve_seconds + 120.0
+    while True:
+        now = time.perf_counter() - t0
+        while i < m and times[i] <= now:
+            d = int(ds[i])
+            rid = srv.submit(prog[d], int(shots[i]), int(seeds[i]))
+            arrival[rid] = (times[i], d, int(shots[i]))
+            i += 1
+        st = srv.stats()
+        if st["queued"] == 0 and st["resident_requests"] == 0:
+            if i == m:
+                break
+            time.sleep(max(0.0, min(times[i] - now, 0.001)))
+            continue
+        if now > drain_limit:
+            break
+        srv.step()
+        steps += 1
+        resident_sum += st["resident_shots"]
+        tdone = time.perf_counter() - t0
+        for rid in srv.poll():
+            ta, d, sh = arrival.pop(rid)
+            lat.append(tdone - ta)
+            done_work += sh * d
+            srv.result(rid, sh)
+    wall = time.perf_counter() - t0
+    unfinished = len(arrival) + (m - i)
+    lat_ms = np.array(lat) * 1000.0
+    p50 = float(np.percentile(lat_ms, 50)) if len(lat) else None
+    p99 = float(np.percentile(lat_ms, 99)) if len(lat) else None
+    log(f"served {len(lat)} of {m} in {wall:.1f} s, p50 {p50:.1f} ms, p99 {p99:.1f} ms, {steps} steps")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import oracle as O
+
+        pick = np.random.default_rng(3).choice(m, size=min(16, m), replace=False)
+        c0 = time.perf_counter()
+        with ThreadPoolExecutor(4) as ex:
+            list(ex.map(lambda j: O.run(circs[int(ds[j])], int(shots[j]), int(seeds[j])), pick))
+        c1 = time.perf_counter()
+        work = int(sum(int(shots[j]) * int(ds[j]) for j in pick))
+        cpu = {"value": round(work / (c1 - c0), 1), "unit": "shot-rounds/s", "cores": O.threads(), "kind": "oracle",
+               "sample": f"{len(pick)} requests drawn from the stream (4 at a time, each over its shots)",
+               "seconds": round(c1 - c0, 2)}
+        log(f"cpu baseline: {cpu}")
+    srv.close()
+    line = {
+        "metric": "continuous-batching sampling service: shot-rounds/sec served, p50/p99 request latency",
+        "value": round(done_work / wall, 1), "unit": "shot-rounds/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(wall * 1000.0 / max(steps, 1), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serve", "rate_per_s": rate, "seconds": args.serve_seconds, "requests": m,
+                   "d_range": [w["d_lo"], w["d_hi"]], "shots_max": w["shots_hi"], "p": w["p"], "seed": w["seed"],
+                   "arena_bytes": arena},
+        "latency_ms": {"p50": p50, "p99": p99, "max": float(lat_ms.max()) if len(lat) else None},
+        "served": len(lat), "unfinished": unfinished, "wall_s": round(wall, 2),
+        "mean_resident_shots": round(resident_sum / max(steps, 1), 1),
+        "roofline": None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

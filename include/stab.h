@@ -263,6 +263,60 @@ int stab_batch_get_counters(stab_batch *batch, uint64_t *counters, int32_t ncoun
 int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, int32_t n,
                  uint64_t *gc, uint64_t *qwc, void *hip_stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Continuous batching of sampling requests.  A server owns a caller-provided device arena;
+ * a request (a registered op stream, a shot count, a seed) is admitted in arrival order once
+ * its bytes (stab_server_request_bytes: one tableau per shot plus its records) fit in the
+ * free arena, and each stab_server_step() runs ONE launch that advances every shot of every
+ * resident request by one measurement step (a round of a memory experiment): rounds of all
+ * resident requests share the launch, new requests join at the next step, finished ones
+ * leave and free their bytes.  Shot s of a request with seed k draws with RNG key (k, s) and
+ * counts its own instructions from 0, so its records equal those of a full-mode context
+ * (stab_create(..., seed = k, first_shot = 0)) running the stream alone, whatever else is
+ * resident.  A server is not thread-safe; it allocates nothing per request.
+ * ------------------------------------------------------------------------------------- */
+typedef struct stab_server stab_server;
+
+/* Arena bytes a request of `shots` shots on n qubits with nrec records per shot occupies. */
+int stab_server_request_bytes(int32_t n, int32_t shots, int64_t nrec, uint64_t *bytes_out);
+
+/* Create a server on dev_buf (buf_bytes, 256-byte aligned, owned by the caller until
+ * stab_server_destroy; its size is the admission cap). */
+int stab_server_create(void *dev_buf, uint64_t buf_bytes, void *hip_stream, stab_server **out);
+void stab_server_destroy(stab_server *server);
+
+/* Validate, compile and upload an op stream for n qubits (<= 8192); *prog_out receives its
+ * id.  Errors as stab_batch_compile. */
+int stab_server_program(stab_server *server, const stab_instr *instrs, int32_t ninstr,
+                        const int32_t *targets, int64_t ntargets, int32_t n, int32_t *prog_out);
+
+/* Records per shot of a registered program, or -1. */
+int64_t stab_server_program_records(const stab_server *server, int32_t prog);
+
+/* Queue a request (host only; nothing runs until stab_server_step).  *id_out receives its id.
+ * Errors: STAB_EINVAL (unknown program, shots < 1), STAB_ERANGE (larger than the arena). */
+int stab_server_submit(stab_server *server, int32_t prog, int32_t shots, uint64_t seed,
+                       int64_t *id_out);
+
+/* Admit what fits, run one launch over every resident shot, retire finished requests
+ * (their records are copied to host memory and their bytes freed).  Synchronous.
+ * *finished_out (may be NULL) receives the number of requests that finished. */
+int stab_server_step(stab_server *server, int32_t *finished_out);
+
+/* Ids of finished requests not returned before, oldest first; returns how many it wrote. */
+int stab_server_poll(stab_server *server, int64_t *ids, int32_t max_ids);
+
+/* Records per shot of a finished request (-1 if unknown or already taken). */
+int64_t stab_server_records(const stab_server *server, int64_t id);
+
+/* Copy a finished request's records (shot s's bits LSB-first from byte s * ceil(M/8)) and
+ * forget the request. */
+int stab_server_result(stab_server *server, int64_t id, uint8_t *out_bits);
+
+/* [0] queued requests, [1] resident requests, [2] resident unfinished shots, [3] arena bytes
+ * in use, [4] arena bytes, [5] steps run, [6] requests finished.  nout <= 7. */
+int stab_server_stats(const stab_server *server, int64_t *out, int32_t nout);
+
 /* Message of the last error on this thread ("" if none). */
 const char *stab_last_error(void);
 

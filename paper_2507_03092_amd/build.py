@@ -8,7 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "stab_api.hip")
 DEPS = [os.path.join(PKG, "csrc", f) for f in ("stab_api.hip", "stab_kernels.hip", "stab_device.h",
-                                                    "stab_batch.hip", "stab_batch_api.hip", "stab_commute.hip")]
+                                                    "stab_batch.hip", "stab_batch_api.hip", "stab_commute.hip",
+                                                    "stab_server_api.hip")]
 HDR = os.path.join(ROOT, "include", "stab.h")
 LIB = os.path.join(PKG, "libstab.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -470,6 +470,28 @@ def random_paulis(m: int, n: int, seed, p_identity: float = 0.25):
 COMMUTE = dict(m=32768, n=256, seed=6)
 
 
+# ---- serving workload (continuous batching) -------------------------------------------------------
+# Poisson arrivals of memory-experiment requests: d ~ U{3, 5, ..., 31}, d rounds, DEP1/DEP2
+# p = 1e-3, shots ~ U{1..100}
+SERVING = dict(rate=200.0, duration=60.0, d_lo=3, d_hi=31, shots_hi=100, p=1e-3, seed=5)
+
+
+def serving_requests(rate: float, duration: float, seed: int, d_lo: int = 3, d_hi: int = 31,
+                     shots_hi: int = 100):
+    """Arrival times (seconds), distances, shot counts and request seeds of a Poisson stream."""
+    rng = np.random.default_rng(seed)
+    times = []
+    t = rng.exponential(1.0 / rate)
+    while t < duration:
+        times.append(t)
+        t += rng.exponential(1.0 / rate)
+    m = len(times)
+    ds = rng.choice(np.arange(d_lo, d_hi + 1, 2), size=m)
+    shots = rng.integers(1, shots_hi + 1, size=m)
+    seeds = rng.integers(0, 2 ** 62, size=m)
+    return np.array(times), ds.astype(np.int32), shots.astype(np.int32), seeds.astype(np.uint64)
+
+
 # ---- the surface-code workloads -----------------------------------------------------------------
 IDLE_T1T2 = twirled_t1t2(1e-6, 100e-6, 100e-6)
 

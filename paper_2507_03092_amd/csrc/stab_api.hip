@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -878,3 +880,6 @@ extern "C" int stab_commute(const uint64_t* A, int32_t na, const uint64_t* B, in
 
 // multi-circuit batches
 #include "stab_batch_api.hip"
+
+// continuous batching of sampling requests
+#include "stab_server_api.hip"

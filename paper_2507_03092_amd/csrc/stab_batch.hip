@@ -54,6 +54,8 @@ struct BatchArgs {
     uint64_t* rs;
     uint32_t* rec;              // packed record bits, zeroed before the launch
     const uint64_t* ibase;      // per circuit: instructions it executed before this launch
+    const ulonglong2* keys;     // per circuit RNG key, or NULL for (seed, circuit index)
+    int meas_quota;             // stop a circuit after this many measurement steps (0: run all)
     uint64_t seed;
     int* err;
     unsigned long long* counters;
@@ -71,6 +73,15 @@ __host__ __device__ inline int batch_lds_words(int Wc)
 }
 
 constexpr int kMK = 7, kMRK = 8, kRK = 9, kT1T2K = 13;   // kinds (include/stab.h enum)
+
+__device__ __forceinline__ ulonglong2 batch_key(const BatchArgs& A, int ci)
+{
+    if (A.keys) return A.keys[ci];
+    ulonglong2 k;
+    k.x = A.seed;
+    k.y = (uint64_t)ci;
+    return k;
+}
 
 // -------------------------------------------------------------------------------- gates ---
 __device__ __forceinline__ void batch_gate(uint64_t* T, int RSP, int Wc, uint2 gt, uint64_t& racc)
@@ -107,11 +118,11 @@ __device__ __forceinline__ void batch_gate(uint64_t* T, int RSP, int Wc, uint2 g
 // Noise unit u of descriptor d for circuit ci: XOR into racc the sign flips of the staged
 // band's rows (the rows the drawn Pauli anticommutes with).
 __device__ __forceinline__ void batch_noise(const uint64_t* T, int RSP, int Wc, const NoiseDesc& d,
-                                            const int* __restrict__ ntg, int u, uint64_t seed, int ci,
+                                            const int* __restrict__ ntg, int u, ulonglong2 key,
                                             uint64_t ibase, uint64_t& racc)
 {
     uint64_t u0, u1;
-    philox(ibase + d.instr, (uint64_t)u, seed, (uint64_t)ci, u0, u1);
+    philox(ibase + d.instr, (uint64_t)u, key.x, key.y, u0, u1);
     int q[2], P[2], ne = 0;
     if (d.kind == STAB_KIND_DEP1) {
         if (u0 < d.t0) { q[ne] = ntg[d.toff + u]; P[ne++] = 1 + (int)__umul64hi(u1, 3ull); }
@@ -143,6 +154,7 @@ __device__ void batch_segment(const BatchArgs& A, const BatchCirc& C, int ci, in
     uint64_t* red = lds + 64 * RSP;
     uint64_t* tab = A.tab + C.tab_off;
     uint64_t* rs = A.rs + C.rs_off;
+    const ulonglong2 key = batch_key(A, ci);
     int wb = 0;
     for (int k = st; k < en; ++k) wb |= (A.steps[k].x == 0) ? A.steps[k].w : 0;
     const int npairs = 32 * RS;
@@ -182,7 +194,7 @@ __device__ void batch_segment(const BatchArgs& A, const BatchCirc& C, int ci, in
             } else {
                 const NoiseDesc d = A.noise[s.y];
                 for (int u = tid; u < d.units; u += nt)
-                    batch_noise(T, RSP, Wc, d, A.noise_tg, u, A.seed, ci, A.ibase[ci], racc);
+                    batch_noise(T, RSP, Wc, d, A.noise_tg, u, key, A.ibase[ci], racc);
             }
             __syncthreads();
         }
@@ -453,6 +465,7 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
     int* s_int = (int*)(part + 2 * kBatchWaves * RS);   // 32 ints: pivot, list and det scratch
     uint16_t* list = (uint16_t*)(s_int + 32);          // 2 * NR entries
 
+    const ulonglong2 key = batch_key(A, ci);
     for (int w = tid; w < NB; w += kBatchThreads) sg[w] = rs[w];
     __syncthreads();
     int nrand = 0, ndet = 0;
@@ -470,7 +483,7 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
                 int act = 0, rb = 0;
                 if (tid < cn) {
                     uint64_t u0, u1;
-                    philox(A.ibase[ci] + md.instr, (uint64_t)(c0 + tid), A.seed, (uint64_t)ci, u0, u1);
+                    philox(A.ibase[ci] + md.instr, (uint64_t)(c0 + tid), key.x, key.y, u0, u1);
                     act = u0 < md.t0 ? 1 : (u0 < md.t1 ? 2 : 0);
                     rb = (int)(u1 >> 63);
                 }
@@ -505,7 +518,7 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
                 rand_bit = (int)((ev_bits >> bit) & 1ull);
             } else {
                 uint64_t u0, u1;
-                philox(A.ibase[ci] + md.instr, (uint64_t)t, A.seed, (uint64_t)ci, u0, u1);
+                philox(A.ibase[ci] + md.instr, (uint64_t)t, key.x, key.y, u0, u1);
                 rand_bit = (int)(u0 >> 63);
             }
             batch_column(tab, RS, NB, a >> 6, a & 63, colx, false);
@@ -586,12 +599,14 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
     const int ci = A.order[blockIdx.x];
     const BatchCirc C = A.circ[ci];
     const int end = C.step_begin + C.step_count;
-    for (int st = C.step_begin; st < end;) {
+    int done = 0;
+    for (int st = C.step_begin; st < end && (A.meas_quota == 0 || done < A.meas_quota);) {
         const int4 s0 = A.steps[st];
         if (s0.x == 2) {
             const BatchMeas md = A.meas[s0.y];
             batch_measure<NW>(A, C, ci, md, lds);
             ++st;
+            ++done;
             continue;
         }
         int en = st + 1;

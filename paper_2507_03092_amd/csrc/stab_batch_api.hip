@@ -422,6 +422,8 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
     A.rs = b->rs;
     A.rec = (uint32_t*)b->rec.p;
     A.ibase = b->d_ibase;
+    A.keys = nullptr;
+    A.meas_quota = 0;
     A.seed = b->seed;
     A.err = b->d_err;
     A.counters = b->d_counters;

@@ -28,7 +28,10 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
            "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
            "stab_batch_execute", "stab_batch_get_tableau", "stab_batch_get_counters",
-           "stab_commute", "stab_last_error")
+           "stab_commute", "stab_server_request_bytes", "stab_server_create", "stab_server_destroy",
+           "stab_server_program", "stab_server_program_records", "stab_server_submit", "stab_server_step",
+           "stab_server_poll", "stab_server_records", "stab_server_result", "stab_server_stats",
+           "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
 KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack", "replay",
@@ -83,6 +86,17 @@ def lib():
         "stab_batch_get_tableau": (C.c_int, [P, I32, P, P, P]),
         "stab_batch_get_counters": (C.c_int, [P, P, I32]),
         "stab_commute": (C.c_int, [P, I32, P, I32, I32, P, P, P]),
+        "stab_server_request_bytes": (C.c_int, [I32, I32, I64, C.POINTER(U64)]),
+        "stab_server_create": (C.c_int, [P, U64, P, C.POINTER(P)]),
+        "stab_server_destroy": (None, [P]),
+        "stab_server_program": (C.c_int, [P, P, I32, P, I64, I32, C.POINTER(I32)]),
+        "stab_server_program_records": (I64, [P, I32]),
+        "stab_server_submit": (C.c_int, [P, I32, I32, U64, C.POINTER(I64)]),
+        "stab_server_step": (C.c_int, [P, C.POINTER(I32)]),
+        "stab_server_poll": (C.c_int, [P, P, I32]),
+        "stab_server_records": (I64, [P, I64]),
+        "stab_server_result": (C.c_int, [P, I64, P]),
+        "stab_server_stats": (C.c_int, [P, P, I32]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -382,3 +396,81 @@ def commute(A, B, n: int, device: str = "cuda:0", qubitwise: bool = True):
         return bits[:, :nb]
 
     return unpack(gc), (unpack(qw) if qw is not None else None)
+
+
+# ------------------------------------------------------------ continuous-batching server ---
+SERVER_STATS = ("queued", "resident_requests", "resident_shots", "bytes_in_use", "arena_bytes", "steps",
+                "finished")
+
+
+def server_request_bytes(n: int, shots: int, nrec: int) -> int:
+    out = C.c_uint64(0)
+    _check(lib().stab_server_request_bytes(n, shots, nrec, C.byref(out)))
+    return out.value
+
+
+class Server:
+    """stab_server_*: requests admitted by arena bytes, one round of every resident shot per
+    step."""
+
+    def __init__(self, arena_bytes: int, device: str = "cuda:0"):
+        import torch
+
+        self.device = torch.device(device)
+        self.buf = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p(None)
+        _check(lib().stab_server_create(C.c_void_p(self.buf.data_ptr()), arena_bytes,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.nrec = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().stab_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown
+            pass
+
+    def program(self, circ) -> int:
+        instr, tg = circ.arrays()
+        tg = np.ascontiguousarray(tg, dtype=np.int32)
+        pid = C.c_int32(0)
+        _check(lib().stab_server_program(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg), circ.n,
+                                         C.byref(pid)))
+        return pid.value
+
+    def submit(self, prog: int, shots: int, seed: int) -> int:
+        rid = C.c_int64(0)
+        _check(lib().stab_server_submit(self.h, prog, shots, seed, C.byref(rid)))
+        return rid.value
+
+    def step(self) -> int:
+        nf = C.c_int32(0)
+        _check(lib().stab_server_step(self.h, C.byref(nf)))
+        return nf.value
+
+    def poll(self, max_ids: int = 4096) -> list:
+        ids = np.zeros(max_ids, dtype=np.int64)
+        k = lib().stab_server_poll(self.h, _ptr(ids), max_ids)
+        if k < 0:
+            _check(k)
+        return [int(v) for v in ids[:k]]
+
+    def result(self, rid: int, shots: int) -> np.ndarray:
+        nrec = lib().stab_server_records(self.h, rid)
+        if nrec < 0:
+            raise StabError(EINVAL, f"request {rid} is not finished")
+        nbytes = (nrec + 7) // 8
+        out = np.zeros(max(shots * nbytes, 1), dtype=np.uint8)
+        _check(lib().stab_server_result(self.h, rid, _ptr(out)))
+        return unpack_record(out[: shots * nbytes], shots, nrec)
+
+    def stats(self) -> dict:
+        v = np.zeros(len(SERVER_STATS), dtype=np.int64)
+        _check(lib().stab_server_stats(self.h, _ptr(v), len(SERVER_STATS)))
+        return dict(zip(SERVER_STATS, (int(x) for x in v)))
