@@ -266,7 +266,7 @@ int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, i
 /* ---------------------------------------------------------------------------------------
  * Continuous batching of sampling requests.  A server owns a caller-provided device arena;
  * a request (a registered op stream, a shot count, a seed) is admitted in arrival order once
- * its bytes (stab_server_request_bytes: one tableau per shot plus its records) fit in the
+ * its bytes (stab_server_request_bytes: per shot a tableau and scratch, plus records) fit in the
  * free arena, and each stab_server_step() runs ONE launch that advances every shot of every
  * resident request by one measurement step (a round of a memory experiment): rounds of all
  * resident requests share the launch, new requests join at the next step, finished ones
@@ -277,8 +277,6 @@ int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, i
  * ------------------------------------------------------------------------------------- */
 typedef struct stab_server stab_server;
 
-/* Arena bytes a request of `shots` shots on n qubits with nrec records per shot occupies. */
-int stab_server_request_bytes(int32_t n, int32_t shots, int64_t nrec, uint64_t *bytes_out);
 
 /* Create a server on dev_buf (buf_bytes, 256-byte aligned, owned by the caller until
  * stab_server_destroy; its size is the admission cap). */
@@ -292,6 +290,11 @@ int stab_server_program(stab_server *server, const stab_instr *instrs, int32_t n
 
 /* Records per shot of a registered program, or -1. */
 int64_t stab_server_program_records(const stab_server *server, int32_t prog);
+
+/* Arena bytes a request of `shots` shots of a registered program occupies (per shot its
+ * tableau, signs and the columns of its largest measurement instruction; then the records). */
+int stab_server_request_bytes(const stab_server *server, int32_t prog, int32_t shots,
+                              uint64_t *bytes_out);
 
 /* Queue a request (host only; nothing runs until stab_server_step).  *id_out receives its id.
  * Errors: STAB_EINVAL (unknown program, shots < 1), STAB_ERANGE (larger than the arena). */

@@ -28,6 +28,8 @@ struct BatchCirc {
     long long rs_off;           // first word of the sign vector [2*Wc]
     int step_begin, step_count; // program steps
     long long rec_bit_off;      // bit offset of the circuit's first record in the output
+    long long col_off;          // first word of the column scratch [2][NB][col_k] (if col_k > 0)
+    int col_k;                  // targets the scratch holds per band (0: no scratch)
 };
 
 struct BatchMeas {
@@ -37,6 +39,7 @@ struct BatchMeas {
     int tq;          // first target in the measurement target array
     int K;           // targets
     int rec;         // record index (within the circuit) of the first target; -1 if none
+    int fast;        // M/MR/R on distinct qubits: its columns can be extracted in the band pass
 };
 
 // Program step: (0, first gate, gates, modifies x|z) gate layer on disjoint qubits;
@@ -53,6 +56,7 @@ struct BatchArgs {
     uint64_t* tab;
     uint64_t* rs;
     uint32_t* rec;              // packed record bits, zeroed before the launch
+    uint64_t* cols;             // base of the circuits' column scratch
     const uint64_t* ibase;      // per circuit: instructions it executed before this launch
     const ulonglong2* keys;     // per circuit RNG key, or NULL for (seed, circuit index)
     int meas_quota;             // stop a circuit after this many measurement steps (0: run all)
@@ -67,12 +71,15 @@ __host__ __device__ inline int batch_lds_words(int Wc)
     const int RS = 2 * Wc, NB = 2 * Wc;
     const int seg = 64 * (RS + 1) + 16;
     // signs, x-column bits, pivot row, per-wave (X, Z) partial products, 32 ints, row list
-    // (uint16, one entry per row)
-    const int meas = 2 * NB + RS + 2 * kBatchWaves * RS + 16 + (NB * 64 * 2 + 7) / 8;
+    // (uint16, one entry per row), outcome and random-at-start bits of up to 64*Wc targets
+    const int meas = 2 * NB + RS + 2 * kBatchWaves * RS + 16 + (NB * 64 * 2 + 7) / 8 + 2 * Wc;
     return seg > meas ? seg : meas;
 }
 
 constexpr int kMK = 7, kMRK = 8, kRK = 9, kT1T2K = 13;   // kinds (include/stab.h enum)
+// A measurement instruction with at least this many targets gets an extraction-only band
+// pass when no gate pass precedes it.
+constexpr int kBatchExtractMin = 8;
 
 __device__ __forceinline__ ulonglong2 batch_key(const BatchArgs& A, int ci)
 {
@@ -144,8 +151,10 @@ __device__ __forceinline__ void batch_noise(const uint64_t* T, int RSP, int Wc, 
 }
 
 // One run of gate/noise steps [st, en) over every band of the circuit.
+// With `ext` set, the band pass also writes the x and z columns of that measurement's targets
+// (64 rows per word) to the circuit's column scratch, [band][target].
 __device__ void batch_segment(const BatchArgs& A, const BatchCirc& C, int ci, int st, int en,
-                              uint64_t* lds)
+                              uint64_t* lds, const BatchMeas* ext)
 {
     const int tid = threadIdx.x, nt = kBatchThreads;
     const int lane = tid & 63, wave = tid >> 6;
@@ -197,6 +206,17 @@ __device__ void batch_segment(const BatchArgs& A, const BatchCirc& C, int ci, in
                     batch_noise(T, RSP, Wc, d, A.noise_tg, u, key, A.ibase[ci], racc);
             }
             __syncthreads();
+        }
+        if (ext) {
+            uint64_t* Xs = A.cols + C.col_off + (size_t)band * C.col_k;
+            uint64_t* Zs = Xs + (size_t)NB * C.col_k;
+            for (int k = tid; k < ext->K; k += nt) {
+                const int q = A.meas_tg[ext->tq + k];
+                const int iq = (q & 63) * RSP + (q >> 6);
+                Xs[k] = T[iq];
+                Zs[k] = T[iq + Wc];
+            }
+            __syncthreads();    // the transpose back rewrites T
         }
         if (wb) {
             for (int c = wave; c < RS; c += kBatchWaves) {
@@ -446,146 +466,314 @@ __device__ int batch_det(const BatchCirc& C, const uint64_t* __restrict__ tab, c
     return s_res[0];
 }
 
-// One M / MR / R instruction of circuit ci, target by target.  A T1T2 instruction runs here
-// too: per target a Philox draw picks reset (u0 < t0: a measurement whose random outcome is
-// u1 >> 63, then X if it is 1), Z (u0 < t1: sign flip of every row with x at the qubit) or
-// nothing.
+// LDS of a measurement instruction (see batch_lds_words).
+struct MeasLds {
+    uint64_t* sg;      // NB sign words
+    uint64_t* colx;    // NB words: x bit of the target, per row
+    uint64_t* prow;    // RS words: pivot row
+    uint64_t* part;    // 2 * kBatchWaves * RS words
+    int* s_int;        // 32 ints: pivot, list and det scratch, T1T2 event masks
+    uint16_t* list;    // 2 * NR row indices
+    uint64_t* outb;    // outcome bits of the instruction's targets
+    uint64_t* rndb;    // random-at-start bits
+};
+
+__device__ __forceinline__ MeasLds meas_lds(const BatchCirc& C, uint64_t* lds)
+{
+    const int NB = 2 * C.Wc, RS = C.RS;
+    MeasLds L;
+    L.sg = lds;
+    L.colx = L.sg + NB;
+    L.prow = L.colx + NB;
+    L.part = L.prow + RS;
+    L.s_int = (int*)(L.part + 2 * kBatchWaves * RS);
+    L.list = (uint16_t*)(L.s_int + 32);
+    L.outb = (uint64_t*)(L.s_int + 32) + 16 * NB;
+    L.rndb = L.outb + C.Wc;
+    return L;
+}
+
+struct MeasWork {
+    int nrand = 0, ndet = 0;
+    long long nrows = 0, bytes = 0;
+};
+
+// Z measurement of qubit a on the live tableau (block-wide): pivot search from the x column,
+// then rowsum and row moves (random, outcome rand_bit) or the deterministic product.
 template <int NW>
-__device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, const BatchMeas& md,
-                              uint64_t* lds)
+__device__ int batch_measure_one(const BatchArgs& A, const BatchCirc& C, int a, int rand_bit, const MeasLds& L,
+                                 MeasWork& W)
 {
     const int tid = threadIdx.x;
     const int Wc = C.Wc, RS = C.RS, NR = C.NR, NB = 2 * C.Wc;
     uint64_t* tab = A.tab + C.tab_off;
-    uint64_t* rs = A.rs + C.rs_off;
-    uint64_t* sg = lds;                      // NB sign words
-    uint64_t* colx = sg + NB;                // NB words: x bit of the target, per row
-    uint64_t* prow = colx + NB;              // RS words: pivot row
-    uint64_t* part = prow + RS;              // 2 * kBatchWaves * RS words
-    int* s_int = (int*)(part + 2 * kBatchWaves * RS);   // 32 ints: pivot, list and det scratch
-    uint16_t* list = (uint16_t*)(s_int + 32);          // 2 * NR entries
-
-    const ulonglong2 key = batch_key(A, ci);
-    for (int w = tid; w < NB; w += kBatchThreads) sg[w] = rs[w];
-    __syncthreads();
-    int nrand = 0, ndet = 0;
-    long long nrows = 0, bytes = 0;
     const long long row_b = (long long)RS * 8, col_b = (long long)2 * NR * 8;
-    const bool stoch = md.kind == kT1T2K;
-    uint64_t* s_ev = (uint64_t*)(s_int + 24);           // a T1T2 chunk: reset, Z, outcome masks
-    for (int c0 = 0; c0 < md.K; c0 += 64) {
-        const int cn = min(64, md.K - c0);
-        const uint64_t live = cn == 64 ? ~0ull : ((1ull << cn) - 1ull);
-        uint64_t ev_meas = live, ev_z = 0, ev_bits = 0;  // M / MR / R: every target, in order
-        if (stoch) {
-            // draws do not depend on the tableau: one wave draws 64 targets at once
-            if (tid < 64) {
-                int act = 0, rb = 0;
-                if (tid < cn) {
-                    uint64_t u0, u1;
-                    philox(A.ibase[ci] + md.instr, (uint64_t)(c0 + tid), key.x, key.y, u0, u1);
-                    act = u0 < md.t0 ? 1 : (u0 < md.t1 ? 2 : 0);
-                    rb = (int)(u1 >> 63);
-                }
-                const uint64_t m1 = __ballot(act == 1), m2 = __ballot(act == 2), mb = __ballot(rb);
-                if (tid == 0) {
-                    s_ev[0] = m1;
-                    s_ev[1] = m2;
-                    s_ev[2] = mb;
-                }
-            }
-            __syncthreads();
-            ev_meas = s_ev[0];
-            ev_z = s_ev[1];
-            ev_bits = s_ev[2];
-            __syncthreads();
+    batch_column(tab, RS, NB, a >> 6, a & 63, L.colx, false);
+    __syncthreads();
+    // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
+    if (tid < 64) {
+        int first = 0x7fffffff;
+        for (int w = Wc + tid; w < NB; w += 64)
+            if (L.colx[w]) first = min(first, 64 * w + ctz64(L.colx[w]));
+        first = wave_min(first);
+        if (tid == 0) L.s_int[0] = first;
+    }
+    __syncthreads();
+    const int p = L.s_int[0];
+    int outcome;
+    if (p != 0x7fffffff) {
+        outcome = rand_bit;
+        for (int j = tid; j < RS; j += kBatchThreads) L.prow[j] = tab[(size_t)p * RS + j];
+        const int rp = (int)((L.sg[p >> 6] >> (p & 63)) & 1ull);
+        const int nl = batch_list(L.colx, 0, NB, p, p - NR, L.list, L.s_int + 1);
+        __syncthreads();    // prow staged
+        batch_rowsum<NW>(C, tab, L.prow, rp, L.list, nl, L.sg, A.err);
+        __syncthreads();
+        // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
+        const int d = p - NR;
+        for (int j = tid; j < RS; j += kBatchThreads) {
+            tab[(size_t)d * RS + j] = L.prow[j];
+            tab[(size_t)p * RS + j] = (j == Wc + (a >> 6)) ? (1ull << (a & 63)) : 0ull;
         }
-        uint64_t evm = (ev_meas | ev_z) & live;
-        while (evm) {
-            const int bit = ctz64(evm);
-            evm &= evm - 1;
-            const int t = c0 + bit;
-            const int a = A.meas_tg[md.tq + t];
-            if ((ev_z >> bit) & 1ull) {
-                // Z on the qubit: flip the sign of every row with x at it
-                batch_column(tab, RS, NB, a >> 6, a & 63, sg, true);
-                __syncthreads();
-                bytes += col_b;
-                continue;
+        if (tid == 0) {
+            uint64_t wd = L.sg[d >> 6];
+            wd = (wd & ~(1ull << (d & 63))) | ((uint64_t)rp << (d & 63));
+            L.sg[d >> 6] = wd;
+            uint64_t wp = L.sg[p >> 6];
+            wp = (wp & ~(1ull << (p & 63))) | ((uint64_t)outcome << (p & 63));
+            L.sg[p >> 6] = wp;
+        }
+        ++W.nrand;
+        W.nrows += nl;
+        // column, pivot row, rowsum read+write, two row writes
+        W.bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
+    } else {
+        const int nl = batch_list(L.colx, 0, Wc, -1, -1, L.list, L.s_int + 1);
+        outcome = batch_det<NW>(C, tab, L.list, nl, L.sg, L.part, L.s_int + 10, A.err);
+        ++W.ndet;
+        W.nrows += nl;
+        W.bytes += col_b + nl * row_b;
+    }
+    __syncthreads();
+    return outcome;
+}
+
+// One wave: the outcome of target k of an instruction whose columns are in the scratch, if it
+// is deterministic (no stabilizer has x at the qubit); -1 if it is random.  The product of
+// the stabilizers selected by the destabilizers with x at the qubit, as in batch_det.
+template <int NW>
+__device__ int batch_det_from_cols(const BatchArgs& A, const BatchCirc& C, const uint64_t* Xs, int k,
+                                   const uint64_t* sg, int& nrows)
+{
+    const int lane = threadIdx.x & 63;
+    const int Wc = C.Wc, RS = C.RS, NR = C.NR, CK = C.col_k;
+    const uint64_t* tab = A.tab + C.tab_off;
+    bool st = false;
+    for (int w = Wc + lane; w < 2 * Wc; w += 64) st |= Xs[(size_t)w * CK + k] != 0ull;
+    if (__ballot(st)) return -1;
+    uint64_t X[NW], Z[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) X[t] = Z[t] = 0;
+    int e = 0, cross = 0, rows = 0;
+    for (int w = 0; w < Wc; ++w) {
+        uint64_t m = Xs[(size_t)w * CK + k];
+        while (m) {
+            const int i = 64 * w + ctz64(m);
+            m &= m - 1;
+            const uint64_t* row = tab + (size_t)(NR + i) * RS;
+#pragma unroll
+            for (int t = 0; t < NW; ++t) {
+                const int j = lane + 64 * t;
+                const uint64_t x = (j < Wc) ? row[j] : 0ull, z = (j < Wc) ? row[Wc + j] : 0ull;
+                e += __popcll(x & z);
+                cross += __popcll(Z[t] & x);
+                X[t] ^= x;
+                Z[t] ^= z;
             }
-            int rand_bit;
-            if (stoch) {
-                rand_bit = (int)((ev_bits >> bit) & 1ull);
-            } else {
+            if (lane == 0) e += 2 * (int)((sg[(NR + i) >> 6] >> ((NR + i) & 63)) & 1ull);
+            ++rows;
+        }
+    }
+    uint64_t xr = 0;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) xr |= X[t];
+    const int tot = wave_sum((e & 3) + 2 * (cross & 1)) & 3;
+    xr = wave_or(xr);
+    if (lane == 0 && ((tot & 1) || xr)) atomicOr(A.err, 1);
+    nrows += rows;
+    return tot >> 1;
+}
+
+// One M / MR / R / T1T2 instruction of circuit ci.
+//
+// Slow form (any instruction): target by target on the live tableau.  A T1T2 instruction runs
+// here too: per target a Philox draw picks reset (u0 < t0: a measurement whose random outcome
+// is u1 >> 63, then X if it is 1), Z (u0 < t1: sign flip of every row with x at the qubit) or
+// nothing; one wave draws 64 targets at a time (draws do not depend on the tableau).
+//
+// Fast form (M/MR/R on distinct qubits whose columns the band pass extracted): every target
+// deterministic at the start of the instruction is reduced at once, one wave per target (a
+// deterministic outcome does not change when other qubits are measured or reset); the
+// random-at-start ones then run in op order on the live tableau; resets come last (an X on a
+// measured qubit flips signs only, which commutes with the other measurements).
+template <int NW>
+__device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, const BatchMeas& md,
+                              uint64_t* lds, bool fast)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int Wc = C.Wc, RS = C.RS, NR = C.NR, NB = 2 * C.Wc;
+    uint64_t* tab = A.tab + C.tab_off;
+    uint64_t* rs = A.rs + C.rs_off;
+    const MeasLds L = meas_lds(C, lds);
+    const ulonglong2 key = batch_key(A, ci);
+    const long long row_b = (long long)RS * 8, col_b = (long long)2 * NR * 8;
+    MeasWork W;
+    for (int w = tid; w < NB; w += kBatchThreads) L.sg[w] = rs[w];
+    __syncthreads();
+
+    if (fast) {
+        const uint64_t* Xs = A.cols + C.col_off;
+        const uint64_t* Zs = Xs + (size_t)NB * C.col_k;
+        const int KW = (md.K + 63) >> 6;
+        for (int w = tid; w < KW; w += kBatchThreads) L.outb[w] = L.rndb[w] = 0;
+        __syncthreads();
+        int nrows = 0, ndet = 0;
+        for (int k = wave; k < md.K; k += kBatchWaves) {
+            const int o = batch_det_from_cols<NW>(A, C, Xs, k, L.sg, nrows);
+            if (lane == 0) {
+                if (o < 0) atomicOr((unsigned long long*)&L.rndb[k >> 6], 1ull << (k & 63));
+                else if (o) atomicOr((unsigned long long*)&L.outb[k >> 6], 1ull << (k & 63));
+            }
+            if (o >= 0) ++ndet;
+        }
+        if (lane == 0) {
+            W.ndet += ndet;
+            W.nrows += nrows;
+            W.bytes += (long long)ndet * NB * 8 + (long long)nrows * row_b;
+        }
+        __syncthreads();
+        // random at the start of the instruction: in op order, on the live tableau
+        bool ran = false;
+        for (int kw = 0; kw < KW; ++kw) {
+            uint64_t m = L.rndb[kw];
+            while (m) {
+                const int k = 64 * kw + ctz64(m);
+                m &= m - 1;
+                ran = true;
                 uint64_t u0, u1;
-                philox(A.ibase[ci] + md.instr, (uint64_t)t, key.x, key.y, u0, u1);
-                rand_bit = (int)(u0 >> 63);
-            }
-            batch_column(tab, RS, NB, a >> 6, a & 63, colx, false);
-            __syncthreads();
-            // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
-            if (tid < 64) {
-                int first = 0x7fffffff;
-                for (int w = Wc + tid; w < NB; w += 64)
-                    if (colx[w]) first = min(first, 64 * w + ctz64(colx[w]));
-                first = wave_min(first);
-                if (tid == 0) s_int[0] = first;
-            }
-            __syncthreads();
-            const int p = s_int[0];
-            int outcome;
-            if (p != 0x7fffffff) {
-                outcome = rand_bit;
-                for (int j = tid; j < RS; j += kBatchThreads) prow[j] = tab[(size_t)p * RS + j];
-                const int rp = (int)((sg[p >> 6] >> (p & 63)) & 1ull);
-                const int nl = batch_list(colx, 0, NB, p, p - NR, list, s_int + 1);
-                __syncthreads();    // prow staged
-                batch_rowsum<NW>(C, tab, prow, rp, list, nl, sg, A.err);
+                philox(A.ibase[ci] + md.instr, (uint64_t)k, key.x, key.y, u0, u1);
+                const int o = batch_measure_one<NW>(A, C, A.meas_tg[md.tq + k], (int)(u0 >> 63), L, W);
+                if (tid == 0 && o) L.outb[kw] |= 1ull << (k & 63);
                 __syncthreads();
-                // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
-                const int d = p - NR;
-                for (int j = tid; j < RS; j += kBatchThreads) {
-                    tab[(size_t)d * RS + j] = prow[j];
-                    tab[(size_t)p * RS + j] = (j == Wc + (a >> 6)) ? (1ull << (a & 63)) : 0ull;
+            }
+        }
+        if (md.rec >= 0)
+            for (int k = tid; k < md.K; k += kBatchThreads)
+                if ((L.outb[k >> 6] >> (k & 63)) & 1ull) {
+                    const long long rb = C.rec_bit_off + md.rec + k;
+                    atomicOr(&A.rec[rb >> 5], 1u << (rb & 31));
                 }
-                if (tid == 0) {
-                    uint64_t wd = sg[d >> 6];
-                    wd = (wd & ~(1ull << (d & 63))) | ((uint64_t)rp << (d & 63));
-                    sg[d >> 6] = wd;
-                    uint64_t wp = sg[p >> 6];
-                    wp = (wp & ~(1ull << (p & 63))) | ((uint64_t)outcome << (p & 63));
-                    sg[p >> 6] = wp;
+        if (md.kind != kMK) {
+            if (!ran) {
+                // the extracted z columns are still those of the live tableau
+                for (int w = tid; w < NB; w += kBatchThreads) {
+                    uint64_t x = 0;
+                    for (int kw = 0; kw < KW; ++kw) {
+                        uint64_t m = L.outb[kw];
+                        while (m) {
+                            const int k = 64 * kw + ctz64(m);
+                            m &= m - 1;
+                            x ^= Zs[(size_t)w * C.col_k + k];
+                        }
+                    }
+                    L.sg[w] ^= x;
                 }
-                ++nrand;
-                nrows += nl;
-                // column, pivot row, rowsum read+write, two row writes
-                bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
+                __syncthreads();
             } else {
-                const int nl = batch_list(colx, 0, Wc, -1, -1, list, s_int + 1);
-                outcome = batch_det<NW>(C, tab, list, nl, sg, part, s_int + 10, A.err);
-                ++ndet;
-                nrows += nl;
-                bytes += col_b + nl * row_b;
+                for (int kw = 0; kw < KW; ++kw) {
+                    uint64_t m = L.outb[kw];
+                    while (m) {
+                        const int k = 64 * kw + ctz64(m);
+                        m &= m - 1;
+                        const int a = A.meas_tg[md.tq + k];
+                        batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, L.sg, true);
+                        __syncthreads();
+                        W.bytes += col_b;
+                    }
+                }
             }
-            __syncthreads();
-            if (md.rec >= 0 && tid == 0 && outcome) {
-                const long long rb = C.rec_bit_off + md.rec + t;
-                atomicOr(&A.rec[rb >> 5], 1u << (rb & 31));
-            }
-            if (md.kind != kMK && outcome) {
-                // reset: apply X_a, i.e. flip the sign of every row with z at a
-                batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, sg, true);
+        }
+    } else {
+        const bool stoch = md.kind == kT1T2K;
+        uint64_t* s_ev = (uint64_t*)(L.s_int + 24);        // a T1T2 chunk: reset, Z, outcome masks
+        for (int c0 = 0; c0 < md.K; c0 += 64) {
+            const int cn = min(64, md.K - c0);
+            const uint64_t live = cn == 64 ? ~0ull : ((1ull << cn) - 1ull);
+            uint64_t ev_meas = live, ev_z = 0, ev_bits = 0;  // M / MR / R: every target, in order
+            if (stoch) {
+                if (tid < 64) {
+                    int act = 0, rb = 0;
+                    if (tid < cn) {
+                        uint64_t u0, u1;
+                        philox(A.ibase[ci] + md.instr, (uint64_t)(c0 + tid), key.x, key.y, u0, u1);
+                        act = u0 < md.t0 ? 1 : (u0 < md.t1 ? 2 : 0);
+                        rb = (int)(u1 >> 63);
+                    }
+                    const uint64_t m1 = __ballot(act == 1), m2 = __ballot(act == 2), mb = __ballot(rb);
+                    if (tid == 0) {
+                        s_ev[0] = m1;
+                        s_ev[1] = m2;
+                        s_ev[2] = mb;
+                    }
+                }
                 __syncthreads();
-                bytes += col_b;
+                ev_meas = s_ev[0];
+                ev_z = s_ev[1];
+                ev_bits = s_ev[2];
+                __syncthreads();
+            }
+            uint64_t evm = (ev_meas | ev_z) & live;
+            while (evm) {
+                const int bit = ctz64(evm);
+                evm &= evm - 1;
+                const int t = c0 + bit;
+                const int a = A.meas_tg[md.tq + t];
+                if ((ev_z >> bit) & 1ull) {
+                    // Z on the qubit: flip the sign of every row with x at it
+                    batch_column(tab, RS, NB, a >> 6, a & 63, L.sg, true);
+                    __syncthreads();
+                    W.bytes += col_b;
+                    continue;
+                }
+                int rand_bit;
+                if (stoch) {
+                    rand_bit = (int)((ev_bits >> bit) & 1ull);
+                } else {
+                    uint64_t u0, u1;
+                    philox(A.ibase[ci] + md.instr, (uint64_t)t, key.x, key.y, u0, u1);
+                    rand_bit = (int)(u0 >> 63);
+                }
+                const int outcome = batch_measure_one<NW>(A, C, a, rand_bit, L, W);
+                if (md.rec >= 0 && tid == 0 && outcome) {
+                    const long long rb = C.rec_bit_off + md.rec + t;
+                    atomicOr(&A.rec[rb >> 5], 1u << (rb & 31));
+                }
+                if (md.kind != kMK && outcome) {
+                    // reset: apply X_a, i.e. flip the sign of every row with z at a
+                    batch_column(tab, RS, NB, Wc + (a >> 6), a & 63, L.sg, true);
+                    __syncthreads();
+                    W.bytes += col_b;
+                }
             }
         }
     }
-    for (int w = tid; w < NB; w += kBatchThreads) rs[w] = sg[w];
-    if (tid == 0) {
-        count_add(A.counters, 4, (unsigned long long)nrand);
-        count_add(A.counters, 2, (unsigned long long)ndet);
-        count_add(A.counters, 5, (unsigned long long)nrows);
-        count_add(A.counters, 6, (unsigned long long)bytes);
+    __syncthreads();
+    for (int w = tid; w < NB; w += kBatchThreads) rs[w] = L.sg[w];
+    if (lane == 0 && (W.ndet || W.nrand || W.nrows)) {
+        count_add(A.counters, 4, (unsigned long long)W.nrand);
+        count_add(A.counters, 2, (unsigned long long)W.ndet);
+        count_add(A.counters, 5, (unsigned long long)W.nrows);
+        count_add(A.counters, 6, (unsigned long long)W.bytes);
     }
     __syncthreads();
 }
@@ -599,19 +787,33 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
     const int ci = A.order[blockIdx.x];
     const BatchCirc C = A.circ[ci];
     const int end = C.step_begin + C.step_count;
-    int done = 0;
+    int done = 0, ext_step = -1;
     for (int st = C.step_begin; st < end && (A.meas_quota == 0 || done < A.meas_quota);) {
         const int4 s0 = A.steps[st];
         if (s0.x == 2) {
             const BatchMeas md = A.meas[s0.y];
-            batch_measure<NW>(A, C, ci, md, lds);
+            if (ext_step != st && A.cols && md.fast && md.K <= C.col_k && md.K >= kBatchExtractMin) {
+                // no band pass ran since the last measurement: one that only reads the rows
+                // and extracts the columns is far cheaper than measuring target by target
+                batch_segment(A, C, ci, st, st, lds, &A.meas[s0.y]);
+                ext_step = st;
+            }
+            batch_measure<NW>(A, C, ci, md, lds, ext_step == st);
+            ext_step = -1;
             ++st;
             ++done;
             continue;
         }
         int en = st + 1;
         while (en < end && A.steps[en].x != 2) ++en;
-        batch_segment(A, C, ci, st, en, lds);
+        // the next measurement's columns come out of this band pass when it allows that
+        const BatchMeas* nx = nullptr;
+        if (en < end && A.cols) {
+            const BatchMeas* m = &A.meas[A.steps[en].y];
+            if (m->fast && m->K <= C.col_k) nx = m;
+        }
+        batch_segment(A, C, ci, st, en, lds, nx);
+        if (nx) ext_step = en;
         st = en;
     }
 }

@@ -29,6 +29,7 @@ struct stab_batch_program {
     int lds_bytes = 0;
     int nw = 1;                       // x words per lane (kernel variant)
     void* dev = nullptr;
+    uint64_t* cols = nullptr;         // column scratch of every circuit
     BatchCirc* d_circ = nullptr;
     int* d_order = nullptr;
     int4* d_steps = nullptr;
@@ -90,10 +91,11 @@ int batch_init(stab_batch* b)
 int batch_compile_one(int c, int n, const stab_instr* ins, int64_t ninstr, const int32_t* tg, int64_t ntg,
                       std::vector<int4>& steps, std::vector<uint2>& gates, std::vector<NoiseDesc>& noise,
                       std::vector<int>& noise_tg, std::vector<BatchMeas>& meas, std::vector<int>& meas_tg,
-                      long long& nrec)
+                      long long& nrec, int& kfast)
 {
     const std::string where = "circuit " + std::to_string(c) + ", instruction ";
-    std::vector<int> stamp(n, -1);
+    std::vector<int> stamp(n, -1), mstamp(n, -1);
+    kfast = 0;
     int layer_id = 0, open_begin = -1, open_mod = 0;
     auto close_layer = [&]() {
         if (open_begin >= 0) {
@@ -171,6 +173,13 @@ int batch_compile_one(int c, int n, const stab_instr* ins, int64_t ninstr, const
             const bool recorded = kind == STAB_M || kind == STAB_MR;
             m.rec = recorded ? (int)nrec : -1;
             if (recorded) nrec += nt;
+            // distinct qubits: its columns can come out of the band pass before it
+            m.fast = kind != STAB_T1T2 ? 1 : 0;
+            for (uint32_t q = 0; q < nt && m.fast; ++q) {
+                if (mstamp[t[q]] == (int)k) m.fast = 0;
+                mstamp[t[q]] = (int)k;
+            }
+            if (m.fast) kfast = std::max(kfast, (int)nt);
             meas_tg.insert(meas_tg.end(), t, t + nt);
             steps.push_back(make_int4(2, (int)meas.size(), 0, 0));
             meas.push_back(m);
@@ -314,12 +323,14 @@ int stab_batch_compile(stab_batch* b, const stab_instr* instrs, const int64_t* i
     P->rec_byte.assign(C + 1, 0);
     std::vector<double> cost(C, 0.0);
     int maxwc = 1;
+    size_t cols_words = 0;
     for (int c = 0; c < C; ++c) {
         const int s0 = (int)steps.size();
         long long nrec = 0;
+        int kfast = 0;
         const int rc = batch_compile_one(c, circ[c].n, instrs + instr_off[c], instr_off[c + 1] - instr_off[c],
                                          targets + target_off[c], target_off[c + 1] - target_off[c], steps, gates,
-                                         noise, noise_tg, meas, meas_tg, nrec);
+                                         noise, noise_tg, meas, meas_tg, nrec, kfast);
         if (rc) {
             delete P;
             return rc;
@@ -327,6 +338,9 @@ int stab_batch_compile(stab_batch* b, const stab_instr* instrs, const int64_t* i
         circ[c].step_begin = s0;
         circ[c].step_count = (int)steps.size() - s0;
         circ[c].rec_bit_off = 8 * P->rec_byte[c];
+        circ[c].col_k = kfast;
+        circ[c].col_off = (long long)cols_words;
+        cols_words += align256((size_t)2 * 2 * circ[c].Wc * kfast * 8) / 8;
         P->n[c] = circ[c].n;
         P->nrec[c] = nrec;
         P->ninstr[c] = instr_off[c + 1] - instr_off[c];
@@ -356,6 +370,11 @@ int stab_batch_compile(stab_batch* b, const stab_instr* instrs, const int64_t* i
         delete P;
         return fail(STAB_ENOMEM, "device allocation failed");
     }
+    if (cols_words > 0 && hipMalloc((void**)&P->cols, cols_words * 8) != hipSuccess) {
+        P->cols = nullptr;
+        stab_batch_program_destroy(P);
+        return fail(STAB_ENOMEM, "device allocation failed");
+    }
     if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
         stab_batch_program_destroy(P);
         b->poisoned = true;
@@ -383,10 +402,9 @@ int64_t stab_batch_program_records(const stab_batch_program* P, int32_t circuit)
 void stab_batch_program_destroy(stab_batch_program* P)
 {
     if (!P) return;
-    if (P->dev) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(P->dev);
-    }
+    if (P->dev || P->cols) (void)hipDeviceSynchronize();
+    if (P->dev) (void)hipFree(P->dev);
+    if (P->cols) (void)hipFree(P->cols);
     delete P;
 }
 
@@ -424,6 +442,7 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
     A.ibase = b->d_ibase;
     A.keys = nullptr;
     A.meas_quota = 0;
+    A.cols = P->cols;
     A.seed = b->seed;
     A.err = b->d_err;
     A.counters = b->d_counters;

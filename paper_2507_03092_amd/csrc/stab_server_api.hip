@@ -51,6 +51,7 @@ struct SrvProgram {
     long long nrec = 0;
     int ninstr = 0;
     int step_base = 0, nsteps = 0;
+    int kfast = 0;                // column scratch targets per band
 };
 
 struct SrvRequest {
@@ -65,15 +66,17 @@ struct SrvRequest {
     std::vector<uint8_t> result;
 };
 
-size_t srv_shot_bytes(int n)
+// per shot: tableau, signs, column scratch [2][NB][kfast]
+size_t srv_shot_bytes(int n, int kfast)
 {
     const int Wc = (n + 63) / 64;
-    return align256((size_t)2 * 64 * Wc * 2 * Wc * 8) + align256((size_t)2 * Wc * 8);
+    return align256((size_t)2 * 64 * Wc * 2 * Wc * 8) + align256((size_t)2 * Wc * 8) +
+           align256((size_t)2 * 2 * Wc * kfast * 8);
 }
 
-size_t srv_request_bytes(int n, int shots, long long nrec)
+size_t srv_request_bytes(int n, int kfast, int shots, long long nrec)
 {
-    return (size_t)shots * srv_shot_bytes(n) + align256((size_t)shots * (size_t)((nrec + 7) / 8));
+    return (size_t)shots * srv_shot_bytes(n, kfast) + align256((size_t)shots * (size_t)((nrec + 7) / 8));
 }
 
 }  // namespace
@@ -152,10 +155,13 @@ BatchCirc srv_circ(const stab_server* s, const SrvRequest& r, int shot, int curs
     C.Wc = (P.n + 63) / 64;
     C.RS = 2 * C.Wc;
     C.NR = 64 * C.Wc;
-    const size_t shot_b = srv_shot_bytes(P.n);
+    const size_t shot_b = srv_shot_bytes(P.n, P.kfast);
     const size_t tab_b = align256((size_t)2 * C.NR * C.RS * 8);
+    const size_t sg_b = align256((size_t)2 * C.Wc * 8);
     C.tab_off = (long long)((r.off + (size_t)shot * shot_b) / 8);
     C.rs_off = (long long)((r.off + (size_t)shot * shot_b + tab_b) / 8);
+    C.col_off = (long long)((r.off + (size_t)shot * shot_b + tab_b + sg_b) / 8);
+    C.col_k = P.kfast;
     C.step_begin = P.step_base + cursor;
     C.step_count = P.nsteps - cursor;
     C.rec_bit_off = (long long)(r.rec_off + (size_t)shot * (size_t)((P.nrec + 7) / 8)) * 8;
@@ -182,7 +188,7 @@ int srv_admit(stab_server* s)
         size_t off = 0;
         if (!srv_alloc(s, r.bytes, &off)) break;
         r.off = off;
-        r.rec_off = off + (size_t)r.shots * srv_shot_bytes(s->progs[r.prog].n);
+        r.rec_off = off + (size_t)r.shots * srv_shot_bytes(s->progs[r.prog].n, s->progs[r.prog].kfast);
         for (int sh = 0; sh < r.shots; ++sh) init.push_back(srv_circ(s, r, sh, 0));
         clear.push_back({r.rec_off, r.off + r.bytes - r.rec_off});
         s->resident.push_back(std::move(r));
@@ -213,11 +219,12 @@ int srv_admit(stab_server* s)
 
 extern "C" {
 
-int stab_server_request_bytes(int32_t n, int32_t shots, int64_t nrec, uint64_t* bytes_out)
+int stab_server_request_bytes(const stab_server* s, int32_t prog, int32_t shots, uint64_t* bytes_out)
 {
-    if (!bytes_out || n < 1 || shots < 1 || nrec < 0) return fail(STAB_EINVAL, "bad arguments");
-    if ((n + 63) / 64 > kBatchMaxWc) return fail(STAB_ERANGE, "more qubits than a batch supports");
-    *bytes_out = srv_request_bytes(n, shots, nrec);
+    if (!s || !bytes_out || shots < 1) return fail(STAB_EINVAL, "bad arguments");
+    if (prog < 0 || prog >= (int32_t)s->progs.size()) return fail(STAB_EINVAL, "unknown program");
+    const SrvProgram& P = s->progs[prog];
+    *bytes_out = srv_request_bytes(P.n, P.kfast, shots, P.nrec);
     return STAB_OK;
 }
 
@@ -279,8 +286,9 @@ int stab_server_program(stab_server* s, const stab_instr* instrs, int32_t ninstr
     const size_t g0 = s->gates.host.size(), n0 = s->noise.host.size(), nt0 = s->noise_tg.host.size(),
                  m0 = s->meas.host.size(), mt0 = s->meas_tg.host.size();
     long long nrec = 0;
+    int kfast = 0;
     const int rc = batch_compile_one(0, n, instrs, ninstr, targets, ntargets, s->steps.host, s->gates.host,
-                                     s->noise.host, s->noise_tg.host, s->meas.host, s->meas_tg.host, nrec);
+                                     s->noise.host, s->noise_tg.host, s->meas.host, s->meas_tg.host, nrec, kfast);
     if (rc) {
         s->steps.host.resize(P.step_base);
         s->gates.host.resize(g0);
@@ -292,6 +300,7 @@ int stab_server_program(stab_server* s, const stab_instr* instrs, int32_t ninstr
     }
     P.nsteps = (int)s->steps.host.size() - P.step_base;
     P.nrec = nrec;
+    P.kfast = kfast;
     int rc2;
     if ((rc2 = devvec_sync(s->steps, s->stream)) || (rc2 = devvec_sync(s->gates, s->stream)) ||
         (rc2 = devvec_sync(s->noise, s->stream)) || (rc2 = devvec_sync(s->noise_tg, s->stream)) ||
@@ -317,7 +326,7 @@ int stab_server_submit(stab_server* s, int32_t prog, int32_t shots, uint64_t see
     if (prog < 0 || prog >= (int32_t)s->progs.size()) return fail(STAB_EINVAL, "unknown program");
     if (shots < 1) return fail(STAB_EINVAL, "shots < 1");
     const SrvProgram& P = s->progs[prog];
-    const size_t bytes = srv_request_bytes(P.n, shots, P.nrec);
+    const size_t bytes = srv_request_bytes(P.n, P.kfast, shots, P.nrec);
     if (bytes > s->bytes) return fail(STAB_ERANGE, "request larger than the whole arena");
     SrvRequest r;
     r.id = s->next_id++;
@@ -383,6 +392,7 @@ int stab_server_step(stab_server* s, int32_t* finished_out)
         A.rec = (uint32_t*)s->base;
         A.ibase = (const uint64_t*)s->d_ibase.p;
         A.keys = (const ulonglong2*)s->d_keys.p;
+        A.cols = (uint64_t*)s->base;
         A.meas_quota = 1;
         A.seed = 0;
         A.err = s->d_err;

@@ -86,7 +86,7 @@ def lib():
         "stab_batch_get_tableau": (C.c_int, [P, I32, P, P, P]),
         "stab_batch_get_counters": (C.c_int, [P, P, I32]),
         "stab_commute": (C.c_int, [P, I32, P, I32, I32, P, P, P]),
-        "stab_server_request_bytes": (C.c_int, [I32, I32, I64, C.POINTER(U64)]),
+        "stab_server_request_bytes": (C.c_int, [P, I32, I32, C.POINTER(U64)]),
         "stab_server_create": (C.c_int, [P, U64, P, C.POINTER(P)]),
         "stab_server_destroy": (None, [P]),
         "stab_server_program": (C.c_int, [P, P, I32, P, I64, I32, C.POINTER(I32)]),
@@ -403,12 +403,6 @@ SERVER_STATS = ("queued", "resident_requests", "resident_shots", "bytes_in_use",
                 "finished")
 
 
-def server_request_bytes(n: int, shots: int, nrec: int) -> int:
-    out = C.c_uint64(0)
-    _check(lib().stab_server_request_bytes(n, shots, nrec, C.byref(out)))
-    return out.value
-
-
 class Server:
     """stab_server_*: requests admitted by arena bytes, one round of every resident shot per
     step."""
@@ -443,6 +437,11 @@ class Server:
         _check(lib().stab_server_program(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg), circ.n,
                                          C.byref(pid)))
         return pid.value
+
+    def request_bytes(self, prog: int, shots: int) -> int:
+        out = C.c_uint64(0)
+        _check(lib().stab_server_request_bytes(self.h, prog, shots, C.byref(out)))
+        return out.value
 
     def submit(self, prog: int, shots: int, seed: int) -> int:
         rid = C.c_int64(0)

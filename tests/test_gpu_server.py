@@ -75,7 +75,9 @@ def test_server_mixed_requests_match_oracle_alone_and_in_the_mix(stab):
 
 def test_server_admission_by_bytes(stab):
     circ = Cc.surface_code_memory(5, 5, 2e-3)[0]
-    per = stab.server_request_bytes(circ.n, 8, circ.num_measurements())
+    probe = stab.Server(1 << 20)
+    per = probe.request_bytes(probe.program(circ), 8)
+    probe.close()
     srv = stab.Server(2 * per + 4096)          # room for two requests at a time
     prog = srv.program(circ)
     ids = [srv.submit(prog, 8, 100 + i) for i in range(5)]
