@@ -271,6 +271,7 @@ def main() -> int:
         "roofline_segment": roofline_segment,
         "work_per_step": {"random_measurements": int(work[4]), "rowsum_rows": int(work[5]),
                           "replay_rowsum_rows": int(work[8]), "replay_walked_rows": int(work[9]),
+                          "replay_rows_by_testing": int(work[10]), "replay_events_by_testing": int(work[11]),
                           "deterministic_measurements": int(work[2] + work[6]),
                           "multiplied_rows": int(work[3]), "chain_rounds": int(work[0]),
                           "noise_events": int(work[7])},

@@ -169,8 +169,10 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
  * (targets touching many rows), [2] measurements deterministic at layer start, [3] stabilizer
  * rows multiplied by deterministic reductions, [4] random measurements, [5] stabilizer rows
  * updated by rowsum, [6] measurements found deterministic inside the chain, [7] noise events,
- * [8] destabilizer rows updated by rowsum (replay), [9] destabilizer rows the replay walked.
- * ncounters <= 10.  Synchronizes the stream. */
+ * [8] destabilizer rows updated by rowsum (replay), [9] destabilizer rows the replay walked,
+ * [10] of those, rows it replayed by testing each run target (a pending list overflowed or
+ * the lists did not fit), [11] rowsums and replacements in those rows.
+ * ncounters <= 12.  Synchronizes the stream. */
 int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 
 /* Per-kernel device timing with HIP events recorded on the context's stream around every
@@ -246,7 +248,7 @@ int stab_batch_get_tableau(stab_batch *batch, int32_t circuit, uint8_t *x, uint8
  * [6] bytes the measurements must move (target columns at one 8-byte word per row, pivot
  * row, rowsum rows read and written, row moves; multiplied rows read), [7] bytes of the
  * band passes (every row read, and written when a gate changed x|z); the others stay 0.
- * ncounters <= 10. */
+ * ncounters <= 12. */
 int stab_batch_get_counters(stab_batch *batch, uint64_t *counters, int32_t ncounters);
 
 /* Pairwise commutation of Pauli strings, the grouping check of Sec. 3.2: strings A_i

@@ -35,6 +35,7 @@ constexpr int kMCap = 256;                // rows listed per deterministic measu
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
 constexpr int kReplayThreads = 512;
+constexpr int kReplayStatic = 512;        // bound on k_replay's static LDS
 constexpr int kNumKernels = 10;           // timing ids (include/stab.h)
 
 // 32-bit words of the segment kernel's LDS for one half-band (before the per-shot accumulators)
@@ -103,6 +104,7 @@ struct stab_ctx {
     int* d_tmap = nullptr;
     DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed, pend;
     DevBuf plog_p, plog_row, plog_rs, plog_rd, ran;   // pivot log of the random chain
+    DevBuf plist, pcnt, povf;                        // pending targets with x in each pivot
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing (stab_set_timing)
     bool timing = false;
@@ -228,6 +230,14 @@ int tcollect(stab_ctx* ctx)
     ctx->evkind.clear();
     ctx->evused = 0;
     return STAB_OK;
+}
+
+// The replay instantiated for the row's words per lane.
+using ReplayFn = decltype(&k_replay<1>);
+static ReplayFn replay_kernel(int Wc)
+{
+    const int wpl = (Wc + 63) / 64;
+    return wpl <= 1 ? k_replay<1> : wpl == 2 ? k_replay<2> : wpl == 3 ? k_replay<3> : k_replay<4>;
 }
 
 #define TIMED(ctx, kind, launch)                 \
@@ -455,6 +465,10 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     }
     (void)hipFuncSetAttribute((const void*)k_segment, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_replay<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_replay<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_replay<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_replay<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipGetLastError();
 
     bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
@@ -486,7 +500,8 @@ void stab_destroy(stab_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount, &ctx->obuf,
                       &ctx->events, &ctx->record, &ctx->packed, &ctx->pend, &ctx->plog_p,
-                      &ctx->plog_row, &ctx->plog_rs, &ctx->plog_rd, &ctx->ran};
+                      &ctx->plog_row, &ctx->plog_rs, &ctx->plog_rd, &ctx->ran, &ctx->plist,
+                      &ctx->pcnt, &ctx->povf};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
@@ -610,7 +625,9 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))) ||
         (rc = ensure(ctx->plog_p, (size_t)g.S * K * 4)) || (rc = ensure(ctx->plog_rs, (size_t)g.S * K * 4)) ||
         (rc = ensure(ctx->plog_row, (size_t)g.S * K * g.RS * 8)) ||
-        (rc = ensure(ctx->plog_rd, (size_t)g.S * K * ((g.bpc + 63) / 64) * 8)) || (rc = ensure(ctx->ran, 4)))
+        (rc = ensure(ctx->plog_rd, (size_t)g.S * K * ((g.bpc + 63) / 64) * 8)) || (rc = ensure(ctx->ran, 4)) ||
+        (rc = ensure(ctx->plist, (size_t)g.S * K * kPListCap * 2)) || (rc = ensure(ctx->pcnt, (size_t)g.S * K * 4)) ||
+        (rc = ensure(ctx->povf, (size_t)g.S * 4)))
         return rc;
     uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
     uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
@@ -628,9 +645,19 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     const int lds_rd = (seg_acc <= ctx->max_lds / 2 || (seg_base > ctx->max_lds / 2 && seg_acc <= ctx->max_lds)) ? 1 : 0;
     const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 4;
     const size_t chain_lds = (size_t)chain_lds_layout(g).total;
-    if (chain_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
-    const size_t replay_lds = (size_t)(kReplayThreads / 64) * ((g.bpc + 63) / 64) * 8 + K * 4;
-    if (replay_lds > (size_t)ctx->max_lds) return fail(STAB_ERANGE, "too many shots per copy for the replay kernel");
+    if (chain_lds + kReplayStatic > (size_t)ctx->max_lds)   // (a bound on its static LDS too)
+        return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
+    // the replay's list form when its fixed part leaves room for list entries in LDS
+    const ReplayLds RL = replay_lds_layout((int)K, (g.bpc + 63) / 64, kReplayThreads / 64);
+    // (kReplayStatic bytes of the block's LDS are its own __shared__ variables)
+    int ent_cap = -1;
+    size_t replay_lds = (size_t)RL.small_bytes;
+    const int replay_room = ctx->max_lds - kReplayStatic;
+    if (replay_walk_fits((int)K) && RL.fixed_bytes + 2 * 1024 <= replay_room) {
+        ent_cap = std::min((replay_room - RL.fixed_bytes) / 2, (int)K * kPListCap);
+        replay_lds = (size_t)RL.fixed_bytes + 2 * (size_t)ent_cap;
+    }
+    if (replay_lds > (size_t)replay_room) return fail(STAB_ERANGE, "too many shots per copy for the replay kernel");
     int* plog_p = (int*)ctx->plog_p.p;
     int* plog_rs = (int*)ctx->plog_rs.p;
     uint64_t* plog_row = (uint64_t*)ctx->plog_row.p;
@@ -685,13 +712,14 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               ctx->d_tmap, (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
-                              m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, obuf, ctx->d_err,
-                              ctx->d_counters)));
+                              m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
+                              (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
             // destabilizer updates of the run targets, then fresh columns of the final tableau
             // (skipped on the device when nothing ran)
-            TIMED(ctx, 8, (k_replay<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
+            TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
-                              plog_rs, plog_rd, ctx->d_err, ctx->d_counters)));
+                              plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
+                              (const int*)ctx->povf.p, ent_cap, ctx->d_err, ctx->d_counters)));
             {
                 SegArgs a{};
                 a.items = P->d_items;

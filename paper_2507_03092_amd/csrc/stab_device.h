@@ -34,7 +34,7 @@ struct NoiseDesc {
 
 // Work counters are striped over this many addresses (by block) to keep atomics uncontended.
 constexpr int kCounterStripes = 32;
-constexpr int kNumCounters = 10;
+constexpr int kNumCounters = 12;
 
 __device__ __forceinline__ void count_add(unsigned long long* counters, int idx, unsigned long long v)
 {
@@ -48,6 +48,7 @@ constexpr int kRCap = 128;
 constexpr int kWide = 4;
 constexpr int kAnalyze = 16;     // window entries (re)analysed per round, at most
 constexpr int kAffCap = 1024;    // column-upkeep work list of a wide batch
+constexpr int kPListCap = 16;    // pending targets listed per run target (more: replay walks rows)
 
 // Dynamic LDS layout of the chain kernel (byte offsets), shared by host and device.
 struct ChainLds {

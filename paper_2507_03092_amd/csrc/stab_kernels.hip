@@ -747,12 +747,24 @@ struct ChainCtx {
     uint64_t* lrd;           // its per-shot signs (nrdw words, bit b = shot b of the copy)
     int nrdw;
     int* ran;                // set to 1 when any random target of the layer runs
+    uint16_t* plist;         // per run target k: pending targets whose qubit has x in its pivot
+    int* pcnt;               // their count (kPListCap at most; *povf = 1 beyond)
+    int* povf;
     uint64_t seed, first_shot, instr;
     int pos_base;
     uint8_t* obuf;
     int* err;
     unsigned long long* counters;
 };
+
+// Pending target k2 has x in the pivot row of target k: the replay must flip that bit of a
+// destabilizer it multiplies by the pivot.
+__device__ __forceinline__ void plist_add(const ChainCtx& c, int k, int k2)
+{
+    const int slot = atomicAdd(&c.pcnt[k], 1);
+    if (slot < kPListCap) c.plist[(size_t)k * kPListCap + slot] = (uint16_t)k2;
+    else *c.povf = 1;
+}
 
 // Outcome draw of target k for global shot index b.
 __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
@@ -883,7 +895,7 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
             const int bit = ctz64(bits);
             bits &= bits - 1;
             const int k2 = c.tm[cw * 64 + bit];
-            if (k2 < 0) continue;
+            if (k2 < 0 || k2 == k) continue;
             if (aff) {
                 const int slot = atomicAdd(aff_n, 1);
                 if (slot < kAffCap) {
@@ -893,6 +905,7 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
                     continue;
                 }
             }
+            plist_add(c, k, k2);
             unsigned long long* X2 = (unsigned long long*)(c.X + k2);
             uint64_t m = 0;
             int wc = -1;
@@ -1051,7 +1064,8 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
             const int bit = ctz64(bits);
             bits &= bits - 1;
             const int k2 = c.tm[j * 64 + bit];
-            if (k2 < 0) continue;
+            if (k2 < 0 || k2 == k) continue;
+            plist_add(c, k, k2);
             uint64_t* X2 = X + k2;
             for (int t = 0; t < nnz; ++t) X2[(size_t)(Wr + nz[t]) * K] ^= sM[nz[t]];
             X2[(size_t)(Wr + wq) * K] &= ~bq;
@@ -1087,7 +1101,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
         int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
         int* __restrict__ plog_p, uint64_t* __restrict__ plog_row, int* __restrict__ plog_rs,
-        uint64_t* __restrict__ plog_rd, int* __restrict__ ran, uint8_t* __restrict__ obuf,
+        uint64_t* __restrict__ plog_rd, int* __restrict__ ran, uint16_t* __restrict__ plist,
+        int* __restrict__ pcnt, int* __restrict__ povf, uint8_t* __restrict__ obuf,
         int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t sm[];
@@ -1131,6 +1146,9 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.lrs = plog_rs + (size_t)s * K;
     c.lrd = plog_rd + (size_t)s * K * c.nrdw;
     c.ran = ran;
+    c.plist = plist + (size_t)s * K * kPListCap;
+    c.pcnt = pcnt + (size_t)s * K;
+    c.povf = povf + s;
     c.seed = seed;
     c.first_shot = first_shot;
     c.instr = instr;
@@ -1143,7 +1161,11 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* cl = cls + (size_t)s * K;
 
     // no target of this layer has run yet (the replay reads the log)
-    for (int k = tid; k < K; k += nt) c.lp[k] = -1;
+    for (int k = tid; k < K; k += nt) {
+        c.lp[k] = -1;
+        c.pcnt[k] = 0;
+    }
+    if (tid == 0) *c.povf = 0;
     // pending list: random-at-start targets in op order (stable compaction)
     int base = 0;
     for (int k0 = 0; k0 < K; k0 += nt) {
@@ -1401,6 +1423,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 } else {
                     const int ip = spiv[wpos[selpos[j]]];
                     atomicAnd(&X2[(size_t)(g.Wr + (ip >> 6)) * K], ~(1ull << (ip & 63)));
+                    plist_add(c, sk[wpos[selpos[j]]], k2);
                 }
             }
         } else {
@@ -1435,19 +1458,87 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
 // Destabilizer replay of a measurement layer: grid (Wr destabilizer bands, S copies), 512
 // threads.  In op order, every target the chain ran did, to each destabilizer D with x at its
 // qubit, rowsum(D, P) with its old pivot row P (sign r_D <- r_D ^ r_P ^ (i-power / 2), the
-// per-shot parts XOR), and replaced its pivot's own destabilizer by P.  The pivots are logged,
-// so each destabilizer is replayed on its own: a wave holds D in registers and walks the
-// targets 64 at a time, testing D's x bit at each target's qubit (and whether D is that
-// target's pivot partner) with one ballot, applying the hits in order and testing again after
-// each.  Only rows with x at some run target at layer start, or partners, can be touched
-// (a row that is never touched keeps its x bits), so only those are walked.
+// per-shot parts XOR), and replaced its pivot's own destabilizer by P.  Each destabilizer is
+// replayed on its own, by one wave, the waves taking the band's touched rows one after the
+// other; only rows with x at some run target at layer start, or a pivot's partner, can be
+// touched (a row never touched keeps its x bits), so only those are.
+//
+// Which targets hit D depends only on D's x bits at the run targets' qubits, and applying P
+// flips exactly the bits of the pending targets the chain listed for P (a target run earlier
+// has no x in P: P commutes with its Z).  So a wave first walks D's hits with those bits in
+// registers (the band's x words at the run targets, transposed once per block so that row D's
+// bits are one LDS read per lane), producing D's ordered list of events; then it applies the
+// events to D's x and z words with kReplayAhead pivot rows in flight, summing the i-powers per
+// lane (every step's power is even, so the halves add); then it takes the signs of the events
+// after the last replacement, whose XOR does not depend on their order, in parallel over the
+// lanes.  When a pivot's list overflowed, or the lists do not fit in LDS, the wave instead
+// tests D's live bits 64 targets at a time and applies each hit before testing again.
 // ------------------------------------------------------------------------------------------
+constexpr int kReplayEvents = 512;     // events a wave collects before applying them
+constexpr int kReplayAhead = 6;        // pivot rows in flight per wave while events are applied
+constexpr int kReplayVW = 3;           // run-target bit words per lane in the walk
+constexpr int kReplayInline = 3;       // list entries kept in a target's descriptor
+
+// Dynamic LDS of the replay.  With lists (ent_cap >= 0): per-shot deltas, partner table, run
+// targets, then the transposed x bits (row-major, KW words per destabilizer of the band), the
+// run-target mask, per-wave event lists, one descriptor per target, then ent_cap list
+// entries of the long lists.  Without: the first three only.
+struct ReplayLds {
+    int acc, prow, rk, vt, exe, ev, desc, ent;      // byte offsets
+    int small_bytes;                                // end of the form without lists
+    int fixed_bytes;                                // end of the form with lists, before entries
+};
+
+__host__ __device__ inline ReplayLds replay_lds_layout(int K, int nrdw, int nwaves)
+{
+    const int KW = (K + 63) / 64;
+    ReplayLds L;
+    int o = 0;
+    L.acc = o; o += nwaves * nrdw * 8;
+    L.prow = o; o += 64 * 4;
+    L.rk = o; o += ((K * 4 + 7) / 8) * 8;
+    L.small_bytes = o;
+    L.vt = o; o += 64 * KW * 8;
+    L.exe = o; o += KW * 8;
+    L.ev = o; o += nwaves * kReplayEvents * 4;
+    L.desc = o; o += K * 8;
+    L.ent = o;
+    L.fixed_bytes = o;
+    return L;
+}
+
+// Whether the register walk covers K targets.
+__host__ __device__ inline bool replay_walk_fits(int K) { return (K + 63) / 64 <= 64 * kReplayVW; }
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Row words of this lane (word lane + 64 t, WPL slots).  No load is conditional, so that the
+// loads of rows in flight are waited for one by one: the last slot's lanes past Wc load word 0
+// instead (any address of the row does) and the caller masks them with tail_mask.
+template <int WPL>
+__device__ __forceinline__ void replay_load(const uint64_t* row, int Wc, int lane, uint64_t* x, uint64_t* z)
+{
+#pragma unroll
+    for (int t = 0; t < WPL; ++t) {
+        const int cw = (t < WPL - 1 || lane + 64 * t < Wc) ? lane + 64 * t : 0;
+        x[t] = row[cw];
+        z[t] = row[Wc + cw];
+    }
+}
+
+template <int WPL>
 __global__ void __launch_bounds__(512)
 k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
          const uint64_t* __restrict__ Xcol, int K, const int* __restrict__ tq,
          const int* __restrict__ plog_p, const uint64_t* __restrict__ plog_row,
          const int* __restrict__ plog_rs, const uint64_t* __restrict__ plog_rd,
-         int* __restrict__ err, unsigned long long* __restrict__ counters)
+         const uint16_t* __restrict__ plist, const int* __restrict__ pcnt, const int* __restrict__ povf,
+         int ent_cap, int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t rsm[];
     const int band = blockIdx.x, s = blockIdx.y;
@@ -1455,23 +1546,43 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int Wc = g.Wc, RS = g.RS, NB = g.NB;
     const int nrdw = (g.bpc + 63) >> 6;
-    uint64_t* acc = rsm;                           // nwaves x nrdw per-shot sign deltas
-    int* rk = (int*)(rsm + (size_t)nwaves * nrdw); // run targets in op order (K entries)
-    __shared__ int s_cnt[16];
+    const int KW = (K + 63) >> 6;
+    const uint64_t tail = lane + 64 * (WPL - 1) < Wc ? ~0ull : 0ull;   // last slot in the row
+    const ReplayLds LL = replay_lds_layout(K, nrdw, nwaves);
+    char* base = (char*)rsm;
+    const bool lists = ent_cap >= 0;                     // LDS holds the list form
+    uint64_t* acc = (uint64_t*)(base + LL.acc);          // nwaves x nrdw per-shot sign deltas
+    int* prow = (int*)(base + LL.prow);                  // per row of the band: target it is the partner of
+    int* rk = (int*)(base + LL.rk);
+    uint64_t* vt = lists ? (uint64_t*)(base + LL.vt) : nullptr;    // [row][KW] x bits at run targets
+    uint64_t* exe = lists ? (uint64_t*)(base + LL.exe) : nullptr;  // run targets
+    int* evs = lists ? (int*)(base + LL.ev) : nullptr;
+    uint64_t* desc = lists ? (uint64_t*)(base + LL.desc) : nullptr;
+    uint16_t* ent = lists ? (uint16_t*)(base + LL.ent) : nullptr;
+    __shared__ int s_cnt[16], s_crow[64], s_ncand, s_next;
     __shared__ unsigned long long s_cand;
     const int* lp = plog_p + (size_t)s * K;
-    const uint64_t* X = Xcol + (size_t)s * NB * K + (size_t)band * K;   // this band's destabilizer words
+    const uint16_t* pl = plist + (size_t)s * K * kPListCap;
+    const int* pc = pcnt + (size_t)s * K;
+    const uint64_t* X = Xcol + (size_t)s * NB * K + (size_t)band * K;
     uint64_t* tb = tab + (size_t)s * 2 * g.NR * RS;
     uint64_t* rsc = rs + (size_t)s * NB;
 
-    // run targets, in op order (stable compaction)
-    int R = 0;
+    // run targets in op order (stable compaction) and their bitmask
+    if (tid == 0) {
+        s_cand = 0;
+        s_next = 0;
+    }
+    for (int r = tid; r < 64; r += nt) prow[r] = -1;
+    __syncthreads();
+    int R = 0, T = 0;
     for (int k0 = 0; k0 < K; k0 += nt) {
         const int k = k0 + tid;
         const bool f = k < K && lp[k] >= 0;
         const uint64_t m = __ballot(f);
         const int rank = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) s_cnt[wave] = __popcll(m);
+        if (lists && lane == 0 && k0 + wave * 64 < K) exe[(k0 >> 6) + wave] = m;
         __syncthreads();
         int before = 0, total = 0;
         for (int w = 0; w < nwaves; ++w) {
@@ -1483,97 +1594,291 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
         __syncthreads();
     }
     if (R == 0) return;
-    // candidate rows of the band
-    if (tid == 0) s_cand = 0;
-    __syncthreads();
     uint64_t cand = 0;
-    for (int j = tid; j < R; j += nt) {
-        const int k = rk[j];
-        cand |= X[k];
-        const int p = lp[k];
-        if ((p >> 6) == band) cand |= 1ull << (p & 63);
+    if (lists) {
+        // one descriptor per target: up to kReplayInline list entries inline (16 bits each) and
+        // the length in bits 48..52; a longer list lives in ent, its offset in bits 0..31
+        // (exclusive scan of the long lists' lengths)
+        for (int k0 = 0; k0 < K; k0 += nt) {
+            const int k = k0 + tid;
+            const bool f = k < K && ((exe[k >> 6] >> (k & 63)) & 1ull);
+            const int len = f ? min(pc[k], kPListCap) : 0;
+            const int big = len > kReplayInline ? len : 0;
+            const int ex = wave_excl_scan(big, lane);
+            const int ws = wave_sum(big);
+            if (lane == 0) s_cnt[wave] = ws;
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int w = 0; w < nwaves; ++w) {
+                if (w < wave) before += s_cnt[w];
+                total += s_cnt[w];
+            }
+            if (k < K) {
+                uint64_t d = (uint64_t)len << 48;
+                if (big) {
+                    const int o = T + before + ex;
+                    d |= (uint32_t)o;
+                    if (o + len <= ent_cap)
+                        for (int e = 0; e < len; ++e) ent[o + e] = pl[(size_t)k * kPListCap + e];
+                } else {
+                    for (int e = 0; e < len; ++e) d |= (uint64_t)pl[(size_t)k * kPListCap + e] << (16 * e);
+                }
+                desc[k] = d;
+            }
+            T += total;
+            __syncthreads();
+        }
+        // the band's x bits at the run targets, transposed: lane r of chunk w gets row r's
+        // bits at targets 64w..64w+63
+        uint64_t any = 0;
+        for (int w = wave; w < KW; w += nwaves) {
+            const int k = w * 64 + lane;
+            const bool f = k < K && ((exe[w] >> lane) & 1ull);
+            const uint64_t t = transpose64(f ? X[k] : 0ull, lane);
+            vt[(size_t)lane * KW + w] = t;
+            any |= t;
+        }
+        cand = __ballot(any != 0);
+        for (int j = tid; j < R; j += nt) {
+            const int p = lp[rk[j]];
+            if ((p >> 6) == band) {
+                cand |= 1ull << (p & 63);
+                prow[p & 63] = rk[j];
+            }
+        }
+    } else {
+        for (int j = tid; j < R; j += nt) {
+            const int k = rk[j];
+            cand |= X[k];
+            const int p = lp[k];
+            if ((p >> 6) == band) {
+                cand |= 1ull << (p & 63);
+                prow[p & 63] = k;
+            }
+        }
     }
     cand = wave_or(cand);
     if (lane == 0 && cand) atomicOr(&s_cand, (unsigned long long)cand);
     __syncthreads();
+    if (tid == 0) {
+        uint64_t c = s_cand;
+        int nc = 0;
+        while (c) {
+            s_crow[nc++] = ctz64(c);
+            c &= c - 1;
+        }
+        s_ncand = nc;
+    }
+    __syncthreads();
+    const bool walk = lists && povf[s] == 0 && T <= ent_cap && replay_walk_fits(K);
+    const int ncand = s_ncand;
+
     uint64_t* myacc = acc + (size_t)wave * nrdw;
-    uint64_t rem = s_cand;
-    int idx = 0, applied = 0;
-    while (rem) {
-        const int r = ctz64(rem);
-        rem &= rem - 1;
-        if ((idx++ % nwaves) != wave) continue;
+    int* ev = lists ? evs + (size_t)wave * kReplayEvents : nullptr;
+    uint64_t er[kReplayVW];                              // run-target bits, word lane + 64 t
+#pragma unroll
+    for (int t = 0; t < kReplayVW; ++t) {
+        const int w = lane + 64 * t;
+        er[t] = (walk && w < KW) ? exe[w] : 0ull;
+    }
+    int nrows = 0, applied = 0, trows = 0, tev = 0;
+    while (true) {
+        int j = 0;
+        if (lane == 0) j = atomicAdd(&s_next, 1);
+        j = __shfl(j, 0, 64);
+        if (j >= ncand) break;
+        ++nrows;
+        const int r = s_crow[j];
         const int i = band * 64 + r;                   // destabilizer index
         uint64_t* row = tb + (size_t)i * RS;
-        uint64_t x[kMaxWordsPerLane], z[kMaxWordsPerLane];
-        load_row_lane(row, Wc, lane, x, z);
+        uint64_t x[WPL], z[WPL];
+        replay_load<WPL>(row, Wc, lane, x, z);
+        x[WPL - 1] &= tail;
+        z[WPL - 1] &= tail;
         int sh = (int)((rsc[band] >> r) & 1ull);
         const int sh0 = sh;
         for (int u = lane; u < nrdw; u += 64) myacc[u] = 0;
         bool mod = false;
-        for (int j0 = 0; j0 < R; j0 += 64) {
-            const int jj = j0 + lane;
-            int k = 0, a = 0, p = -1;
-            if (jj < R) {
-                k = rk[jj];
-                a = tq[k];
-                p = lp[k];
+        int G = 0;                                     // i-powers since the last replacement, per lane
+        // D := P_kk, signs included (the per-shot deltas make rd's bits equal P's)
+        auto replace_signs = [&](int kk) {
+            const uint64_t* Pd = plog_rd + ((size_t)s * K + kk) * nrdw;
+            sh = plog_rs[(size_t)s * K + kk];
+            for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+                const int b = b0 + lane;
+                const bool cur = b < g.bpc && ((rd[(size_t)(s * g.bpc + b) * NB + band] >> r) & 1ull);
+                const uint64_t m = __ballot(cur);
+                if (lane == 0) myacc[b0 >> 6] = m ^ Pd[b0 >> 6];
             }
-            int from = 0;
-            while (true) {
-                // D's x bit at each target's qubit (word a >> 6 lives in lane (a >> 6) & 63)
-                const int wa = a >> 6, src = wa & 63, slot = wa >> 6;
-                uint64_t v = 0;
+        };
+        // x and z words of one event: replace (G so far applies to the row being replaced) or
+        // multiply in
+        // (the pivot row's last slot is masked here, at use)
+        auto step = [&](bool repl, const uint64_t* px, const uint64_t* pz) {
+            if (repl) {
+                const int Gs = wave_sum(G);
+                if (lane == 0 && (Gs & 1)) atomicOr(err, 8);
 #pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                    const uint64_t o = shfl_u64(x[t], src);
-                    if (slot == t) v = o;
+                for (int t = 0; t < WPL; ++t) {
+                    const uint64_t m = t == WPL - 1 ? tail : ~0ull;
+                    x[t] = px[t] & m;
+                    z[t] = pz[t] & m;
                 }
-                const bool hit = jj < R && lane >= from && ((((v >> (a & 63)) & 1ull) != 0) || p == i);
-                const uint64_t hm = __ballot(hit);
-                if (!hm) break;
-                const int l = ctz64(hm);
-                const int kk = __shfl(k, l, 64), pk = __shfl(p, l, 64);
-                const uint64_t* P = plog_row + ((size_t)s * K + kk) * RS;
-                const uint64_t* Pd = plog_rd + ((size_t)s * K + kk) * nrdw;
-                uint64_t px[kMaxWordsPerLane], pz[kMaxWordsPerLane];
-                load_row_lane(P, Wc, lane, px, pz);
-                const int rsp = plog_rs[(size_t)s * K + kk];
-                if (pk == i) {
-                    // the pivot's own destabilizer: replaced by the old pivot row
+                G = 0;
+            } else {
 #pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        x[t] = px[t];
-                        z[t] = pz[t];
-                    }
-                    sh = rsp;
-                    for (int b0 = 0; b0 < g.bpc; b0 += 64) {
-                        const int b = b0 + lane;
-                        const bool cur = b < g.bpc && ((rd[(size_t)(s * g.bpc + b) * NB + band] >> r) & 1ull);
-                        const uint64_t m = __ballot(cur);
-                        if (lane == 0) myacc[b0 >> 6] = m ^ Pd[b0 >> 6];
-                    }
-                } else {
-                    int G = 0;
-#pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        G += gsum(px[t], pz[t], x[t], z[t]);
-                        x[t] ^= px[t];
-                        z[t] ^= pz[t];
-                    }
-                    G = wave_sum(G);
-                    if (lane == 0 && (G & 1)) atomicOr(err, 8);
-                    sh ^= rsp ^ ((G >> 1) & 1);
-                    for (int u = lane; u < nrdw; u += 64) myacc[u] ^= Pd[u];
-                    ++applied;
+                for (int t = 0; t < WPL; ++t) {
+                    const uint64_t m = t == WPL - 1 ? tail : ~0ull;
+                    const uint64_t a = px[t] & m, b = pz[t] & m;
+                    G += gsum(a, b, x[t], z[t]);
+                    x[t] ^= a;
+                    z[t] ^= b;
                 }
+                ++applied;
+            }
+        };
+        if (walk) {
+            uint64_t vr[kReplayVW];
+#pragma unroll
+            for (int t = 0; t < kReplayVW; ++t) {
+                const int w = lane + 64 * t;
+                vr[t] = w < KW ? vt[(size_t)r * KW + w] : 0ull;
+            }
+            const int pk = prow[r];
+            int pos = 0;
+            bool more = true;
+            while (more) {
+                // walk: collect up to kReplayEvents events
+                int nev = 0, lastrep = -1;
+                while (nev < kReplayEvents) {
+                    // next set bit of vr at >= pos: the first lane of the first slot with one
+                    const int pw = pos >> 6;
+                    int nb = 0x7fffffff;
+#pragma unroll
+                    for (int t = 0; t < kReplayVW; ++t) {
+                        const int w = lane + 64 * t;
+                        uint64_t m = vr[t];
+                        if (w < pw) m = 0;
+                        else if (w == pw) m &= ~0ull << (pos & 63);
+                        const uint64_t bal = __ballot(m != 0ull);
+                        if (nb == 0x7fffffff && bal) {
+                            const int l = ctz64(bal);
+                            nb = (l + 64 * t) * 64 + ctz64(readlane_u64(m, l));
+                        }
+                    }
+                    int kk;
+                    bool repl;
+                    if (pk >= pos && pk <= nb) {          // D is this target's partner: replaced
+                        kk = pk;
+                        repl = true;
+                    } else if (nb != 0x7fffffff) {
+                        kk = nb;
+                        repl = false;
+                    } else {
+                        more = false;
+                        break;
+                    }
+                    if (lane == 0) ev[nev] = repl ? (kk | (1 << 30)) : kk;
+                    if (repl) {
+                        lastrep = nev;
+#pragma unroll
+                        for (int t = 0; t < kReplayVW; ++t)
+                            if (lane + 64 * t >= (kk >> 6)) vr[t] = 0;
+                    }
+                    ++nev;
+                    // D's x bits at later run targets: flip (multiply) or become P's (replace)
+                    const uint64_t d = desc[kk];
+                    const int len = (int)((d >> 48) & 31);
+                    for (int e = 0; e < len; ++e) {
+                        const int k2 = len <= kReplayInline ? (int)((d >> (16 * e)) & 0xffff)
+                                                            : (int)ent[(uint32_t)d + e];
+                        const uint64_t bit = (lane == ((k2 >> 6) & 63)) ? 1ull << (k2 & 63) : 0ull;
+#pragma unroll
+                        for (int t = 0; t < kReplayVW; ++t)
+                            if ((k2 >> 12) == t) vr[t] ^= bit & er[t];
+                    }
+                    pos = kk + 1;
+                }
+                if (nev == 0) break;
                 mod = true;
-                from = l + 1;
+                // apply in order, the next kReplayAhead pivot rows in flight (a ring of register
+                // buffers rotated by the unrolled loop; loads past the end repeat the last row)
+                const uint64_t* prow0 = plog_row + (size_t)s * K * RS;
+                uint64_t px[kReplayAhead][WPL], pz[kReplayAhead][WPL];
+#pragma unroll
+                for (int u = 0; u < kReplayAhead; ++u)
+                    replay_load<WPL>(prow0 + (size_t)(ev[min(u, nev - 1)] & 0x3fffffff) * RS, Wc, lane, px[u], pz[u]);
+                for (int e0 = 0; e0 < nev; e0 += kReplayAhead) {
+#pragma unroll
+                    for (int u = 0; u < kReplayAhead; ++u) {
+                        const int e = e0 + u;
+                        if (e < nev) step((ev[e] >> 30) & 1, px[u], pz[u]);
+                        const int en = min(e + kReplayAhead, nev - 1);
+                        replay_load<WPL>(prow0 + (size_t)(ev[en] & 0x3fffffff) * RS, Wc, lane, px[u], pz[u]);
+                    }
+                }
+                // signs: from the last replacement on (XOR over events, in any order)
+                if (lastrep >= 0) replace_signs(ev[lastrep] & 0x3fffffff);
+                int par = 0;
+                for (int e = lastrep + 1 + lane; e < nev; e += 64)
+                    par ^= plog_rs[(size_t)s * K + (ev[e] & 0x3fffffff)];
+                sh ^= __popcll(__ballot(par & 1)) & 1;
+                for (int u = 0; u < nrdw; ++u) {
+                    uint64_t a = 0;
+                    for (int e = lastrep + 1 + lane; e < nev; e += 64)
+                        a ^= plog_rd[((size_t)s * K + (ev[e] & 0x3fffffff)) * nrdw + u];
+                    a = wave_xor(a);
+                    if (lane == 0) myacc[u] ^= a;
+                }
+            }
+        } else {
+            // walk by testing D's live x bits 64 run targets at a time
+            ++trows;
+            for (int j0 = 0; j0 < R; j0 += 64) {
+                const int jj = j0 + lane;
+                int k = 0, a = 0, p = -1;
+                if (jj < R) {
+                    k = rk[jj];
+                    a = tq[k];
+                    p = lp[k];
+                }
+                int from = 0;
+                while (true) {
+                    const int wa = a >> 6, src = wa & 63, slot = wa >> 6;
+                    uint64_t vv = 0;
+#pragma unroll
+                    for (int t = 0; t < WPL; ++t) {
+                        const uint64_t o = shfl_u64(x[t], src);
+                        if (slot == t) vv = o;
+                    }
+                    const bool hit = jj < R && lane >= from && ((((vv >> (a & 63)) & 1ull) != 0) || p == i);
+                    const uint64_t hm = __ballot(hit);
+                    if (!hm) break;
+                    const int l = ctz64(hm);
+                    const int kk = __shfl(k, l, 64), pkk = __shfl(p, l, 64);
+                    uint64_t px[WPL], pz[WPL];
+                    replay_load<WPL>(plog_row + ((size_t)s * K + kk) * RS, Wc, lane, px, pz);
+                    const bool repl = pkk == i;
+                    step(repl, px, pz);
+                    if (repl) {
+                        replace_signs(kk);
+                    } else {
+                        sh ^= plog_rs[(size_t)s * K + kk];
+                        const uint64_t* Pd = plog_rd + ((size_t)s * K + kk) * nrdw;
+                        for (int u = lane; u < nrdw; u += 64) myacc[u] ^= Pd[u];
+                    }
+                    mod = true;
+                    ++tev;
+                    from = l + 1;
+                }
             }
         }
         if (mod) {
+            const int Gs = wave_sum(G);
+            if (lane == 0 && (Gs & 1)) atomicOr(err, 8);
+            sh ^= (Gs >> 1) & 1;
 #pragma unroll
-            for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            for (int t = 0; t < WPL; ++t) {
                 const int cw = lane + 64 * t;
                 if (cw < Wc) {
                     row[cw] = x[t];
@@ -1586,9 +1891,11 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
                     atomicXor((unsigned long long*)&rd[(size_t)(s * g.bpc + b) * NB + band], 1ull << r);
         }
     }
-    if (lane == 0 && idx) {
+    if (lane == 0 && nrows) {
         if (applied) count_add(counters, 8, (unsigned long long)applied);
-        if (wave == 0) count_add(counters, 9, (unsigned long long)idx);
+        count_add(counters, 9, (unsigned long long)nrows);
+        if (trows) count_add(counters, 10, (unsigned long long)trows);
+        if (tev) count_add(counters, 11, (unsigned long long)tev);
     }
 }
 

@@ -243,8 +243,8 @@ class Context:
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def counters(self) -> np.ndarray:
-        c = np.zeros(10, dtype=np.uint64)
-        _check(lib().stab_get_counters(self.h, _ptr(c), 10))
+        c = np.zeros(12, dtype=np.uint64)
+        _check(lib().stab_get_counters(self.h, _ptr(c), 12))
         return c
 
 
