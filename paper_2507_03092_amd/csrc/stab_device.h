@@ -9,6 +9,7 @@ namespace stabdev {
 constexpr int kMaxWordsPerLane = 4;
 // Most sign/band words (2 * ceil(n/64)) a lane of the chain's analysis wave reads.
 constexpr int kMaxBandsPerLane = 5;
+constexpr int kMaxStabBandsPerLane = (32 * kMaxBandsPerLane + 63) / 64;   // the stabilizer half
 
 struct Geom {
     int n;    // qubits

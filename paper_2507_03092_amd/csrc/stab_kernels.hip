@@ -128,6 +128,14 @@ __device__ __forceinline__ int gsum(uint64_t x1, uint64_t z1, uint64_t x2, uint6
 
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
 
+// Lane l's 64-bit value, l uniform (scalar result).
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // v from lane (lane ^ j), j in {1, 2, 4, 8, 16}, without the LDS crossbar: DPP quad permutes
 // and row mirrors for j <= 8 (xor 4 = half-mirror then quad xor 3; xor 8 = mirror then
 // half-mirror) and the gfx950 permlane16 swap for j = 16.  Every lane must be active.
@@ -1218,20 +1226,37 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         for (int a_i = wave; a_i < s_na; a_i += nwaves) {
             const int sl = alist[a_i];
             const int k = sk[sl];
-            // all column words at once (NB <= 64 * kMaxBandsPerLane); pivot from the stabilizer half
-            uint64_t cw[kMaxBandsPerLane];
+            // the stabilizer half of the column (band Wr + lane + 64 u), all words at once
+            uint64_t cw[kMaxStabBandsPerLane];
 #pragma unroll
-            for (int u = 0; u < kMaxBandsPerLane; ++u) {
+            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
                 const int w = lane + 64 * u;
-                cw[u] = (w < g.NB) ? c.X[(size_t)w * K + k] : 0ull;
+                cw[u] = (w < g.Wr) ? c.X[(size_t)(g.Wr + w) * K + k] : 0ull;
             }
-            int pv = INT_MAX;
+            // pivot = first set bit in band order, the other set bits are the rowsum rows
+            // (ascending); the few nonzero words are read out one by one with scalar loops
+            int pv = INT_MAX, cnt = 0;
 #pragma unroll
-            for (int u = 0; u < kMaxBandsPerLane; ++u) {
-                const int w = lane + 64 * u;
-                if (w >= g.Wr && w < g.NB && cw[u]) pv = min(pv, (w - g.Wr) * 64 + ctz64(cw[u]));
+            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+                uint64_t lanes = __ballot(cw[u] != 0ull);
+                while (lanes) {
+                    const int l = ctz64(lanes);
+                    lanes &= lanes - 1;
+                    uint64_t v = readlane_u64(cw[u], l);
+                    const int wb = l + 64 * u;                 // stabilizer band
+                    if (pv == INT_MAX) {
+                        pv = wb * 64 + ctz64(v);
+                        v &= v - 1;
+                    }
+                    while (v && cnt < kRCap) {
+                        const int bit = ctz64(v);
+                        v &= v - 1;
+                        if (lane == 0) srows[sl * kRCap + cnt] = (g.Wr + wb) * 64 + bit;
+                        ++cnt;
+                    }
+                    cnt += __popcll(v);                        // beyond kRCap: counted only
+                }
             }
-            pv = wave_min(pv);
             if (pv == INT_MAX) {
                 // deterministic now: evaluated after the chain
                 if (lane == 0) {
@@ -1239,25 +1264,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                     cl[k] = -2;
                 }
                 continue;
-            }
-            const int pw = pv >> 6;
-            const uint64_t pb = 1ull << (pv & 63);
-            int cnt = 0;
-            // the other stabilizer rows with x at the qubit
-#pragma unroll
-            for (int u = 0; u < kMaxBandsPerLane; ++u) {
-                const int w = lane + 64 * u;
-                uint64_t v = w >= g.Wr ? cw[u] : 0ull;
-                if (w == g.Wr + pw) v &= ~pb;
-                const int pc = __popcll(v);
-                int off = cnt + wave_excl_scan(pc, lane);
-                while (v) {
-                    const int bit = ctz64(v);
-                    v &= v - 1;
-                    if (off < kRCap) srows[sl * kRCap + off] = w * 64 + bit;
-                    ++off;
-                }
-                cnt += wave_sum(pc);
             }
             if (lane == 0) {
                 stype[sl] = cnt > kRCap ? T_BIG_RANDOM : T_RANDOM;
@@ -1295,57 +1301,45 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         __syncthreads();
         const int nw = s_nwin;
         if (nw == 0) break;
-        // ---- selection: only analysed entries before the first unknown or big one ----
+        // ---- selection, by wave 0 with one lane per window position t: only analysed
+        // entries before the first unknown or big one are eligible; an eligible entry runs iff
+        // it is the first owner of all its row pairs.  Entries sharing a pair with a selected
+        // one must be analysed again; big entries (incomplete row lists) whenever anything runs.
         if (wave == 0) {
-            const int ty = lane < nw ? stype[wpos[lane]] : T_UNKNOWN;
-            const uint64_t m = __ballot(ty == T_UNKNOWN || ty == T_BIG_RANDOM);
-            if (lane == 0) s_bar = m ? min(ctz64(m), nw) : nw;
+            const int t = lane;
+            const int sl = t < nw ? wpos[t] : 0;
+            const int ty = t < nw ? stype[sl] : T_UNKNOWN;
+            const uint64_t um = __ballot(ty == T_UNKNOWN || ty == T_BIG_RANDOM);
+            const int bar = um ? min(ctz64(um), nw) : nw;
+            const bool elig = t < bar;
+            const int cnt = (t < nw && ty == T_RANDOM) ? scnt[sl] : -1;
+            const int pv = cnt >= 0 ? spiv[sl] : 0;
+            const int* rw = srows + sl * kRCap;
+            if (elig)
+                for (int r = 0; r <= cnt; ++r) atomicMin(&owner[r < cnt ? rw[r] % g.NR : pv], t);
+            __builtin_amdgcn_wave_barrier();
+            bool ok = elig;
+            if (elig)
+                for (int r = 0; r <= cnt && ok; ++r)
+                    if (owner[r < cnt ? rw[r] % g.NR : pv] != t) ok = false;
+            const uint64_t selm = __ballot(ok);
+            if (t < nw) wsel[t] = ok ? 1 : 0;
+            bool st = false;
+            if (!ok && cnt >= 0)
+                for (int r = 0; r <= cnt && !st; ++r) {
+                    const int o = owner[r < cnt ? rw[r] % g.NR : pv];
+                    if (o != INT_MAX && o != t && ((selm >> o) & 1ull)) st = true;
+                }
+            if (t < nw && (st || (ty == T_BIG_RANDOM && bar > 0))) stype[sl] = T_UNKNOWN;
+            if (ok) selpos[__popcll(selm & ((1ull << lane) - 1ull))] = t;
+            if (lane == 0) {
+                s_bar = bar;
+                s_nsel = __popcll(selm);
+                s_aff = 0;
+            }
         }
         __syncthreads();
         const int bar = s_bar;
-        // first owner of every row pair among the eligible entries (one wave per entry)
-        for (int t = wave; t < bar; t += nwaves) {
-            const int sl = wpos[t], cnt = scnt[sl];
-            for (int r = lane; r <= cnt; r += 64)
-                atomicMin(&owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]], t);
-        }
-        __syncthreads();
-        // an eligible entry runs iff it owns all its pairs
-        for (int t = wave; t < nw; t += nwaves) {
-            bool ok = t < bar;
-            if (ok) {
-                const int sl = wpos[t], cnt = scnt[sl];
-                for (int r = lane; r <= cnt; r += 64)
-                    if (owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]] != t) ok = false;
-            }
-            const uint64_t bad = __ballot(!ok);
-            if (lane == 0) wsel[t] = bad ? 0 : 1;
-        }
-        __syncthreads();
-        // entries sharing a pair with a selected one must be analysed again; big entries
-        // (incomplete row lists) whenever anything runs
-        for (int t = wave; t < nw; t += nwaves) {
-            const int sl = wpos[t];
-            const int ty = stype[sl];
-            bool st = false;
-            if (!wsel[t] && ty == T_RANDOM) {
-                const int cnt = scnt[sl];
-                for (int r = lane; r <= cnt; r += 64) {
-                    const int o = owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]];
-                    if (o != INT_MAX && o != t && wsel[o]) st = true;
-                }
-            }
-            const uint64_t any = __ballot(st);
-            if (lane == 0 && (any || (ty == T_BIG_RANDOM && bar > 0))) stype[sl] = T_UNKNOWN;
-        }
-        if (wave == 0) {
-            const bool sel = lane < bar && wsel[lane];
-            const uint64_t m = __ballot(sel);
-            if (sel) selpos[__popcll(m & ((1ull << lane) - 1ull))] = lane;
-            if (lane == 0) s_nsel = __popcll(m);
-        }
-        if (tid == 0) s_aff = 0;
-        __syncthreads();
         const int nsel = s_nsel;
         // ---- execution ----
         if (bar == 0 && stype[wpos[0]] == T_BIG_RANDOM) {
@@ -1509,13 +1503,6 @@ __host__ __device__ inline ReplayLds replay_lds_layout(int K, int nrdw, int nwav
 
 // Whether the register walk covers K targets.
 __host__ __device__ inline bool replay_walk_fits(int K) { return (K + 63) / 64 <= 64 * kReplayVW; }
-
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // Row words of this lane (word lane + 64 t, WPL slots).  No load is conditional, so that the
 // loads of rows in flight are waited for one by one: the last slot's lanes past Wc load word 0
