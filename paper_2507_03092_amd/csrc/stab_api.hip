@@ -101,7 +101,6 @@ struct stab_ctx {
     int max_lds = kLdsBytes;
     int* d_err = nullptr;
     unsigned long long* d_counters = nullptr;
-    int* d_tmap = nullptr;
     DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed, pend;
     DevBuf plog_p, plog_row, plog_rs, plog_rd, ran;   // pivot log of the random chain
     DevBuf plist, pcnt, povf;                        // pending targets with x in each pivot
@@ -339,18 +338,27 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
             d.kind = (int)kind;
             d.toff = (int)noise_tg.size();
             d.units = units;
-            d.bucket = (int)noise.size();
+            // noise layers with no gate between them act on the same tableau: they share one
+            // event bucket (their events commute) and one item of the segment kernel
+            const bool join = seg.item_count > 0 && items.back().x == 1;
+            d.bucket = join ? items.back().w : (int)ev_base.size();
             noise_tg.insert(noise_tg.end(), t, t + nt);
             unit_start.push_back(seg.units);
             seg.units += units;
             seg.max_units = std::max(seg.max_units, units);
-            ev_base.push_back((int)seg.ev_cap);
-            seg.ev_cap += (long long)units * (kind == STAB_DEP2 ? 2 : 1) * g.B;
+            if (!join) ev_base.push_back((int)seg.ev_cap);
+            const long long cap = (long long)units * (kind == STAB_DEP2 ? 2 : 1) * g.B;
+            seg.ev_cap += cap;
             if (seg.ev_cap > (1ll << 31) - 1) return fail(STAB_ERANGE, "too many noise locations in one segment");
             noise.push_back(d);
             seg.noise_count++;
-            items.push_back(make_int4(1, 0, 0, d.bucket));
-            seg.item_count++;
+            if (join) {
+                items.back().z += (int)cap;
+            } else {
+                // {1, first event slot, event capacity, bucket}
+                items.push_back(make_int4(1, ev_base.back(), (int)cap, d.bucket));
+                seg.item_count++;
+            }
         } break;
         case STAB_M: case STAB_MR: case STAB_R: {
             uint32_t q = 0;
@@ -473,14 +481,12 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
 
     bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
               hipMalloc((void**)&ctx->d_counters, kNumCounters * kCounterStripes * sizeof(unsigned long long)) == hipSuccess &&
-              hipMalloc((void**)&ctx->d_tmap, (size_t)ctx->g.S * n * sizeof(int)) == hipSuccess &&
               hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
     if (!ok) {
         stab_destroy(ctx);
         return fail(STAB_ENOMEM, "device allocation failed");
     }
-    if (hipMemsetAsync(ctx->d_counters, 0, kNumCounters * kCounterStripes * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
-        hipMemsetAsync(ctx->d_tmap, 0xFF, (size_t)ctx->g.S * n * sizeof(int), ctx->stream) != hipSuccess) {
+    if (hipMemsetAsync(ctx->d_counters, 0, kNumCounters * kCounterStripes * sizeof(unsigned long long), ctx->stream) != hipSuccess) {
         stab_destroy(ctx);
         return fail(STAB_EDEVICE, "memset failed");
     }
@@ -506,7 +512,6 @@ void stab_destroy(stab_ctx* ctx)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
-    if (ctx->d_tmap) (void)hipFree(ctx->d_tmap);
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -711,7 +716,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             HIP_CHECK(ctx, hipMemsetAsync(ran, 0, sizeof(int), ctx->stream));
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
-                              ctx->d_tmap, (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
+                              (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
                               m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
                               (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
             // destabilizer updates of the run targets, then fresh columns of the final tableau

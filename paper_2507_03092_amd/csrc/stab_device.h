@@ -30,7 +30,7 @@ struct NoiseDesc {
     int kind;              // DEP1, DEP2 or PAULI1
     int toff;              // first target in the segment's noise target array
     int units;             // targets (DEP1, PAULI1) or pairs (DEP2)
-    int bucket;            // event bucket (= item.w of the noise layer)
+    int bucket;            // event bucket (= item.w of the noise item; consecutive noise layers share one)
 };
 
 // Work counters are striped over this many addresses (by block) to keep atomics uncontended.
@@ -59,6 +59,7 @@ struct ChainLds {
     int words;   // kWide x kRCap (word, mask) lists of the batch's rowsum rows
     int aff;     // kAffCap column-upkeep entries {code, flags, batch index}
     int win;     // window arrays: 9 x kWin ints + kWin x kRCap row indices
+    int tm;      // n int16: qubit -> pending target whose x column is kept, or -1
     int total;
 };
 
@@ -74,12 +75,13 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
     L.words = L.wide + kWide * g.RS * 8;
     L.aff = L.words + kWide * kRCap * 12;
     L.win = L.aff + kAffCap * 12;
-    L.total = L.win + (9 * kWin + kWin * kRCap) * 4;
+    L.tm = L.win + (9 * kWin + kWin * kRCap) * 4;
+    L.total = L.tm + align16i(g.n * 2);
     return L;
 }
 
 struct SegArgs {
-    const int4* items;     // {type (0 gates, 1 noise), first gate, gate count, bucket}
+    const int4* items;     // {0, first gate, gate count, -1} or {1, first event slot, event capacity, bucket}
     int nitems;
     const uint2* gates;    // {kind | q0 << 4, q1}
     const uint2* events;   // noise events {qubit | pauli << 28, shot}

@@ -256,7 +256,7 @@ k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int 
 // Segment kernel helpers.  Column j of a staged half-band: x word at
 // T[(j & 63) * RSP + (j >> 6)], z word at + Wc (32-bit words, one bit per staged row).
 // ------------------------------------------------------------------------------------------
-constexpr int kSegPrefetch = 8;   // gates / events per thread prefetched into registers
+constexpr int kSegPrefetch = 10;  // gates / events per thread prefetched into registers
 
 // Registers holding one item's gate or noise-event list (first kSegPrefetch * blockDim.x).
 struct ItemBuf {
@@ -275,17 +275,14 @@ __device__ __forceinline__ void fetch_item(const SegArgs& a, int it, int tid, in
     }
     const int4 item = a.items[it];
     b.type = item.x;
-    if (item.x == 0) {
-        b.src = a.gates + item.y;
-        b.count = item.z;
-    } else {
-        b.src = a.events + a.ev_base[item.w];
-        b.count = a.ev_count[item.w];
-    }
+    // gates: count known; events: the bucket's slots are read up to its capacity while its
+    // count is loaded (both in flight at once), and the count bounds their use
+    b.src = item.x == 0 ? a.gates + item.y : a.events + item.y;
+    b.count = item.x == 0 ? item.z : a.ev_count[item.w];
 #pragma unroll
     for (int u = 0; u < kSegPrefetch; ++u) {
         const int i = tid + u * nt;
-        if (i < b.count) b.v[u] = b.src[i];
+        if (i < item.z) b.v[u] = b.src[i];
     }
 }
 
@@ -357,6 +354,23 @@ __device__ __forceinline__ uint32_t transpose32(uint32_t v, int lane)
     return v;
 }
 
+// Transpose every 32x32 tile (column c of the 64 staged lanes) in place, four tiles per wave in
+// flight so that their LDS reads overlap.
+__device__ __forceinline__ void transpose_tiles(uint32_t* T, int RSP, int RS, int lane, int wave, int nwaves)
+{
+    int c = wave;
+    for (; c + 3 * nwaves < RS; c += 4 * nwaves) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = T[lane * RSP + c + u * nwaves];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = transpose32(v[u], lane);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) T[lane * RSP + c + u * nwaves] = v[u];
+    }
+    for (; c < RS; c += nwaves) T[lane * RSP + c] = transpose32(T[lane * RSP + c], lane);
+}
+
 // ------------------------------------------------------------------------------------------
 // Segment kernel: grid (2 * NB half-bands, S copies), 512 threads.  A block stages 32 rows
 // (half of a 64-row band) as 32-bit qubit-major words: row r's 64-bit word c is split into
@@ -417,11 +431,7 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
     if (a.lds_rd)
         for (int b = tid; b < g.bpc; b += nt) rdacc[b] = 0;
     __syncthreads();
-    for (int c = wave; c < RS; c += nwaves) {
-        uint32_t v = T[lane * RSP + c];
-        v = transpose32(v, lane);
-        T[lane * RSP + c] = v;
-    }
+    transpose_tiles(T, RSP, RS, lane, wave, nwaves);
     __syncthreads();
 
     uint32_t racc = 0;
@@ -456,11 +466,7 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
     }
     if (a.write_back) {
         __syncthreads();
-        for (int c = wave; c < RS; c += nwaves) {
-            uint32_t v = T[lane * RSP + c];
-            v = transpose32(v, lane);
-            T[lane * RSP + c] = v;
-        }
+        transpose_tiles(T, RSP, RS, lane, wave, nwaves);
         __syncthreads();
         ulonglong2* gw2 = (ulonglong2*)gb;
         for (int p = tid; p < npairs; p += nt) {
@@ -747,7 +753,7 @@ struct ChainCtx {
     uint64_t* Z;
     int K, s;
     const int* tq;
-    int* tm;                 // qubit -> pending target whose x column is kept, or -1
+    int16_t* tm;             // (LDS) qubit -> pending target whose x column is kept, or -1
     int* cl;                 // this copy's target classes (-2 marks "deterministic now")
     int* lp;                 // pivot log: stabilizer index of target k's pivot (-1: not run)
     uint64_t* lrow;          // old pivot row of target k (RS words)
@@ -785,12 +791,14 @@ __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
 // rowsum(i, p) for rows[r], r = r0, r0 + stride, ... < nrows, pivot row words in registers
 // (lane owns column words lane + 64 t).  Sign r_i <- r_i ^ r_p ^ (i-power / 2).  Loads of 4 rows
 // are issued together.
-__device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_t* zp, int rsp,
-                            const int* rows, int nrows, int r0, int stride, int lane)
+__device__ __forceinline__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_t* zp, int rsp,
+                                            const int* rows, int nrows, int r0, int stride, int lane)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, RS = g.RS;
     for (int rb = r0; rb < nrows; rb += 4 * stride) {
+        // 4 rows in flight; no load depends on the pivot row (lanes past Wc read word 0 and
+        // write nothing), so they overlap its load
         uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -798,10 +806,9 @@ __device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_
             const uint64_t* row = c.tb + (size_t)rows[min(r, nrows - 1)] * RS;
 #pragma unroll
             for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                const int cw = lane + 64 * t;
-                const bool ok = r < nrows && cw < Wc && (xp[t] | zp[t]);
-                rx[u][t] = ok ? row[cw] : 0ull;
-                rz[u][t] = ok ? row[Wc + cw] : 0ull;
+                const int cw = lane + 64 * t < Wc ? lane + 64 * t : 0;
+                rx[u][t] = row[cw];
+                rz[u][t] = row[Wc + cw];
             }
         }
 #pragma unroll
@@ -841,7 +848,8 @@ __device__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_
 // done in-wave otherwise or when the list is full.
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const int* rows, int nrows, int lane,
-                                int* aff = nullptr, int* aff_n = nullptr, int j = 0)
+                                int* aff = nullptr, int* aff_n = nullptr, int j = 0,
+                                bool have_rd0 = false, uint64_t rd0 = 0)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
@@ -870,7 +878,7 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         if (b < g.bpc) {
             const int gb = c.s * g.bpc + b;
             uint64_t* rdb = c.rd + (size_t)gb * NB;
-            rdp = ((rdb[Wr + wq] >> (ip & 63)) & 1ull) != 0;
+            rdp = (((b0 == 0 && have_rd0 ? rd0 : rdb[Wr + wq]) >> (ip & 63)) & 1ull) != 0;
             if (rdp) {
                 uint64_t m = 0;
                 int wc = -1;
@@ -894,17 +902,32 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         if (lane == 0) c.lrd[(size_t)k * c.nrdw + (b0 >> 6)] = m;
     }
     // x columns of pending targets: rows with x at the pivot's qubits flip there; p's x clears
+    auto upkeep = [&](int k2) {
+        unsigned long long* X2 = (unsigned long long*)(c.X + k2);
+        uint64_t m = 0;
+        int wc = -1;
+        for (int r = 0; r <= nrows; ++r) {
+            const int w = r < nrows ? rows[r] >> 6 : -2;
+            if (w != wc) {
+                if (m) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
+                wc = w;
+                m = 0;
+            }
+            if (r < nrows) m |= 1ull << (rows[r] & 63);
+        }
+        atomicAnd(&X2[(size_t)(Wr + wq) * K], ~(unsigned long long)bq);
+    };
+    if (aff) {
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-        const int cw = lane + 64 * t;
-        if (cw >= Wc) continue;
-        uint64_t bits = xp[t];
-        while (bits) {
-            const int bit = ctz64(bits);
-            bits &= bits - 1;
-            const int k2 = c.tm[cw * 64 + bit];
-            if (k2 < 0 || k2 == k) continue;
-            if (aff) {
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int cw = lane + 64 * t;
+            if (cw >= Wc) continue;
+            uint64_t bits = xp[t];
+            while (bits) {
+                const int bit = ctz64(bits);
+                bits &= bits - 1;
+                const int k2 = c.tm[cw * 64 + bit];
+                if (k2 < 0 || k2 == k) continue;
                 const int slot = atomicAdd(aff_n, 1);
                 if (slot < kAffCap) {
                     aff[3 * slot] = k2;
@@ -912,21 +935,37 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
                     aff[3 * slot + 2] = j;
                     continue;
                 }
+                plist_add(c, k, k2);
+                upkeep(k2);
             }
-            plist_add(c, k, k2);
-            unsigned long long* X2 = (unsigned long long*)(c.X + k2);
-            uint64_t m = 0;
-            int wc = -1;
-            for (int r = 0; r <= nrows; ++r) {
-                const int w = r < nrows ? rows[r] >> 6 : -2;
-                if (w != wc) {
-                    if (m) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
-                    wc = w;
-                    m = 0;
+        }
+    } else {
+        // this wave is the only writer of target k's list: slots by ballot rank, no atomics
+        int np = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int cw = lane + 64 * t;
+            uint64_t bits = cw < Wc ? xp[t] : 0ull;
+            while (__ballot(bits != 0ull)) {
+                int k2 = -1;
+                if (bits) {
+                    const int bit = ctz64(bits);
+                    bits &= bits - 1;
+                    k2 = c.tm[cw * 64 + bit];
                 }
-                if (r < nrows) m |= 1ull << (rows[r] & 63);
+                const bool hit = k2 >= 0 && k2 != k;
+                const uint64_t hm = __ballot(hit);
+                if (hit) {
+                    const int slot = np + __popcll(hm & ((1ull << lane) - 1ull));
+                    if (slot < kPListCap) c.plist[(size_t)k * kPListCap + slot] = (uint16_t)k2;
+                    upkeep(k2);
+                }
+                np += __popcll(hm);
             }
-            atomicAnd(&X2[(size_t)(Wr + wq) * K], ~(unsigned long long)bq);
+        }
+        if (lane == 0 && np) {
+            c.pcnt[k] = np;
+            if (np > kPListCap) *c.povf = 1;
         }
     }
 #pragma unroll
@@ -961,11 +1000,22 @@ __device__ __forceinline__ void load_row_lane(const uint64_t* row, int Wc, int l
 __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
 {
     const Geom& g = c.g;
+    // the pivot row, its signs and the first rowsum rows are all read at once
     uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
-    load_row_lane(c.tb + (size_t)(g.NR + ip) * g.RS, g.Wc, lane, xp, zp);
+    const uint64_t* prow = c.tb + (size_t)(g.NR + ip) * g.RS;
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int cw = lane + 64 * t < g.Wc ? lane + 64 * t : 0;
+        xp[t] = prow[cw];
+        zp[t] = prow[g.Wc + cw];
+    }
+    const uint64_t rd0 = lane < g.bpc ? c.rd[(size_t)(c.s * g.bpc + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
     const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+#pragma unroll
+    for (int t = 0; t < kMaxWordsPerLane; ++t)
+        if (lane + 64 * t >= g.Wc) xp[t] = zp[t] = 0ull;
     rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
-    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane);
+    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0);
 }
 
 // Whole block: one target with many stabilizer rows (dense tableaux).  Called by every thread.
@@ -1106,8 +1156,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
 __global__ void __launch_bounds__(512)
 k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
-        int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ tmap,
-        int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
+        int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
         int* __restrict__ plog_p, uint64_t* __restrict__ plog_row, int* __restrict__ plog_rs,
         uint64_t* __restrict__ plog_rd, int* __restrict__ ran, uint16_t* __restrict__ plist,
         int* __restrict__ pcnt, int* __restrict__ povf, uint8_t* __restrict__ obuf,
@@ -1146,7 +1195,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.K = K;
     c.s = s;
     c.tq = tq;
-    c.tm = tmap + (size_t)s * g.n;
+    c.tm = (int16_t*)((char*)sm + L.tm);
     c.cl = cls + (size_t)s * K;
     c.nrdw = (g.bpc + 63) >> 6;
     c.lp = plog_p + (size_t)s * K;
@@ -1165,7 +1214,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.err = err;
     c.counters = counters;
     int* pd = pend + (size_t)s * K;
-    int* tmw = tmap + (size_t)s * g.n;
     int* cl = cls + (size_t)s * K;
 
     // no target of this layer has run yet (the replay reads the log)
@@ -1195,7 +1243,10 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     const int npend = base;
     if (npend == 0) return;
     // column upkeep: the x columns of pending random targets
-    for (int k = tid; k < K; k += nt) tmw[tq[k]] = cl[k] >= 0 ? k : -1;
+    for (int q = tid; q < g.n; q += nt) c.tm[q] = -1;
+    __syncthreads();
+    for (int k = tid; k < K; k += nt)
+        if (cl[k] >= 0) c.tm[tq[k]] = (int16_t)k;
     for (int i = tid; i < g.NR; i += nt) owner[i] = INT_MAX;
     const int w0 = min(kWin, npend);
     for (int t = tid; t < w0; t += nt) {
@@ -1445,7 +1496,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         __syncthreads();
     }
     if (tid == 0) count_add(counters, 0, (unsigned long long)rounds);
-    for (int k = tid; k < K; k += nt) tmw[tq[k]] = -1;
 }
 
 // ------------------------------------------------------------------------------------------
