@@ -47,7 +47,7 @@ __device__ __forceinline__ void count_add(unsigned long long* counters, int idx,
 constexpr int kWin = 64;
 constexpr int kRCap = 128;
 constexpr int kWide = 4;
-constexpr int kAnalyze = 16;     // window entries (re)analysed per round, at most
+constexpr int kAnalyze = 48;     // window entries (re)analysed per round, at most
 constexpr int kAffCap = 1024;    // column-upkeep work list of a wide batch
 constexpr int kPListCap = 16;    // pending targets listed per run target (more: replay walks rows)
 

@@ -1274,16 +1274,27 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             if (lane == 0) s_na = min(__popcll(m), kAnalyze);
         }
         __syncthreads();
-        for (int a_i = wave; a_i < s_na; a_i += nwaves) {
-            const int sl = alist[a_i];
-            const int k = sk[sl];
-            // the stabilizer half of the column (band Wr + lane + 64 u), all words at once
-            uint64_t cw[kMaxStabBandsPerLane];
+        // the stabilizer half of an entry's column (band Wr + lane + 64 u), all words at once;
+        // a wave's next entry is read while it works on the current one (lanes past Wr read
+        // band Wr and are masked)
+        const int na = s_na;
+        auto load_col = [&](int a_i, uint64_t* cw) {
+            const int kk = a_i < na ? sk[alist[a_i]] : 0;
 #pragma unroll
             for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
                 const int w = lane + 64 * u;
-                cw[u] = (w < g.Wr) ? c.X[(size_t)(g.Wr + w) * K + k] : 0ull;
+                cw[u] = c.X[(size_t)(g.Wr + (w < g.Wr ? w : 0)) * K + kk];
             }
+        };
+        uint64_t cwn[kMaxStabBandsPerLane];
+        if (wave < na) load_col(wave, cwn);
+        for (int a_i = wave; a_i < na; a_i += nwaves) {
+            const int sl = alist[a_i];
+            const int k = sk[sl];
+            uint64_t cw[kMaxStabBandsPerLane];
+#pragma unroll
+            for (int u = 0; u < kMaxStabBandsPerLane; ++u) cw[u] = lane + 64 * u < g.Wr ? cwn[u] : 0ull;
+            if (a_i + nwaves < na) load_col(a_i + nwaves, cwn);
             // pivot = first set bit in band order, the other set bits are the rowsum rows
             // (ascending); the few nonzero words are read out one by one with scalar loops
             int pv = INT_MAX, cnt = 0;
