@@ -1513,61 +1513,62 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
 // Destabilizer replay of a measurement layer: grid (Wr destabilizer bands, S copies), 512
 // threads.  In op order, every target the chain ran did, to each destabilizer D with x at its
 // qubit, rowsum(D, P) with its old pivot row P (sign r_D <- r_D ^ r_P ^ (i-power / 2), the
-// per-shot parts XOR), and replaced its pivot's own destabilizer by P.  Each destabilizer is
-// replayed on its own, by one wave, the waves taking the band's touched rows one after the
-// other; only rows with x at some run target at layer start, or a pivot's partner, can be
-// touched (a row never touched keeps its x bits), so only those are.
+// per-shot parts XOR), and replaced its pivot's own destabilizer by P.  Only rows with x at
+// some run target at layer start, or a pivot's partner, can be touched.
 //
-// Which targets hit D depends only on D's x bits at the run targets' qubits, and applying P
-// flips exactly the bits of the pending targets the chain listed for P (a target run earlier
-// has no x in P: P commutes with its Z).  So a wave first walks D's hits with those bits in
-// registers (the band's x words at the run targets, transposed once per block so that row D's
-// bits are one LDS read per lane), producing D's ordered list of events; then it applies the
-// events to D's x and z words with kReplayAhead pivot rows in flight, summing the i-powers per
-// lane (every step's power is even, so the halves add); then it takes the signs of the events
-// after the last replacement, whose XOR does not depend on their order, in parallel over the
-// lanes.  When a pivot's list overflowed, or the lists do not fit in LDS, the wave instead
-// tests D's live bits 64 targets at a time and applies each hit before testing again.
+// Which targets hit D depends only on D's x bits at the run targets' qubits; applying P flips
+// exactly the bits of the pending targets the chain listed for P (a target run earlier has no
+// x in P: P commutes with its Z), and replacing D by P sets them to P's.  So the hits of all
+// 64 rows of the band are found at once, bit-sliced: word V[j] holds the band's x bits at run
+// target j, and one wave walks the run targets in order with the next 64 words in a ring of
+// lanes (flips to words within the ring land in registers, flips beyond it are LDS atomics),
+// leaving H[j] = the rows target j hits (in place of V[j]).  Runs of targets that hit nothing
+// are skipped a ring at a time.  Then every wave takes rows: a row's events (its replacement,
+// if it is a partner, and the hits after it) are read off H with ballots and applied to its
+// x and z words with kReplayAhead pivot rows in flight, summing the i-powers per lane (every
+// step's power is even, so the halves add); the signs of the events after the replacement
+// XOR in any order and are taken in parallel over the lanes.  When a pivot's list overflowed
+// or the lists do not fit in LDS, a wave instead tests its row's live bits 64 run targets at a
+// time and applies each hit before testing again.
 // ------------------------------------------------------------------------------------------
 constexpr int kReplayEvents = 512;     // events a wave collects before applying them
-constexpr int kReplayAhead = 6;        // pivot rows in flight per wave while events are applied
-constexpr int kReplayVW = 3;           // run-target bit words per lane in the walk
+// pivot rows in flight per wave while events are applied (a ring of register buffers)
+template <int WPL> struct ReplayRing { static constexpr int depth = WPL <= 2 ? 16 : WPL == 3 ? 12 : 8; };
 constexpr int kReplayInline = 3;       // list entries kept in a target's descriptor
 
 // Dynamic LDS of the replay.  With lists (ent_cap >= 0): per-shot deltas, partner table, run
-// targets, then the transposed x bits (row-major, KW words per destabilizer of the band), the
-// run-target mask, per-wave event lists, one descriptor per target, then ent_cap list
-// entries of the long lists.  Without: the first three only.
+// targets, then per run target its x word V (H after the walk) and its descriptor, the
+// target -> run index map, the per-wave event lists, then ent_cap entries of the long lists.
+// Without: the first three only.
 struct ReplayLds {
-    int acc, prow, rk, vt, exe, ev, desc, ent;      // byte offsets
+    int acc, prow, rk, V, desc, jmap, ev, ent;      // byte offsets
     int small_bytes;                                // end of the form without lists
     int fixed_bytes;                                // end of the form with lists, before entries
 };
 
 __host__ __device__ inline ReplayLds replay_lds_layout(int K, int nrdw, int nwaves)
 {
-    const int KW = (K + 63) / 64;
     ReplayLds L;
     int o = 0;
     L.acc = o; o += nwaves * nrdw * 8;
     L.prow = o; o += 64 * 4;
     L.rk = o; o += ((K * 4 + 7) / 8) * 8;
     L.small_bytes = o;
-    L.vt = o; o += 64 * KW * 8;
-    L.exe = o; o += KW * 8;
-    L.ev = o; o += nwaves * kReplayEvents * 4;
+    L.V = o; o += K * 8;
     L.desc = o; o += K * 8;
+    L.jmap = o; o += ((K * 2 + 7) / 8) * 8;
+    L.ev = o; o += nwaves * kReplayEvents * 4;
     L.ent = o;
     L.fixed_bytes = o;
     return L;
 }
 
-// Whether the register walk covers K targets.
-__host__ __device__ inline bool replay_walk_fits(int K) { return (K + 63) / 64 <= 64 * kReplayVW; }
+// Whether the run-index map (16-bit) covers every target.
+__host__ __device__ inline bool replay_walk_fits(int K) { return K <= 32767; }
 
 // Row words of this lane (word lane + 64 t, WPL slots).  No load is conditional, so that the
 // loads of rows in flight are waited for one by one: the last slot's lanes past Wc load word 0
-// instead (any address of the row does) and the caller masks them with tail_mask.
+// instead (any address of the row does) and the caller masks them with the tail mask.
 template <int WPL>
 __device__ __forceinline__ void replay_load(const uint64_t* row, int Wc, int lane, uint64_t* x, uint64_t* z)
 {
@@ -1578,6 +1579,12 @@ __device__ __forceinline__ void replay_load(const uint64_t* row, int Wc, int lan
         z[t] = row[Wc + cw];
     }
 }
+
+// Descriptor of run target j: bits 0..47 up to kReplayInline later run indices of its list
+// (16 bits each) or, for a longer list, its offset in the entry area (bits 0..31); bits 48..52
+// the list length; bits 53..59 its partner row in the band + 1 (0: the partner is elsewhere).
+__device__ __forceinline__ int desc_len(uint64_t d) { return (int)((d >> 48) & 31); }
+__device__ __forceinline__ int desc_partner(uint64_t d) { return (int)((d >> 53) & 127) - 1; }
 
 template <int WPL>
 __global__ void __launch_bounds__(512)
@@ -1594,18 +1601,17 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int Wc = g.Wc, RS = g.RS, NB = g.NB;
     const int nrdw = (g.bpc + 63) >> 6;
-    const int KW = (K + 63) >> 6;
     const uint64_t tail = lane + 64 * (WPL - 1) < Wc ? ~0ull : 0ull;   // last slot in the row
     const ReplayLds LL = replay_lds_layout(K, nrdw, nwaves);
     char* base = (char*)rsm;
     const bool lists = ent_cap >= 0;                     // LDS holds the list form
     uint64_t* acc = (uint64_t*)(base + LL.acc);          // nwaves x nrdw per-shot sign deltas
-    int* prow = (int*)(base + LL.prow);                  // per row of the band: target it is the partner of
+    int* prow = (int*)(base + LL.prow);                  // per row of the band: see below
     int* rk = (int*)(base + LL.rk);
-    uint64_t* vt = lists ? (uint64_t*)(base + LL.vt) : nullptr;    // [row][KW] x bits at run targets
-    uint64_t* exe = lists ? (uint64_t*)(base + LL.exe) : nullptr;  // run targets
-    int* evs = lists ? (int*)(base + LL.ev) : nullptr;
+    uint64_t* V = lists ? (uint64_t*)(base + LL.V) : nullptr;
     uint64_t* desc = lists ? (uint64_t*)(base + LL.desc) : nullptr;
+    int16_t* jmap = lists ? (int16_t*)(base + LL.jmap) : nullptr;
+    int* evs = lists ? (int*)(base + LL.ev) : nullptr;
     uint16_t* ent = lists ? (uint16_t*)(base + LL.ent) : nullptr;
     __shared__ int s_cnt[16], s_crow[64], s_ncand, s_next;
     __shared__ unsigned long long s_cand;
@@ -1616,21 +1622,20 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     uint64_t* tb = tab + (size_t)s * 2 * g.NR * RS;
     uint64_t* rsc = rs + (size_t)s * NB;
 
-    // run targets in op order (stable compaction) and their bitmask
+    // run targets in op order (stable compaction)
     if (tid == 0) {
         s_cand = 0;
         s_next = 0;
     }
     for (int r = tid; r < 64; r += nt) prow[r] = -1;
     __syncthreads();
-    int R = 0, T = 0;
+    int R = 0;
     for (int k0 = 0; k0 < K; k0 += nt) {
         const int k = k0 + tid;
         const bool f = k < K && lp[k] >= 0;
         const uint64_t m = __ballot(f);
         const int rank = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) s_cnt[wave] = __popcll(m);
-        if (lists && lane == 0 && k0 + wave * 64 < K) exe[(k0 >> 6) + wave] = m;
         __syncthreads();
         int before = 0, total = 0;
         for (int w = 0; w < nwaves; ++w) {
@@ -1642,58 +1647,62 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
         __syncthreads();
     }
     if (R == 0) return;
+    // the list form holds for this copy when no pending list overflowed and the long lists fit
+    bool walk = lists && povf[s] == 0;
     uint64_t cand = 0;
-    if (lists) {
-        // one descriptor per target: up to kReplayInline list entries inline (16 bits each) and
-        // the length in bits 48..52; a longer list lives in ent, its offset in bits 0..31
-        // (exclusive scan of the long lists' lengths)
-        for (int k0 = 0; k0 < K; k0 += nt) {
-            const int k = k0 + tid;
-            const bool f = k < K && ((exe[k >> 6] >> (k & 63)) & 1ull);
-            const int len = f ? min(pc[k], kPListCap) : 0;
+    if (walk) {
+        for (int k = tid; k < K; k += nt) jmap[k] = -1;
+        __syncthreads();
+        for (int j = tid; j < R; j += nt) jmap[rk[j]] = (int16_t)j;
+        __syncthreads();
+        // descriptors (list entries as run indices; entries that did not run are dropped),
+        // x words, partners; long lists go to ent at offsets from an exclusive scan
+        int T = 0;
+        for (int j0 = 0; j0 < R; j0 += nt) {
+            const int j = j0 + tid;
+            int len = 0, n2 = 0, pr = -1;
+            const uint16_t* lst = nullptr;
+            if (j < R) {
+                const int k = rk[j];
+                lst = pl + (size_t)k * kPListCap;
+                n2 = min(pc[k], kPListCap);
+                for (int e = 0; e < n2; ++e) len += jmap[lst[e]] >= 0 ? 1 : 0;
+                const uint64_t xw = X[k];
+                V[j] = xw;
+                cand |= xw;
+                const int p = lp[k];
+                if ((p >> 6) == band) {
+                    pr = p & 63;
+                    prow[pr] = j;
+                    cand |= 1ull << pr;
+                }
+            }
             const int big = len > kReplayInline ? len : 0;
             const int ex = wave_excl_scan(big, lane);
-            const int ws = wave_sum(big);
-            if (lane == 0) s_cnt[wave] = ws;
+            if (lane == 0) s_cnt[wave] = wave_sum(big);
             __syncthreads();
             int before = 0, total = 0;
             for (int w = 0; w < nwaves; ++w) {
                 if (w < wave) before += s_cnt[w];
                 total += s_cnt[w];
             }
-            if (k < K) {
-                uint64_t d = (uint64_t)len << 48;
-                if (big) {
-                    const int o = T + before + ex;
-                    d |= (uint32_t)o;
-                    if (o + len <= ent_cap)
-                        for (int e = 0; e < len; ++e) ent[o + e] = pl[(size_t)k * kPListCap + e];
-                } else {
-                    for (int e = 0; e < len; ++e) d |= (uint64_t)pl[(size_t)k * kPListCap + e] << (16 * e);
+            if (j < R) {
+                uint64_t d = ((uint64_t)len << 48) | ((uint64_t)(pr + 1) << 53);
+                const int o = T + before + ex;
+                if (big) d |= (uint32_t)o;
+                for (int e = 0, n = 0; e < n2; ++e) {
+                    const int jj = jmap[lst[e]];
+                    if (jj < 0) continue;
+                    if (!big) d |= (uint64_t)jj << (16 * n);
+                    else if (o + n < ent_cap) ent[o + n] = (uint16_t)jj;
+                    ++n;
                 }
-                desc[k] = d;
+                desc[j] = d;
             }
             T += total;
             __syncthreads();
         }
-        // the band's x bits at the run targets, transposed: lane r of chunk w gets row r's
-        // bits at targets 64w..64w+63
-        uint64_t any = 0;
-        for (int w = wave; w < KW; w += nwaves) {
-            const int k = w * 64 + lane;
-            const bool f = k < K && ((exe[w] >> lane) & 1ull);
-            const uint64_t t = transpose64(f ? X[k] : 0ull, lane);
-            vt[(size_t)lane * KW + w] = t;
-            any |= t;
-        }
-        cand = __ballot(any != 0);
-        for (int j = tid; j < R; j += nt) {
-            const int p = lp[rk[j]];
-            if ((p >> 6) == band) {
-                cand |= 1ull << (p & 63);
-                prow[p & 63] = rk[j];
-            }
-        }
+        walk = T <= ent_cap;
     } else {
         for (int j = tid; j < R; j += nt) {
             const int k = rk[j];
@@ -1708,6 +1717,47 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     cand = wave_or(cand);
     if (lane == 0 && cand) atomicOr(&s_cand, (unsigned long long)cand);
     __syncthreads();
+
+    if (walk && wave == 0) {
+        // bit-sliced walk, 64 run targets at a time: lane l holds target j0 + l (its word and
+        // descriptor); flips to targets of the same 64 land in registers, later ones are LDS
+        // atomics made before those targets are read
+        for (int j0 = 0; j0 < R; j0 += 64) {
+            const int jl = j0 + lane;
+            uint64_t val = jl < R ? V[jl] : 0ull;
+            const uint64_t dsc = jl < R ? desc[jl] : 0ull;
+            const uint64_t pm = __ballot(jl < R && desc_partner(dsc) >= 0);
+            int off = 0;
+            while (true) {
+                // next target from off on that hits a row or has its partner here
+                const uint64_t am = (__ballot(val != 0ull) | pm) & (off < 64 ? ~0ull << off : 0ull);
+                if (!am) break;
+                const int cj = ctz64(am);
+                const uint64_t cur = readlane_u64(val, cj);
+                const uint64_t d = readlane_u64(dsc, cj);
+                const int len = desc_len(d), pr = desc_partner(d);
+                const uint64_t bpr = pr >= 0 ? 1ull << pr : 0ull;
+                const uint64_t hit = cur & ~bpr;
+                if (lane == cj) val = hit;                  // H[j]
+                if (pr >= 0) {
+                    // the partner's bits at later targets become P's: cleared here, set below
+                    if (lane > cj) val &= ~bpr;
+                    for (int w = j0 + 64 + lane; w < R; w += 64) atomicAnd((unsigned long long*)&V[w], ~bpr);
+                }
+                for (int e = 0; e < len; ++e) {
+                    const int j2 = len <= kReplayInline ? (int)((d >> (16 * e)) & 0xffff) : (int)ent[(uint32_t)d + e];
+                    if (j2 < j0 + 64) {
+                        if (lane == j2 - j0) val = (val ^ hit) | bpr;
+                    } else if (lane == 0) {
+                        if (hit) atomicXor((unsigned long long*)&V[j2], hit);
+                        if (bpr) atomicOr((unsigned long long*)&V[j2], bpr);
+                    }
+                }
+                off = cj + 1;
+            }
+            if (jl < R) V[jl] = val;                        // H of the 64 (0 where nothing hit)
+        }
+    }
     if (tid == 0) {
         uint64_t c = s_cand;
         int nc = 0;
@@ -1718,25 +1768,18 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
         s_ncand = nc;
     }
     __syncthreads();
-    const bool walk = lists && povf[s] == 0 && T <= ent_cap && replay_walk_fits(K);
     const int ncand = s_ncand;
 
     uint64_t* myacc = acc + (size_t)wave * nrdw;
     int* ev = lists ? evs + (size_t)wave * kReplayEvents : nullptr;
-    uint64_t er[kReplayVW];                              // run-target bits, word lane + 64 t
-#pragma unroll
-    for (int t = 0; t < kReplayVW; ++t) {
-        const int w = lane + 64 * t;
-        er[t] = (walk && w < KW) ? exe[w] : 0ull;
-    }
     int nrows = 0, applied = 0, trows = 0, tev = 0;
     while (true) {
-        int j = 0;
-        if (lane == 0) j = atomicAdd(&s_next, 1);
-        j = __shfl(j, 0, 64);
-        if (j >= ncand) break;
+        int jr = 0;
+        if (lane == 0) jr = atomicAdd(&s_next, 1);
+        jr = __shfl(jr, 0, 64);
+        if (jr >= ncand) break;
         ++nrows;
-        const int r = s_crow[j];
+        const int r = s_crow[jr];
         const int i = band * 64 + r;                   // destabilizer index
         uint64_t* row = tb + (size_t)i * RS;
         uint64_t x[WPL], z[WPL];
@@ -1747,38 +1790,57 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
         const int sh0 = sh;
         for (int u = lane; u < nrdw; u += 64) myacc[u] = 0;
         bool mod = false;
-        int G = 0;                                     // i-powers since the last replacement, per lane
-        // D := P_kk, signs included (the per-shot deltas make rd's bits equal P's)
+        // Phase of the rowsums since the last replacement, telescoped: with |u| the number of
+        // qubits where a row has both x and z, rowsum(D, P) raises i to |P| + |D| + 2 z_P.x_D
+        // - |P D| (mod 4), so the steps from D0 to Dn sum to sum|P| + |D0| - |Dn| + 2 sum z_P.x_D,
+        // and only the parity of the last sum matters: its terms XOR into cr.  G holds
+        // sum|P| + |D0| per lane.
+        int G = 0;
+        uint64_t cr[WPL];
+#pragma unroll
+        for (int t = 0; t < WPL; ++t) {
+            G += __popcll(x[t] & z[t]);
+            cr[t] = 0;
+        }
+        auto phase = [&]() {
+            int v = G;
+#pragma unroll
+            for (int t = 0; t < WPL; ++t) v += 2 * __popcll(cr[t]) - __popcll(x[t] & z[t]);
+            return wave_sum(v);
+        };
+        // D := P_k, signs included (the per-shot deltas make rd's bits equal P's)
         auto replace_signs = [&](int kk) {
             const uint64_t* Pd = plog_rd + ((size_t)s * K + kk) * nrdw;
             sh = plog_rs[(size_t)s * K + kk];
             for (int b0 = 0; b0 < g.bpc; b0 += 64) {
                 const int b = b0 + lane;
-                const bool cur = b < g.bpc && ((rd[(size_t)(s * g.bpc + b) * NB + band] >> r) & 1ull);
-                const uint64_t m = __ballot(cur);
+                const bool cb = b < g.bpc && ((rd[(size_t)(s * g.bpc + b) * NB + band] >> r) & 1ull);
+                const uint64_t m = __ballot(cb);
                 if (lane == 0) myacc[b0 >> 6] = m ^ Pd[b0 >> 6];
             }
         };
         // x and z words of one event: replace (G so far applies to the row being replaced) or
-        // multiply in
-        // (the pivot row's last slot is masked here, at use)
+        // multiply in (the pivot row's last slot is masked here, at use)
         auto step = [&](bool repl, const uint64_t* px, const uint64_t* pz) {
             if (repl) {
-                const int Gs = wave_sum(G);
+                const int Gs = phase();
                 if (lane == 0 && (Gs & 1)) atomicOr(err, 8);
+                G = 0;
 #pragma unroll
                 for (int t = 0; t < WPL; ++t) {
                     const uint64_t m = t == WPL - 1 ? tail : ~0ull;
                     x[t] = px[t] & m;
                     z[t] = pz[t] & m;
+                    G += __popcll(x[t] & z[t]);
+                    cr[t] = 0;
                 }
-                G = 0;
             } else {
 #pragma unroll
                 for (int t = 0; t < WPL; ++t) {
                     const uint64_t m = t == WPL - 1 ? tail : ~0ull;
                     const uint64_t a = px[t] & m, b = pz[t] & m;
-                    G += gsum(a, b, x[t], z[t]);
+                    cr[t] ^= b & x[t];
+                    G += __popcll(a & b);
                     x[t] ^= a;
                     z[t] ^= b;
                 }
@@ -1786,81 +1848,46 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
             }
         };
         if (walk) {
-            uint64_t vr[kReplayVW];
-#pragma unroll
-            for (int t = 0; t < kReplayVW; ++t) {
-                const int w = lane + 64 * t;
-                vr[t] = w < KW ? vt[(size_t)r * KW + w] : 0ull;
-            }
-            const int pk = prow[r];
-            int pos = 0;
-            bool more = true;
-            while (more) {
-                // walk: collect up to kReplayEvents events
-                int nev = 0, lastrep = -1;
-                while (nev < kReplayEvents) {
-                    // next set bit of vr at >= pos: the first lane of the first slot with one
-                    const int pw = pos >> 6;
-                    int nb = 0x7fffffff;
-#pragma unroll
-                    for (int t = 0; t < kReplayVW; ++t) {
-                        const int w = lane + 64 * t;
-                        uint64_t m = vr[t];
-                        if (w < pw) m = 0;
-                        else if (w == pw) m &= ~0ull << (pos & 63);
-                        const uint64_t bal = __ballot(m != 0ull);
-                        if (nb == 0x7fffffff && bal) {
-                            const int l = ctz64(bal);
-                            nb = (l + 64 * t) * 64 + ctz64(readlane_u64(m, l));
-                        }
-                    }
-                    int kk;
-                    bool repl;
-                    if (pk >= pos && pk <= nb) {          // D is this target's partner: replaced
-                        kk = pk;
-                        repl = true;
-                    } else if (nb != 0x7fffffff) {
-                        kk = nb;
-                        repl = false;
-                    } else {
-                        more = false;
-                        break;
-                    }
-                    if (lane == 0) ev[nev] = repl ? (kk | (1 << 30)) : kk;
-                    if (repl) {
-                        lastrep = nev;
-#pragma unroll
-                        for (int t = 0; t < kReplayVW; ++t)
-                            if (lane + 64 * t >= (kk >> 6)) vr[t] = 0;
-                    }
-                    ++nev;
-                    // D's x bits at later run targets: flip (multiply) or become P's (replace)
-                    const uint64_t d = desc[kk];
-                    const int len = (int)((d >> 48) & 31);
-                    for (int e = 0; e < len; ++e) {
-                        const int k2 = len <= kReplayInline ? (int)((d >> (16 * e)) & 0xffff)
-                                                            : (int)ent[(uint32_t)d + e];
-                        const uint64_t bit = (lane == ((k2 >> 6) & 63)) ? 1ull << (k2 & 63) : 0ull;
-#pragma unroll
-                        for (int t = 0; t < kReplayVW; ++t)
-                            if ((k2 >> 12) == t) vr[t] ^= bit & er[t];
-                    }
-                    pos = kk + 1;
+            // events: the replacement (if this row is a partner), then the hits after it
+            const int jp = prow[r];
+            int jn = jp >= 0 ? jp : 0;                 // next run index to read off H
+            bool first = jp >= 0;
+            const uint64_t* prow0 = plog_row + (size_t)s * K * RS;
+            while (true) {
+                int nev = 0;
+                if (first) {
+                    if (lane == 0) ev[0] = rk[jp] | (1 << 30);
+                    nev = 1;
+                    jn = jp + 1;
+                    first = false;
+                }
+                while (jn < R && nev + 64 <= kReplayEvents) {
+                    const int jj = jn + lane;
+                    const bool h = jj < R && ((V[jj] >> r) & 1ull);
+                    const uint64_t hm = __ballot(h);
+                    if (h) ev[nev + __popcll(hm & ((1ull << lane) - 1ull))] = rk[jj];
+                    nev += __popcll(hm);
+                    jn += 64;
                 }
                 if (nev == 0) break;
                 mod = true;
                 // apply in order, the next kReplayAhead pivot rows in flight (a ring of register
                 // buffers rotated by the unrolled loop; loads past the end repeat the last row)
-                const uint64_t* prow0 = plog_row + (size_t)s * K * RS;
+                constexpr int kReplayAhead = ReplayRing<WPL>::depth;
                 uint64_t px[kReplayAhead][WPL], pz[kReplayAhead][WPL];
 #pragma unroll
                 for (int u = 0; u < kReplayAhead; ++u)
                     replay_load<WPL>(prow0 + (size_t)(ev[min(u, nev - 1)] & 0x3fffffff) * RS, Wc, lane, px[u], pz[u]);
+                int lastrep = -1;
                 for (int e0 = 0; e0 < nev; e0 += kReplayAhead) {
 #pragma unroll
                     for (int u = 0; u < kReplayAhead; ++u) {
                         const int e = e0 + u;
-                        if (e < nev) step((ev[e] >> 30) & 1, px[u], pz[u]);
+                        if (e < nev) {
+                            const bool rp = (ev[e] >> 30) & 1;
+                            if (rp) lastrep = e;
+                            step(rp, px[u], pz[u]);
+                        }
                         const int en = min(e + kReplayAhead, nev - 1);
                         replay_load<WPL>(prow0 + (size_t)(ev[en] & 0x3fffffff) * RS, Wc, lane, px[u], pz[u]);
                     }
@@ -1878,6 +1905,7 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
                     a = wave_xor(a);
                     if (lane == 0) myacc[u] ^= a;
                 }
+                if (jn >= R) break;
             }
         } else {
             // walk by testing D's live x bits 64 run targets at a time
@@ -1922,7 +1950,7 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
             }
         }
         if (mod) {
-            const int Gs = wave_sum(G);
+            const int Gs = phase();
             if (lane == 0 && (Gs & 1)) atomicOr(err, 8);
             sh ^= (Gs >> 1) & 1;
 #pragma unroll
