@@ -709,8 +709,8 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         } else {
             const MeasPlan& m = P->meas[st.second];
             const int K2 = m.K;
-            const dim3 cgrid((K2 + 255) / 256, g.S), dgrid((K2 + 3) / 4, g.S);
-            TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 0)));
+            const dim3 cgrid((K2 + 63) / 64, g.S), dgrid((K2 + 3) / 4, g.S);
+            TIMED(ctx, 3, (k_classify<<<cgrid, 64 * kClsChunks, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 0)));
             TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
                                                                  mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -1)));
             HIP_CHECK(ctx, hipMemsetAsync(ran, 0, sizeof(int), ctx->stream));
@@ -744,7 +744,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                                            ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
             // targets the chain found deterministic: reduced in parallel on the final tableau
-            TIMED(ctx, 3, (k_classify<<<cgrid, 256, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
+            TIMED(ctx, 3, (k_classify<<<cgrid, 64 * kClsChunks, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
             TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
                                                                  mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -3)));
             const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;

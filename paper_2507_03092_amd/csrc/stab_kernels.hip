@@ -505,46 +505,75 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 // destabilizer rows with x at the qubit (they select the stabilizers whose product is +-Z_a).
 // Pass 1 (after the random chain) only lists the rows of targets the chain found
 // deterministic (cls == -2) and marks them -3.
-// Thread per (target k, copy s); reads of Xcol [s][band][k] are coalesced over k.
+// Reads of Xcol [s][band][k] are coalesced over k (the lanes of a wave).
 // ------------------------------------------------------------------------------------------
-__global__ void k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K,
-                           int* __restrict__ cls, int* __restrict__ mlist,
-                           int* __restrict__ mcount, int mcap, int pass)
+// Block: 64 targets (lane) x kClsChunks band ranges (wave), so a target's scan is split
+// kClsChunks ways; the ranges' results combine in band order through LDS.
+constexpr int kClsChunks = 4;
+
+__global__ void __launch_bounds__(64 * kClsChunks)
+k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
+           int* __restrict__ mlist, int* __restrict__ mcount, int mcap, int pass)
 {
+    __shared__ int s_piv[kClsChunks][64], s_cnt[kClsChunks][64];
     const int s = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    if (pass == 1 && cls[s * K + k] != -2) return;
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane;
+    const bool in = k < K;
+    const bool mine = in && (pass == 0 || cls[s * K + k] == -2);
     const uint64_t* X = Xcol + (size_t)s * g.NB * K;
-    // 8 independent loads in flight per step: the scan is latency-bound otherwise
-    int piv = -1;
-    for (int w0 = 0; pass == 0 && w0 < g.Wr && piv < 0; w0 += 8) {
+    const int w0 = c * g.Wr / kClsChunks, w1 = (c + 1) * g.Wr / kClsChunks;
+    // this range's first stabilizer with x at the qubit; 8 loads in flight per step
+    int piv = INT_MAX;
+    for (int w = w0; pass == 0 && mine && w < w1 && piv == INT_MAX; w += 8) {
         uint64_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (w0 + u < g.Wr) ? X[(size_t)(g.Wr + w0 + u) * K + k] : 0ull;
+        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(g.Wr + w + u) * K + k] : 0ull;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (piv < 0 && v[u]) piv = (w0 + u) * 64 + ctz64(v[u]);
+            if (piv == INT_MAX && v[u]) piv = (w + u) * 64 + ctz64(v[u]);
     }
-    cls[s * K + k] = (pass == 0) ? piv : -3;
-    if (piv < 0) {
-        int cnt = 0;
-        for (int w0 = 0; w0 < g.Wr; w0 += 8) {
-            uint64_t v[8];
+    s_piv[c][lane] = piv;
+    __syncthreads();
+    int pv = INT_MAX;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = (w0 + u < g.Wr) ? X[(size_t)(w0 + u) * K + k] : 0ull;
+    for (int cc = 0; cc < kClsChunks; ++cc) pv = min(pv, s_piv[cc][lane]);
+    const bool det = mine && pv == INT_MAX;
+    if (mine && c == 0) cls[s * K + k] = (pass == 0) ? (det ? -1 : pv) : -3;
+    // deterministic: the destabilizers with x at the qubit, in row order (this range's share
+    // after the counts of the ranges before it)
+    int cnt = 0;
+    for (int w = w0; det && w < w1; w += 8) {
+        uint64_t v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                while (v[u]) {
-                    const int bit = ctz64(v[u]);
-                    v[u] &= v[u] - 1;
-                    if (cnt < mcap) mlist[((size_t)s * mcap + cnt) * K + k] = (w0 + u) * 64 + bit;
-                    ++cnt;
-                }
+        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(w + u) * K + k] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cnt += __popcll(v[u]);
+    }
+    s_cnt[c][lane] = cnt;
+    __syncthreads();
+    if (!det) return;
+    int pos = 0, tot = 0;
+#pragma unroll
+    for (int cc = 0; cc < kClsChunks; ++cc) {
+        if (cc < c) pos += s_cnt[cc][lane];
+        tot += s_cnt[cc][lane];
+    }
+    for (int w = w0; w < w1 && pos < mcap; w += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(w + u) * K + k] : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            while (v[u]) {
+                const int bit = ctz64(v[u]);
+                v[u] &= v[u] - 1;
+                if (pos < mcap) mlist[((size_t)s * mcap + pos) * K + k] = (w + u) * 64 + bit;
+                ++pos;
             }
         }
-        mcount[s * K + k] = cnt;
     }
+    if (c == 0) mcount[s * K + k] = tot;
 }
 
 // Deterministic outcome, one wave: product of stabilizer rows NR+i over the listed rows i,
@@ -608,12 +637,21 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
     const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
     const uint64_t* rsc = rs + (size_t)s * g.NB;
     if (cnt <= mcap) {
-        // rows listed: ids 64 at a time, row words 4 rows at a time, all loads of a batch in flight
+        // rows listed: ids 64 at a time, row words 4 rows at a time, all loads of a batch in
+        // flight (none conditional: lanes past Wc read word 0 and are masked, rows past the
+        // list repeat its last one and are skipped).  The product's phase is telescoped as in
+        // the replay: sum|row| - |S| + 2 (parity of sum z_row.x_S), |u| = popcount(x & z).
         const uint64_t* base = tb + (size_t)g.NR * g.RS;
         const int* ml = mlist + (size_t)s * mcap * K + k;
-        uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
+        int jc[kMaxWordsPerLane];
+        uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int j = lane + 64 * t;
+            jc[t] = j < g.Wc ? j : 0;
+            msk[t] = j < g.Wc ? ~0ull : 0ull;
+            sx[t] = sz[t] = cr[t] = 0;
+        }
         int G = 0, rsum = 0;
         for (int c0 = 0; c0 < cnt; c0 += 64) {
             const int nc = min(64, cnt - c0);
@@ -623,36 +661,41 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
                 uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int i = __shfl(myrow, min(u0 + u, 63), 64);
+                    const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
                     const uint64_t* row = base + (size_t)i * g.RS;
 #pragma unroll
                     for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        const int j = lane + 64 * t;
-                        const bool ok = u0 + u < nc && j < g.Wc;
-                        rx[u][t] = ok ? row[j] : 0ull;
-                        rz[u][t] = ok ? row[g.Wc + j] : 0ull;
+                        rx[u][t] = row[jc[t]];
+                        rz[u][t] = row[g.Wc + jc[t]];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    if (u0 + u >= nc) break;
 #pragma unroll
                     for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        G += gsum(rx[u][t], rz[u][t], sx[t], sz[t]);
-                        sx[t] ^= rx[u][t];
-                        sz[t] ^= rz[u][t];
+                        const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
+                        cr[t] ^= b & sx[t];
+                        G += __popcll(a & b);
+                        sx[t] ^= a;
+                        sz[t] ^= b;
                     }
                 }
             }
         }
-        G = wave_sum(G);
         uint64_t xres = 0;
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) xres |= sx[t];
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
+            xres |= sx[t];
+        }
+        G = wave_sum(G);
         xres = wave_or(xres);
         const int e = (2 * rsum + G) & 3;
         if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
         const int shared = e >> 1;
-        // per-shot part of the sign: parity of the shot's sign bits over the same rows
+        // per-shot part of the sign: parity of the shot's sign bits over the same rows, eight
+        // rows' words in flight at a time
         for (int b0 = 0; b0 < g.bpc; b0 += 64) {
             const int b = b0 + lane;
             const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b, g.bpc - 1)) * g.NB + g.Wr;
@@ -660,9 +703,16 @@ __global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* 
             for (int c0 = 0; c0 < cnt; c0 += 64) {
                 const int nc = min(64, cnt - c0);
                 const int myrow = lane < nc ? ml[(size_t)(c0 + lane) * K] : 0;
-                for (int c = 0; c < nc; ++c) {
-                    const int i = __shfl(myrow, c, 64);
-                    par ^= (int)((rdb[i >> 6] >> (i & 63)) & 1ull);
+                for (int c = 0; c < nc; c += 8) {
+                    int iu[8];
+                    uint64_t wv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
                 }
             }
             if (b < g.bpc) obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
