@@ -646,10 +646,11 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
             }
             if (o >= 0) ++ndet;
         }
-        if (lane == 0) {
-            W.ndet += ndet;
-            W.nrows += nrows;
-            W.bytes += (long long)ndet * NB * 8 + (long long)nrows * row_b;
+        // (per-wave work, counted by each wave; the block-wide work in W by thread 0 below)
+        if (lane == 0 && ndet) {
+            count_add(A.counters, 2, (unsigned long long)ndet);
+            count_add(A.counters, 5, (unsigned long long)nrows);
+            count_add(A.counters, 6, (unsigned long long)((long long)ndet * NB * 8 + (long long)nrows * row_b));
         }
         __syncthreads();
         // random at the start of the instruction: in op order, on the live tableau
@@ -769,7 +770,7 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
     }
     __syncthreads();
     for (int w = tid; w < NB; w += kBatchThreads) rs[w] = L.sg[w];
-    if (lane == 0 && (W.ndet || W.nrand || W.nrows)) {
+    if (tid == 0 && (W.ndet || W.nrand || W.nrows)) {
         count_add(A.counters, 4, (unsigned long long)W.nrand);
         count_add(A.counters, 2, (unsigned long long)W.ndet);
         count_add(A.counters, 5, (unsigned long long)W.nrows);
