@@ -1768,15 +1768,21 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     if (lane == 0 && cand) atomicOr(&s_cand, (unsigned long long)cand);
     __syncthreads();
 
-    if (walk && wave == 0) {
+    if (walk) {
         // bit-sliced walk, 64 run targets at a time: lane l holds target j0 + l (its word and
         // descriptor); flips to targets of the same 64 land in registers, later ones are LDS
-        // atomics made before those targets are read
+        // atomics made before those targets are read.  A row's bits only ever change by its
+        // own hits and replacement, so each wave walks its own slice of the 64 rows (bits gm of
+        // every word) on its own: its updates touch no other wave's bits.
+        const int rpw = 64 / nwaves;
+        const uint64_t gm = (rpw == 64 ? ~0ull : ((1ull << rpw) - 1ull)) << (rpw * wave);
         for (int j0 = 0; j0 < R; j0 += 64) {
             const int jl = j0 + lane;
-            uint64_t val = jl < R ? V[jl] : 0ull;
+            const uint64_t raw = jl < R ? V[jl] & gm : 0ull;
+            uint64_t val = raw;
             const uint64_t dsc = jl < R ? desc[jl] : 0ull;
-            const uint64_t pm = __ballot(jl < R && desc_partner(dsc) >= 0);
+            const int pl_ = desc_partner(dsc);
+            const uint64_t pm = __ballot(jl < R && pl_ >= 0 && ((gm >> pl_) & 1ull));
             int off = 0;
             while (true) {
                 // next target from off on that hits a row or has its partner here
@@ -1785,7 +1791,8 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
                 const int cj = ctz64(am);
                 const uint64_t cur = readlane_u64(val, cj);
                 const uint64_t d = readlane_u64(dsc, cj);
-                const int len = desc_len(d), pr = desc_partner(d);
+                const int len = desc_len(d), prd = desc_partner(d);
+                const int pr = (prd >= 0 && ((gm >> prd) & 1ull)) ? prd : -1;
                 const uint64_t bpr = pr >= 0 ? 1ull << pr : 0ull;
                 const uint64_t hit = cur & ~bpr;
                 if (lane == cj) val = hit;                  // H[j]
@@ -1805,7 +1812,8 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
                 }
                 off = cj + 1;
             }
-            if (jl < R) V[jl] = val;                        // H of the 64 (0 where nothing hit)
+            // H of the 64 in this wave's bits (0 where nothing hit)
+            if (jl < R && (raw ^ val)) atomicXor((unsigned long long*)&V[jl], raw ^ val);
         }
     }
     if (tid == 0) {
