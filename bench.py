@@ -188,8 +188,11 @@ def main() -> int:
         "replay": work[9] * 2 * row_b + work[8] * row_b,
         # the final tableau read and the columns of every target written (about d*d targets)
         "extract": per_step["extract"][1] * seg_bytes_per_launch(n, shots, args.mode, d * d, False),
-        # per deterministic measurement: its column and every multiplied stabilizer row read
-        "det": (work[2] + work[6]) * nb * 8 + work[3] * row_b,
+        # layer start: every target's column read, and every stabilizer row multiplied by a
+        # deterministic reduction (both passes; the second pass reduces few)
+        "classify": (work[2] + work[4] + work[6]) * nb * 8 + work[3] * row_b,
+        # after the chain: the columns of the targets it left deterministic
+        "det": work[6] * nb * 8,
     }
     pmc = load_pmc(args.workload, args.mode)
 

@@ -181,7 +181,8 @@ int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
  * each timed launch costs two event records on the stream).
  * stab_get_kernel_times writes, for each kernel id, the summed milliseconds and the number of
  * launches since timing started.  Kernel ids: 0 init, 1 noise draw, 2 segment (gates + noise
- * + column extraction), 3 classify, 4 deterministic batch, 5 random chain (stabilizer rows),
+ * + column extraction), 3 classes and deterministic outcomes at layer start, 4 outcomes of
+ * targets the random chain left deterministic, 5 random chain (stabilizer rows),
  * 6 reset/record, 7 record packing, 8 destabilizer replay, 9 column extraction after a layer
  * with random outcomes.  nkernels <= 10. */
 #define STAB_NUM_KERNELS 10

@@ -31,7 +31,6 @@ int fail(int code, const std::string& msg)
 constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
 constexpr int kSegThreads = 512;
 constexpr int kChainThreads = 512;
-constexpr int kMCap = 256;                // rows listed per deterministic measurement
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
 constexpr int kReplayThreads = 512;
@@ -101,7 +100,7 @@ struct stab_ctx {
     int max_lds = kLdsBytes;
     int* d_err = nullptr;
     unsigned long long* d_counters = nullptr;
-    DevBuf xcol, zcol, cls, mlist, mcount, obuf, events, record, packed, pend;
+    DevBuf xcol, zcol, cls, obuf, events, record, packed, pend;
     DevBuf plog_p, plog_row, plog_rs, plog_rd, ran;   // pivot log of the random chain
     DevBuf plist, pcnt, povf;                        // pending targets with x in each pivot
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -473,6 +472,7 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     }
     (void)hipFuncSetAttribute((const void*)k_segment, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_det, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -504,7 +504,7 @@ void stab_destroy(stab_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->mlist, &ctx->mcount, &ctx->obuf,
+    DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->obuf,
                       &ctx->events, &ctx->record, &ctx->packed, &ctx->pend, &ctx->plog_p,
                       &ctx->plog_row, &ctx->plog_rs, &ctx->plog_rd, &ctx->ran, &ctx->plist,
                       &ctx->pcnt, &ctx->povf};
@@ -622,9 +622,8 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     const size_t K = (size_t)std::max(P->Kmax, 1);
     int rc;
     if ((rc = ensure(ctx->xcol, (size_t)g.S * g.NB * K * 8)) || (rc = ensure(ctx->zcol, (size_t)g.S * g.NB * K * 8)) ||
-        (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->mcount, (size_t)g.S * K * 4)) ||
-        (rc = ensure(ctx->pend, (size_t)g.S * K * 4)) ||
-        (rc = ensure(ctx->mlist, (size_t)g.S * kMCap * K * 4)) || (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
+        (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->pend, (size_t)g.S * K * 4)) ||
+        (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
         (rc = ensure(ctx->events, (size_t)std::max<long long>(P->ev_cap_max, 1) * 8)) ||
         (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
         (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))) ||
@@ -637,8 +636,6 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
     uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
     int* cls = (int*)ctx->cls.p;
-    int* mcount = (int*)ctx->mcount.p;
-    int* mlist = (int*)ctx->mlist.p;
     uint8_t* obuf = (uint8_t*)ctx->obuf.p;
     uint2* events = (uint2*)ctx->events.p;
     uint8_t* record = (uint8_t*)ctx->record.p;
@@ -709,11 +706,11 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         } else {
             const MeasPlan& m = P->meas[st.second];
             const int K2 = m.K;
-            const dim3 cgrid((K2 + 63) / 64, g.S), dgrid((K2 + 3) / 4, g.S);
-            TIMED(ctx, 3, (k_classify<<<cgrid, 64 * kClsChunks, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 0)));
-            TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
-                                                                 mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -1)));
-            HIP_CHECK(ctx, hipMemsetAsync(ran, 0, sizeof(int), ctx->stream));
+            // classes of the targets and the outcomes of the deterministic ones (also clears ran)
+            const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
+            const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
+            TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 0)));
             TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
@@ -744,9 +741,8 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                                            ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
             // targets the chain found deterministic: reduced in parallel on the final tableau
-            TIMED(ctx, 3, (k_classify<<<cgrid, 64 * kClsChunks, 0, ctx->stream>>>(g, Xcol, K2, cls, mlist, mcount, kMCap, 1)));
-            TIMED(ctx, 4, (k_det<<<dgrid, 256, 0, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls, mlist,
-                                                                 mcount, kMCap, obuf, ctx->d_err, ctx->d_counters, -3)));
+            TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 1)));
             const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
             TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
                               g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,

@@ -500,248 +500,173 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 }
 
 // ------------------------------------------------------------------------------------------
-// Classify each target of a measurement layer at layer start: pivot = first stabilizer row
-// with x at the qubit (Sec. 2.4), or -1 (deterministic).  For deterministic ones, list the
-// destabilizer rows with x at the qubit (they select the stabilizers whose product is +-Z_a).
-// Pass 1 (after the random chain) only lists the rows of targets the chain found
-// deterministic (cls == -2) and marks them -3.
-// Reads of Xcol [s][band][k] are coalesced over k (the lanes of a wave).
+// Classification and deterministic outcomes of a measurement layer (Sec. 2.4), one wave per
+// (copy, target).
+//
+// pass 0, at layer start: the block's eight consecutive targets have their x columns staged in
+// LDS first (a band's eight words are contiguous in Xcol, so the loads are coalesced), then a
+// wave takes each target's column one word per 64-row band and lane.  The first stabilizer with x at the qubit is the pivot: the target is
+// random, its class is that stabilizer index (the random chain takes it).  Without one the
+// outcome is deterministic: +-Z_a is the product of the stabilizers NR + i over the
+// destabilizers i with x at the qubit (class -1).  pass 1, after the chain on the final
+// tableau (only when a random target ran): the targets the chain marked deterministic (-2)
+// are reduced and marked -3.  A deterministic outcome is unchanged by Z measurements and
+// resets on other qubits, so every one of a layer is reduced in parallel (the paper
+// serialises every row behind two grid barriers, Alg. 2).
+//
+// The product.  The destabilizer bits are enumerated in row order (ballot, then scalar loops
+// over the few nonzero words), 64 rows at a time with lane c holding the c-th; rows are loaded
+// kDetRowBatch at a time (no load conditional, so a batch is in flight at once).  Its phase is
+// telescoped: with |u| the number of qubits where u has both x and z, multiplying rows into
+// the scratch row S raises i to sum|row| - |S| + 2 sum z_row.x_S (mod 4), and only the parity
+// of the last sum matters, so it is XOR-accumulated and popcounted once.  The per-shot part of
+// the sign is the parity of each shot's sign bits over the same rows; the bits of a shot group
+// of 64 gather in LDS (nrdw words per wave).
 // ------------------------------------------------------------------------------------------
-// Block: 64 targets (lane) x kClsChunks band ranges (wave), so a target's scan is split
-// kClsChunks ways; the ranges' results combine in band order through LDS.
-constexpr int kClsChunks = 4;
+constexpr int kDetTargets = 8;                 // targets (waves) per block
+constexpr int kDetRowBatch = 2;                // rows a wave loads at once
 
-__global__ void __launch_bounds__(64 * kClsChunks)
-k_classify(Geom g, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
-           int* __restrict__ mlist, int* __restrict__ mcount, int mcap, int pass)
+__global__ void __launch_bounds__(64 * kDetTargets) __attribute__((amdgpu_waves_per_eu(4)))
+k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
+      const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
+      uint8_t* __restrict__ obuf, int* __restrict__ ran, int* __restrict__ err,
+      unsigned long long* __restrict__ counters, int pass)
 {
-    __shared__ int s_piv[kClsChunks][64], s_cnt[kClsChunks][64];
+    extern __shared__ uint64_t dsm[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * kDetTargets, k = k0 + wave;
     const int s = blockIdx.y;
-    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + lane;
-    const bool in = k < K;
-    const bool mine = in && (pass == 0 || cls[s * K + k] == -2);
-    const uint64_t* X = Xcol + (size_t)s * g.NB * K;
-    const int w0 = c * g.Wr / kClsChunks, w1 = (c + 1) * g.Wr / kClsChunks;
-    // this range's first stabilizer with x at the qubit; 8 loads in flight per step
-    int piv = INT_MAX;
-    for (int w = w0; pass == 0 && mine && w < w1 && piv == INT_MAX; w += 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(g.Wr + w + u) * K + k] : 0ull;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (piv == INT_MAX && v[u]) piv = (w + u) * 64 + ctz64(v[u]);
+    const int NB = g.NB, nrdw = (g.bpc + 63) >> 6;
+    uint64_t* colw = dsm;                                          // [kDetTargets][NB] columns
+    uint64_t* parw = dsm + (size_t)kDetTargets * NB + (size_t)wave * nrdw;   // shot parity bits
+    if (pass == 0) {
+        // the next launch (the random chain) sets this when a random target runs
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran = 0;
+    } else if (*ran == 0) {
+        return;
     }
-    s_piv[c][lane] = piv;
+    const uint64_t* X = Xcol + (size_t)s * NB * K;
+    for (int i = threadIdx.x; i < NB * kDetTargets; i += blockDim.x) {
+        const int w = i / kDetTargets, j = i - w * kDetTargets;
+        colw[j * NB + w] = k0 + j < K ? X[(size_t)w * K + k0 + j] : 0ull;
+    }
     __syncthreads();
-    int pv = INT_MAX;
+    if (k >= K) return;
+    if (pass == 1 && cls[s * K + k] != -2) return;
+    const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
+    const uint64_t* rsc = rs + (size_t)s * NB;
+    // the column: destabilizer words cd, stabilizer words cs (band lane + 64 u of each half)
+    uint64_t cd[kMaxStabBandsPerLane], cs[kMaxStabBandsPerLane];
 #pragma unroll
-    for (int cc = 0; cc < kClsChunks; ++cc) pv = min(pv, s_piv[cc][lane]);
-    const bool det = mine && pv == INT_MAX;
-    if (mine && c == 0) cls[s * K + k] = (pass == 0) ? (det ? -1 : pv) : -3;
-    // deterministic: the destabilizers with x at the qubit, in row order (this range's share
-    // after the counts of the ranges before it)
-    int cnt = 0;
-    for (int w = w0; det && w < w1; w += 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(w + u) * K + k] : 0ull;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) cnt += __popcll(v[u]);
+    for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+        const int w = lane + 64 * u;
+        cd[u] = w < g.Wr ? colw[wave * NB + w] : 0ull;
+        cs[u] = w < g.Wr && pass == 0 ? colw[wave * NB + g.Wr + w] : 0ull;
     }
-    s_cnt[c][lane] = cnt;
-    __syncthreads();
-    if (!det) return;
-    int pos = 0, tot = 0;
+    if (pass == 0) {
 #pragma unroll
-    for (int cc = 0; cc < kClsChunks; ++cc) {
-        if (cc < c) pos += s_cnt[cc][lane];
-        tot += s_cnt[cc][lane];
-    }
-    for (int w = w0; w < w1 && pos < mcap; w += 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (w + u < w1) ? X[(size_t)(w + u) * K + k] : 0ull;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            while (v[u]) {
-                const int bit = ctz64(v[u]);
-                v[u] &= v[u] - 1;
-                if (pos < mcap) mlist[((size_t)s * mcap + pos) * K + k] = (w + u) * 64 + bit;
-                ++pos;
+        for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+            const uint64_t m = __ballot(cs[u] != 0ull);
+            if (m) {
+                const int l = ctz64(m);
+                if (lane == 0) cls[s * K + k] = (l + 64 * u) * 64 + ctz64(readlane_u64(cs[u], l));
+                return;                              // random at layer start
             }
         }
     }
-    if (c == 0) mcount[s * K + k] = tot;
-}
-
-// Deterministic outcome, one wave: product of stabilizer rows NR+i over the listed rows i,
-// in increasing i (Alg. 2 of the paper reduces the same product into a scratch row).  Each
-// lane owns column words j = lane + 64 t and keeps its part of the scratch row in registers;
-// the i-power of every rowsum step is accumulated per lane and reduced once at the end.
-// The x part of the product must vanish (the product is +-Z_a).
-// tb / rsc: this copy's tableau and sign words.
-template <typename RowFn>
-__device__ __forceinline__ int det_wave_shared(const Geom& g, const uint64_t* __restrict__ tb,
-                                               const uint64_t* __restrict__ rsc, int lane,
-                                               int nrows, RowFn row_of, int* __restrict__ err)
-{
-    uint64_t sx[kMaxWordsPerLane], sz[kMaxWordsPerLane];
-#pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) sx[t] = sz[t] = 0;
-    int G = 0, rsum = 0;
+    if (lane == 0) cls[s * K + k] = pass == 0 ? -1 : -3;
+    for (int u = lane; u < nrdw; u += 64) parw[u] = 0;
     const uint64_t* base = tb + (size_t)g.NR * g.RS;
-    for (int c = 0; c < nrows; ++c) {
-        const int i = row_of(c);
-        const uint64_t* row = base + (size_t)i * g.RS;
+    int jc[kMaxWordsPerLane];
+    uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
-            const int j = lane + 64 * t;
-            if (j < g.Wc) {
-                const uint64_t x1 = row[j], z1 = row[g.Wc + j];
-                G += gsum(x1, z1, sx[t], sz[t]);
-                sx[t] ^= x1;
-                sz[t] ^= z1;
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        const int j = lane + 64 * t;
+        jc[t] = j < g.Wc ? j : 0;
+        msk[t] = j < g.Wc ? ~0ull : 0ull;
+        sx[t] = sz[t] = cr[t] = 0;
+    }
+    int G = 0, rsum = 0, cnt = 0, nc = 0, myrow = 0;
+    // multiply the nc listed rows (lane c holds the c-th) into S, and their shot sign bits
+    auto flush = [&]() {
+        rsum += __popcll(__ballot(lane < nc && ((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull)));
+        for (int u0 = 0; u0 < nc; u0 += kDetRowBatch) {
+            uint64_t rx[kDetRowBatch][kMaxWordsPerLane], rz[kDetRowBatch][kMaxWordsPerLane];
+#pragma unroll
+            for (int u = 0; u < kDetRowBatch; ++u) {
+                const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
+                const uint64_t* row = base + (size_t)i * g.RS;
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    rx[u][t] = row[jc[t]];
+                    rz[u][t] = row[g.Wc + jc[t]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kDetRowBatch; ++u) {
+                if (u0 + u >= nc) break;
+#pragma unroll
+                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
+                    cr[t] ^= b & sx[t];
+                    G += __popcll(a & b);
+                    sx[t] ^= a;
+                    sz[t] ^= b;
+                }
             }
         }
-        rsum += (int)((rsc[g.Wr + (i >> 6)] >> (i & 63)) & 1ull);
+        for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+            const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b0 + lane, g.bpc - 1)) * g.NB + g.Wr;
+            int par = 0;
+            for (int c = 0; c < nc; c += 8) {
+                int iu[8];
+                uint64_t wv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
+            }
+            const uint64_t pb = __ballot(par & 1);
+            if (lane == 0) parw[b0 >> 6] ^= pb;
+        }
+        cnt += nc;
+        nc = 0;
+    };
+#pragma unroll
+    for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+        uint64_t lanes = __ballot(cd[u] != 0ull);
+        while (lanes) {
+            const int l = ctz64(lanes);
+            lanes &= lanes - 1;
+            uint64_t v = readlane_u64(cd[u], l);
+            const int wb = l + 64 * u;
+            while (v) {
+                const int bit = ctz64(v);
+                v &= v - 1;
+                if (lane == nc) myrow = wb * 64 + bit;
+                if (++nc == 64) flush();
+            }
+        }
     }
-    G = wave_sum(G);
+    if (nc) flush();
     uint64_t xres = 0;
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) xres |= sx[t];
+    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
+        xres |= sx[t];
+    }
+    G = wave_sum(G);
     xres = wave_or(xres);
     const int e = (2 * rsum + G) & 3;
     if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
-    return e >> 1;
-}
-
-// One wave per (copy, target) whose class is `want`: -1 for the targets deterministic at layer
-// start, -3 for those the random chain found deterministic.  A deterministic outcome is the
-// same at any later point of the layer (Z measurements and X resets on other qubits keep +-Z_a
-// in the stabilizer group with its sign), so both kinds are reduced in parallel.
-__global__ void k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
-                      const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K,
-                      const int* __restrict__ cls, const int* __restrict__ mlist,
-                      const int* __restrict__ mcount, int mcap, uint8_t* __restrict__ obuf,
-                      int* __restrict__ err, unsigned long long* __restrict__ counters, int want)
-{
-    const int lane = threadIdx.x & 63;
-    const int k = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
-    const int s = blockIdx.y;
-    if (k >= K) return;
-    if (cls[s * K + k] != want) return;
-    const int cnt = mcount[s * K + k];
-    const uint64_t* X = Xcol + (size_t)s * g.NB * K;
-    const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
-    const uint64_t* rsc = rs + (size_t)s * g.NB;
-    if (cnt <= mcap) {
-        // rows listed: ids 64 at a time, row words 4 rows at a time, all loads of a batch in
-        // flight (none conditional: lanes past Wc read word 0 and are masked, rows past the
-        // list repeat its last one and are skipped).  The product's phase is telescoped as in
-        // the replay: sum|row| - |S| + 2 (parity of sum z_row.x_S), |u| = popcount(x & z).
-        const uint64_t* base = tb + (size_t)g.NR * g.RS;
-        const int* ml = mlist + (size_t)s * mcap * K + k;
-        int jc[kMaxWordsPerLane];
-        uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
-#pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
-            const int j = lane + 64 * t;
-            jc[t] = j < g.Wc ? j : 0;
-            msk[t] = j < g.Wc ? ~0ull : 0ull;
-            sx[t] = sz[t] = cr[t] = 0;
-        }
-        int G = 0, rsum = 0;
-        for (int c0 = 0; c0 < cnt; c0 += 64) {
-            const int nc = min(64, cnt - c0);
-            const int myrow = lane < nc ? ml[(size_t)(c0 + lane) * K] : 0;
-            rsum += wave_sum(lane < nc ? (int)((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull) : 0);
-            for (int u0 = 0; u0 < nc; u0 += 4) {
-                uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
-                    const uint64_t* row = base + (size_t)i * g.RS;
-#pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        rx[u][t] = row[jc[t]];
-                        rz[u][t] = row[g.Wc + jc[t]];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (u0 + u >= nc) break;
-#pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                        const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
-                        cr[t] ^= b & sx[t];
-                        G += __popcll(a & b);
-                        sx[t] ^= a;
-                        sz[t] ^= b;
-                    }
-                }
-            }
-        }
-        uint64_t xres = 0;
-#pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
-            G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
-            xres |= sx[t];
-        }
-        G = wave_sum(G);
-        xres = wave_or(xres);
-        const int e = (2 * rsum + G) & 3;
-        if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
-        const int shared = e >> 1;
-        // per-shot part of the sign: parity of the shot's sign bits over the same rows, eight
-        // rows' words in flight at a time
-        for (int b0 = 0; b0 < g.bpc; b0 += 64) {
-            const int b = b0 + lane;
-            const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b, g.bpc - 1)) * g.NB + g.Wr;
-            int par = 0;
-            for (int c0 = 0; c0 < cnt; c0 += 64) {
-                const int nc = min(64, cnt - c0);
-                const int myrow = lane < nc ? ml[(size_t)(c0 + lane) * K] : 0;
-                for (int c = 0; c < nc; c += 8) {
-                    int iu[8];
-                    uint64_t wv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
-                }
-            }
-            if (b < g.bpc) obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
-        }
-    } else {
-        // long list: walk the destabilizer x-words of the column directly
-        auto nth = [&](int c) {
-            int seen = 0;
-            for (int w = 0; w < g.Wr; ++w) {
-                uint64_t v = X[(size_t)w * K + k];
-                const int pc = __popcll(v);
-                if (seen + pc > c) {
-                    for (int q = 0; q < c - seen; ++q) v &= v - 1;
-                    return w * 64 + ctz64(v);
-                }
-                seen += pc;
-            }
-            return 0;
-        };
-        const int shared = det_wave_shared(g, tb, rsc, lane, cnt, nth, err);
-        for (int b = lane; b < g.bpc; b += 64) {
-            const uint64_t* rdb = rd + (size_t)(s * g.bpc + b) * g.NB + g.Wr;
-            int par = 0;
-            for (int w = 0; w < g.Wr; ++w) par ^= __popcll(rdb[w] & X[(size_t)w * K + k]) & 1;
-            obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ par);
-        }
-    }
+    const int shared = e >> 1;
+    for (int b = lane; b < g.bpc; b += 64)
+        obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ (int)((parw[b >> 6] >> (b & 63)) & 1ull));
     if (lane == 0) {
-        count_add(counters, want == -1 ? 2 : 6, 1ull);
+        count_add(counters, pass == 0 ? 2 : 6, 1ull);
         count_add(counters, 3, (unsigned long long)cnt);
     }
 }
@@ -1506,12 +1431,12 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 load_row_lane(wideP + j * g.RS, g.Wc, lane, xp, zp);
                 rowsum_rows(c, xp, zp, s_rsp[j], srows + sl * kRCap, scnt[sl], wave, nwaves, lane);
             }
-            if (wave < nsel) {
-                const int sl = wpos[selpos[wave]];
+            for (int j = wave; j < nsel; j += nwaves) {
+                const int sl = wpos[selpos[j]];
                 uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
-                load_row_lane(wideP + wave * g.RS, g.Wc, lane, xp, zp);
-                random_epilogue(c, sk[sl], spiv[sl], s_rsp[wave], xp, zp, srows + sl * kRCap, scnt[sl], lane,
-                                aff, &s_aff, wave);
+                load_row_lane(wideP + j * g.RS, g.Wc, lane, xp, zp);
+                random_epilogue(c, sk[sl], spiv[sl], s_rsp[j], xp, zp, srows + sl * kRCap, scnt[sl], lane,
+                                aff, &s_aff, j);
             }
             __syncthreads();
             // column upkeep of the batch: (entry, word) pairs over the block; the extra slot
