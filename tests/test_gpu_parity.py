@@ -270,3 +270,28 @@ def test_largest_supported_n(stab):
     c.append(Cc.MR, [int(q) for q in rng.choice(n, 200, replace=False)])
     c.append(Cc.M, [n - 1, n - 2, 0])
     _compare(stab, c, shots=2, seed=1, mode="shared", tableau_shots=(1,))
+
+
+def test_replay_list_and_testing_forms(stab):
+    """Both forms of the destabilizer replay, each bit-exact against the oracle: on a dense
+    tableau the pivots' pending lists overflow and rows are replayed by testing every run target
+    (work counter 10); on a surface-code readout every row is replayed from the hit words."""
+    n = 129
+    dense = Cc.random_layered_clifford(n, layers=40, seed=77, meas_every=4, meas_frac=0.3)
+    dense.append(Cc.M, list(range(n)))
+    surf, _ = Cc.surface_code_memory(7, 3, 0.0)
+    for circ, expect_testing in ((dense, True), (surf, False)):
+        want, (tx, tz, tr) = O.run(circ, 2, 9, want_tableau=True)
+        ctx = stab.Context(circ.n, 2, mode="shared", seed=9)
+        got = ctx.run(circ)
+        c = ctx.counters()
+        say(f"n={circ.n}: replay rows {int(c[9])}, by testing {int(c[10])}")
+        assert np.array_equal(got, want)
+        x, z, r = ctx.get_tableau(1)
+        assert np.array_equal(x, tx[1]) and np.array_equal(z, tz[1]) and np.array_equal(r, tr[1])
+        assert c[9] > 0
+        if expect_testing:
+            assert c[10] > 0
+        else:
+            assert c[10] == 0
+        ctx.close()
