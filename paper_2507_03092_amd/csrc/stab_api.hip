@@ -721,7 +721,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
                               plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
-                              (const int*)ctx->povf.p, ent_cap, ctx->d_err, ctx->d_counters)));
+                              (const int*)ctx->povf.p, ran, ent_cap, ctx->d_err, ctx->d_counters)));
             {
                 SegArgs a{};
                 a.items = P->d_items;

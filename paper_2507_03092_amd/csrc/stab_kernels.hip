@@ -1191,6 +1191,22 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* pd = pend + (size_t)s * K;
     int* cl = cls + (size_t)s * K;
 
+    // a layer with no random target at its start (most of them) ends here, after one pass of
+    // independent loads (nothing runs, so nothing downstream reads the log)
+    {
+        bool any = false;
+        for (int k0 = 0; k0 < K; k0 += 8 * nt) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u * nt + tid;
+                v[u] = k < K ? cl[k] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) any |= v[u] >= 0;
+        }
+        if (!__syncthreads_or(any)) return;
+    }
     // no target of this layer has run yet (the replay reads the log)
     for (int k = tid; k < K; k += nt) {
         c.lp[k] = -1;
@@ -1568,8 +1584,9 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
          const int* __restrict__ plog_p, const uint64_t* __restrict__ plog_row,
          const int* __restrict__ plog_rs, const uint64_t* __restrict__ plog_rd,
          const uint16_t* __restrict__ plist, const int* __restrict__ pcnt, const int* __restrict__ povf,
-         int ent_cap, int* __restrict__ err, unsigned long long* __restrict__ counters)
+         const int* __restrict__ ran, int ent_cap, int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
+    if (*ran == 0) return;                             // no random target ran in this layer
     extern __shared__ uint64_t rsm[];
     const int band = blockIdx.x, s = blockIdx.y;
     const int tid = threadIdx.x, nt = blockDim.x;
