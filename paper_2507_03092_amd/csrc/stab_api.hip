@@ -259,6 +259,10 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
     if (ninstr < 0 || ntg < 0) return fail(STAB_EINVAL, "negative count");
     if ((ninstr > 0 && !ins) || (ntg > 0 && !tg)) return fail(STAB_EINVAL, "null stream");
     const int n = g.n;
+    // gate and noise targets are stored as the word index of the qubit's column in the segment
+    // kernel's staged tile, (q mod 64) * (RS + 1) + q / 64
+    const uint32_t RSP = (uint32_t)g.RS + 1u;
+    auto tile_index = [&](int q) { return (uint32_t)(q & 63) * RSP + (uint32_t)(q >> 6); };
     std::vector<int> stamp(n, -1), mstamp(n, -1);
     int layer_id = 0, mlayer_id = 0;
     SegPlan seg;
@@ -310,7 +314,7 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
                 if (stamp[t[q]] == layer_id) close_layer();
                 if (open_begin < 0) open_begin = (int)gates.size();
                 stamp[t[q]] = layer_id;
-                gates.push_back(make_uint2(kind | ((uint32_t)t[q] << 4), 0u));
+                gates.push_back(make_uint2(kind | (tile_index(t[q]) << 4), 0u));
                 if (kind == STAB_H || kind == STAB_S) seg.modifies = 1;
             }
             break;
@@ -321,7 +325,7 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
                 if (stamp[c] == layer_id || stamp[d] == layer_id) close_layer();
                 if (open_begin < 0) open_begin = (int)gates.size();
                 stamp[c] = stamp[d] = layer_id;
-                gates.push_back(make_uint2(kind | ((uint32_t)c << 4), (uint32_t)d));
+                gates.push_back(make_uint2(kind | (tile_index(c) << 4), tile_index(d)));
                 seg.modifies = 1;
             }
             break;
@@ -341,7 +345,7 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
             // event bucket (their events commute) and one item of the segment kernel
             const bool join = seg.item_count > 0 && items.back().x == 1;
             d.bucket = join ? items.back().w : (int)ev_base.size();
-            noise_tg.insert(noise_tg.end(), t, t + nt);
+            for (uint32_t q = 0; q < nt; ++q) noise_tg.push_back((int)tile_index(t[q]));
             unit_start.push_back(seg.units);
             seg.units += units;
             seg.max_units = std::max(seg.max_units, units);

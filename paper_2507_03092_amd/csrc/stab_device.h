@@ -83,8 +83,8 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
 struct SegArgs {
     const int4* items;     // {0, first gate, gate count, -1} or {1, first event slot, event capacity, bucket}
     int nitems;
-    const uint2* gates;    // {kind | q0 << 4, q1}
-    const uint2* events;   // noise events {qubit | pauli << 28, shot}
+    const uint2* gates;    // {kind | i0 << 4, i1}, i = the qubit's word index in the staged tile
+    const uint2* events;   // noise events {tile word index of the qubit | pauli << 28, shot}
     const int* ev_count;   // per bucket
     const int* ev_base;    // per bucket: first slot in events
     int write_back;        // 1 if some gate changes x|z (H, S, CX)

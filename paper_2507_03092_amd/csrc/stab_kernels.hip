@@ -192,8 +192,8 @@ __global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict_
 // ------------------------------------------------------------------------------------------
 // Noise draws for one segment: block (x, y) handles kNoiseUnitsPerBlock consecutive (shot,
 // unit) pairs of noise layer y.  Draws never depend on the tableau, so they are made up front
-// and the segment kernel applies them at their layer.  Event = (qubit | pauli << 28, shot).
-// A block gathers its events in LDS and reserves space with one atomic.
+// and the segment kernel applies them at their layer.  Event = (tile word index of the qubit
+// | pauli << 28, shot).  A block gathers its events in LDS and reserves space with one atomic.
 // ------------------------------------------------------------------------------------------
 constexpr int kNoiseThreads = 1024;
 constexpr int kNoiseUnitsPerBlock = 4 * kNoiseThreads;
@@ -286,12 +286,12 @@ __device__ __forceinline__ void fetch_item(const SegArgs& a, int it, int tid, in
     }
 }
 
-// A gate on the 32 staged rows: x word of qubit q at T[(q & 63) * RSP + (q >> 6)], z at + Wc.
-__device__ __forceinline__ void apply_gate(uint32_t* T, int RSP, int Wc, uint2 gt, uint32_t& racc)
+// A gate on the 32 staged rows: x word of qubit q at T[(q & 63) * RSP + (q >> 6)], z at + Wc;
+// the gate list holds these word indices (resolved on the host).
+__device__ __forceinline__ void apply_gate(uint32_t* T, int Wc, uint2 gt, uint32_t& racc)
 {
     const int kind = (int)(gt.x & 15u);
-    const int q0 = (int)(gt.x >> 4);
-    const int i0 = (q0 & 63) * RSP + (q0 >> 6);
+    const int i0 = (int)(gt.x >> 4);
     const uint32_t x0 = T[i0], z0 = T[i0 + Wc];
     switch (kind) {
     case STAB_KIND_H:
@@ -307,8 +307,7 @@ __device__ __forceinline__ void apply_gate(uint32_t* T, int RSP, int Wc, uint2 g
     case STAB_KIND_Y: racc ^= x0 ^ z0; break;
     case STAB_KIND_Z: racc ^= x0; break;
     case STAB_KIND_CX: {
-        const int q1 = (int)gt.y;
-        const int i1 = (q1 & 63) * RSP + (q1 >> 6);
+        const int i1 = (int)gt.y;
         const uint32_t x1 = T[i1], z1 = T[i1 + Wc];
         racc ^= x0 & z1 & ~(x1 ^ z0);
         T[i1] = x1 ^ x0;
@@ -318,15 +317,15 @@ __device__ __forceinline__ void apply_gate(uint32_t* T, int RSP, int Wc, uint2 g
     }
 }
 
-// Noise event {qubit | pauli << 28, shot}: flip the signs of the rows the Pauli anticommutes with.
-__device__ __forceinline__ void apply_event(const uint32_t* T, int RSP, int Wc, uint2 v, int s, int hb,
+// Noise event {tile word index of the qubit | pauli << 28, shot}: flip the signs of the rows the
+// Pauli anticommutes with.
+__device__ __forceinline__ void apply_event(const uint32_t* T, int Wc, uint2 v, int s, int hb,
                                             const Geom& g, const SegArgs& a, uint32_t* rdacc,
                                             uint32_t* rd32)
 {
     const int sb = (int)v.y - s * g.bpc;
     if (sb < 0 || sb >= g.bpc) return;
-    const int q = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
-    const int iq = (q & 63) * RSP + (q >> 6);
+    const int iq = (int)(v.x & 0x0FFFFFFFu), P = (int)(v.x >> 28);
     const uint32_t xq = T[iq], zq = T[iq + Wc];
     const uint32_t m = (P == 1) ? zq : (P == 3) ? xq : (xq ^ zq);
     if (m) {
@@ -440,15 +439,15 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
         if (cur.type == 0) {
 #pragma unroll
             for (int u = 0; u < kSegPrefetch; ++u)
-                if (tid + u * nt < cur.count) apply_gate(T, RSP, Wc, cur.v[u], racc);
+                if (tid + u * nt < cur.count) apply_gate(T, Wc, cur.v[u], racc);
             for (int gi = tid + kSegPrefetch * nt; gi < cur.count; gi += nt)
-                apply_gate(T, RSP, Wc, cur.src[gi], racc);
+                apply_gate(T, Wc, cur.src[gi], racc);
         } else {
 #pragma unroll
             for (int u = 0; u < kSegPrefetch; ++u)
-                if (tid + u * nt < cur.count) apply_event(T, RSP, Wc, cur.v[u], s, 2 * band + half, g, a, rdacc, rd32);
+                if (tid + u * nt < cur.count) apply_event(T, Wc, cur.v[u], s, 2 * band + half, g, a, rdacc, rd32);
             for (int e = tid + kSegPrefetch * nt; e < cur.count; e += nt)
-                apply_event(T, RSP, Wc, cur.src[e], s, 2 * band + half, g, a, rdacc, rd32);
+                apply_event(T, Wc, cur.src[e], s, 2 * band + half, g, a, rdacc, rd32);
         }
         __syncthreads();
         cur = nxt;
