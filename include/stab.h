@@ -187,6 +187,16 @@ int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
  * with random outcomes.  nkernels <= 10. */
 #define STAB_NUM_KERNELS 10
 int stab_set_timing(stab_ctx *ctx, int32_t kernel_mask);
+
+/* Graph replay of stab_execute.  With enable != 0 (and no per-kernel timing selected),
+ * stab_execute captures the device work of a program (every kernel launch up to the record
+ * packing) into a hipGraph the first time it runs it, and replays the graph while the program,
+ * the RNG seed and first shot, the instruction counter and the context's buffers are the same
+ * as at capture (a program executed right after stab_reset, again and again, replays); any
+ * other execution captures anew.  Results are those of the eager launches.  The record copy
+ * to the host and the consistency check stay outside the graph.  Errors: STAB_EINVAL (null
+ * context). */
+int stab_set_graph(stab_ctx *ctx, int32_t enable);
 int stab_get_kernel_times(stab_ctx *ctx, double *ms, uint64_t *launches, int32_t nkernels);
 
 /* ---------------------------------------------------------------------------------------

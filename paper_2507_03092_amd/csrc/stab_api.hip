@@ -10,6 +10,7 @@
 #include "stab.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -106,6 +107,12 @@ struct stab_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing (stab_set_timing)
     bool timing = false;
+    // captured launch sequence of the last program executed with graphs on, and its key
+    bool graph_on = false;
+    hipStream_t cap_stream = nullptr;   // capture happens here (the context's stream may be the null stream)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey[5] = {0, 0, 0, 0, 0};
     uint32_t tmask = 0;           // kernel ids timed (bit k = kernel k)
     std::vector<hipEvent_t> evpool;
     std::vector<int> evkind;      // kernel id of each recorded pair
@@ -159,6 +166,7 @@ struct stab_program {
     int* d_mtq = nullptr;
     // geometry it was compiled for
     int n = 0, B = 0;
+    uint64_t serial = 0;   // distinct for every program of the process (keys captured graphs)
 };
 
 namespace {
@@ -514,6 +522,9 @@ void stab_destroy(stab_ctx* ctx)
                       &ctx->pcnt, &ctx->povf};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
@@ -543,6 +554,8 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     *out = nullptr;
     if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
     stab_program* P = new stab_program();
+    static std::atomic<uint64_t> program_serial{0};
+    P->serial = ++program_serial;
     std::vector<int4> items;
     std::vector<uint2> gates;
     std::vector<NoiseDesc> noise;
@@ -670,95 +683,140 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     uint64_t* plog_rd = (uint64_t*)ctx->plog_rd.p;
     int* ran = (int*)ctx->ran.p;
 
-    HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (P->nnoise > 0)
-        HIP_CHECK(ctx, hipMemsetAsync(P->d_ev_count, 0, (size_t)P->nnoise * sizeof(int), ctx->stream));
-    for (const auto& st : P->steps) {
-        if (st.first == 0) {
-            const SegPlan& sp = P->segs[st.second];
-            if (sp.noise_count > 0) {
-                const long long most = (long long)sp.max_units * g.B;
-                const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
-                                (unsigned)sp.noise_count);
-                TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
-                    P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                    P->d_ev_base, P->d_ev_count, ctx->d_counters)));
-            }
-            if (sp.item_count > 0 || sp.meas >= 0) {
-                SegArgs a{};
-                a.items = P->d_items + sp.item_begin;
-                a.nitems = sp.item_count;
-                a.gates = P->d_gates;
-                a.events = events;
-                a.ev_count = P->d_ev_count;
-                a.ev_base = P->d_ev_base;
-                a.write_back = sp.modifies;
-                a.lds_rd = lds_rd;
-                if (sp.meas >= 0) {
-                    const MeasPlan& m = P->meas[sp.meas];
-                    a.ext_q = P->d_mtq + m.tq_begin;
-                    a.K = m.K;
-                } else {
-                    a.ext_q = nullptr;
-                    a.K = 0;
-                }
-                a.Xcol = Xcol;
-                a.Zcol = Zcol;
-                TIMED(ctx, 2, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
-                                  g, ctx->tab, ctx->rs, ctx->rd, a)));
-            }
-        } else {
-            const MeasPlan& m = P->meas[st.second];
-            const int K2 = m.K;
-            // classes of the targets and the outcomes of the deterministic ones (also clears ran)
-            const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
-            const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
-            TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 0)));
-            TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
-                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
-                              (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
-                              m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
-                              (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
-            // destabilizer updates of the run targets, then fresh columns of the final tableau
-            // (skipped on the device when nothing ran)
-            TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
-                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
-                              plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
-                              (const int*)ctx->povf.p, ran, ent_cap, ctx->d_err, ctx->d_counters)));
-            {
-                SegArgs a{};
-                a.items = P->d_items;
-                a.nitems = 0;
-                a.gates = P->d_gates;
-                a.events = events;
-                a.ev_count = P->d_ev_count;
-                a.ev_base = P->d_ev_base;
-                a.write_back = 0;
-                a.lds_rd = 0;
-                a.ext_q = P->d_mtq + m.tq_begin;
-                a.K = K2;
-                a.Xcol = Xcol;
-                a.Zcol = Zcol;
-                a.gate = ran;
-                TIMED(ctx, 9, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, (size_t)seg_lds_words(g.RS) * 4,
-                                           ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
-            }
-            // targets the chain found deterministic: reduced in parallel on the final tableau
-            TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 1)));
-            const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
-            TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
-                              g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
-                              do_record)));
-        }
-    }
     const long long nbytes = (P->nrec + 7) / 8;
+    // every launch of the program, eagerly or into a graph (a fill kernel clears the event
+    // counts: no memset node in a captured graph)
+    auto enqueue = [&]() -> int {
+        if (P->nnoise > 0)
+            k_zero32<<<1, 256, 0, ctx->stream>>>((uint32_t*)P->d_ev_count, (long long)P->nnoise);
+        for (const auto& st : P->steps) {
+            if (st.first == 0) {
+                const SegPlan& sp = P->segs[st.second];
+                if (sp.noise_count > 0) {
+                    const long long most = (long long)sp.max_units * g.B;
+                    const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
+                                    (unsigned)sp.noise_count);
+                    TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
+                        P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
+                        P->d_ev_base, P->d_ev_count, ctx->d_counters)));
+                }
+                if (sp.item_count > 0 || sp.meas >= 0) {
+                    SegArgs a{};
+                    a.items = P->d_items + sp.item_begin;
+                    a.nitems = sp.item_count;
+                    a.gates = P->d_gates;
+                    a.events = events;
+                    a.ev_count = P->d_ev_count;
+                    a.ev_base = P->d_ev_base;
+                    a.write_back = sp.modifies;
+                    a.lds_rd = lds_rd;
+                    if (sp.meas >= 0) {
+                        const MeasPlan& m = P->meas[sp.meas];
+                        a.ext_q = P->d_mtq + m.tq_begin;
+                        a.K = m.K;
+                    } else {
+                        a.ext_q = nullptr;
+                        a.K = 0;
+                    }
+                    a.Xcol = Xcol;
+                    a.Zcol = Zcol;
+                    TIMED(ctx, 2, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
+                                      g, ctx->tab, ctx->rs, ctx->rd, a)));
+                }
+            } else {
+                const MeasPlan& m = P->meas[st.second];
+                const int K2 = m.K;
+                // classes of the targets and the outcomes of the deterministic ones (also clears ran)
+                const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
+                const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
+                TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 0)));
+                TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+                                  g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
+                                  (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
+                                  m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
+                                  (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
+                // destabilizer updates of the run targets, then fresh columns of the final tableau
+                // (skipped on the device when nothing ran)
+                TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
+                                  g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
+                                  plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
+                                  (const int*)ctx->povf.p, ran, ent_cap, ctx->d_err, ctx->d_counters)));
+                {
+                    SegArgs a{};
+                    a.items = P->d_items;
+                    a.nitems = 0;
+                    a.gates = P->d_gates;
+                    a.events = events;
+                    a.ev_count = P->d_ev_count;
+                    a.ev_base = P->d_ev_base;
+                    a.write_back = 0;
+                    a.lds_rd = 0;
+                    a.ext_q = P->d_mtq + m.tq_begin;
+                    a.K = K2;
+                    a.Xcol = Xcol;
+                    a.Zcol = Zcol;
+                    a.gate = ran;
+                    TIMED(ctx, 9, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, (size_t)seg_lds_words(g.RS) * 4,
+                                               ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
+                }
+                // targets the chain found deterministic: reduced in parallel on the final tableau
+                TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 1)));
+                const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
+                TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
+                                  g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
+                                  do_record)));
+            }
+        }
+        if (P->nrec > 0) {
+            const long long total = nbytes * g.B;
+            const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
+            TIMED(ctx, 7, (k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p)));
+        }
+        HIP_CHECK(ctx, hipGetLastError());
+        return STAB_OK;
+    };
+
+    HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (ctx->graph_on && !ctx->timing) {
+        // the launches depend on the program, the RNG key, the instruction counter and the
+        // buffers: replay the captured graph while they are unchanged, capture again otherwise
+        uint64_t bufsig = 0;
+        const DevBuf* bufs[] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->obuf, &ctx->events, &ctx->record,
+                                &ctx->packed, &ctx->pend, &ctx->plog_p, &ctx->plog_row, &ctx->plog_rs,
+                                &ctx->plog_rd, &ctx->ran, &ctx->plist, &ctx->pcnt, &ctx->povf};
+        for (const DevBuf* b : bufs) bufsig = bufsig * 1099511628211ull ^ (uint64_t)(uintptr_t)b->p;
+        const uint64_t key[5] = {P->serial, ctx->seed, ctx->first_shot, base, bufsig};
+        if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof(key)) != 0) {
+            if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+            if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+            ctx->gexec = nullptr;
+            ctx->graph = nullptr;
+            if (!ctx->cap_stream) HIP_CHECK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            HIP_CHECK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipStream_t run_stream = ctx->stream;
+            ctx->stream = ctx->cap_stream;          // the launches below are recorded, not run
+            const int erc = enqueue();
+            hipGraph_t gr = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &gr);
+            ctx->stream = run_stream;
+            if (erc || ec != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                ctx->poisoned = true;
+                return erc ? erc : fail(STAB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            }
+            ctx->graph = gr;
+            HIP_CHECK(ctx, hipGraphInstantiate(&ctx->gexec, gr, nullptr, nullptr, 0));
+            std::memcpy(ctx->gkey, key, sizeof(key));
+        }
+        HIP_CHECK(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+    } else if ((rc = enqueue())) {
+        return rc;
+    }
     std::vector<uint8_t> host;
     if (P->nrec > 0) {
         const long long total = nbytes * g.B;
-        const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
-        TIMED(ctx, 7, (k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p)));
         host.resize((size_t)total);
         HIP_CHECK(ctx, hipMemcpyAsync(host.data(), ctx->packed.p, (size_t)total, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -861,6 +919,13 @@ int stab_set_timing(stab_ctx* ctx, int32_t kernel_mask)
         ctx->kms[i] = 0.0;
         ctx->klaunch[i] = 0;
     }
+    return STAB_OK;
+}
+
+int stab_set_graph(stab_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(STAB_EINVAL, "null context");
+    ctx->graph_on = enable != 0;
     return STAB_OK;
 }
 

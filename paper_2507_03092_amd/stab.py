@@ -24,7 +24,7 @@ _MODES = {"shared": MODE_SHARED, "full": MODE_FULL, MODE_SHARED: MODE_SHARED, MO
 EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy", "stab_run",
            "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
            "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
-           "stab_get_counters", "stab_set_timing", "stab_get_kernel_times", "stab_plan_describe",
+           "stab_get_counters", "stab_set_timing", "stab_set_graph", "stab_get_kernel_times", "stab_plan_describe",
            "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
            "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
            "stab_batch_execute", "stab_batch_get_tableau", "stab_batch_get_counters",
@@ -73,6 +73,7 @@ def lib():
         "stab_sample": (C.c_int, [P, I32, P, I64, I32, I32, I32, U64, P, U64, P, P, C.POINTER(C.c_float)]),
         "stab_get_counters": (C.c_int, [P, P, I32]),
         "stab_set_timing": (C.c_int, [P, I32]),
+        "stab_set_graph": (C.c_int, [P, I32]),
         "stab_get_kernel_times": (C.c_int, [P, P, P, I32]),
         "stab_plan_describe": (C.c_int, [I32, I32, I32, P, I32, P, I64, P, I32]),
         "stab_batch_bytes": (C.c_int, [I32, P, C.POINTER(U64)]),
@@ -234,6 +235,10 @@ class Context:
         else:
             mask = sum(1 << KERNELS.index(k) for k in kernels)
         _check(lib().stab_set_timing(self.h, mask))
+
+    def set_graph(self, enable: bool) -> None:
+        """Replay a program's launches as a captured hipGraph while its key is unchanged."""
+        _check(lib().stab_set_graph(self.h, 1 if enable else 0))
 
     def kernel_times(self) -> dict:
         """{kernel name: (total ms, launches)} since set_timing(True)."""

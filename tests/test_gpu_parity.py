@@ -295,3 +295,33 @@ def test_replay_list_and_testing_forms(stab):
         else:
             assert c[10] == 0
         ctx.close()
+
+
+def test_graph_replay_matches_eager(stab):
+    """A compiled program replayed as a captured hipGraph: every replay, with eager work and
+    synchronizations between replays, equals the eager result (and the oracle's); another seed
+    captures anew and equals its own eager result."""
+    circ, _ = Cc.surface_code_memory(5, 4, 5e-3, Cc.IDLE_T1T2)
+    other = Cc.random_clifford_measure(circ.n, depth=6, seed=4, p_meas=0.3, noise=0.02)
+    shots = 16
+    ctx = stab.Context(circ.n, shots, mode="shared", seed=21)
+    prog, prog2 = ctx.compile(circ), ctx.compile(other)
+    ctx.reset(21)
+    eager = ctx.execute(prog)
+    ctx.reset(22)
+    eager22 = ctx.execute(prog)
+    assert np.array_equal(eager, O.run(circ, shots, 21))
+    ctx.set_graph(True)
+    for i in range(4):
+        ctx.reset(21)
+        say(f"graph replay {i}")
+        assert np.array_equal(ctx.execute(prog), eager), f"replay {i}"
+        ctx.set_graph(False)
+        ctx.reset(5)
+        ctx.execute(prog2)                      # eager work between replays
+        ctx.set_graph(True)
+    ctx.reset(22)
+    assert np.array_equal(ctx.execute(prog), eager22)
+    ctx.reset(21)
+    assert np.array_equal(ctx.execute(prog), eager)
+    ctx.close()
