@@ -87,6 +87,10 @@ def main() -> int:
     ap.add_argument("--plain-shots", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="auto",
+                    help="random_batch launch configuration: 'auto' (autotuner, first two measurement "
+                         "instructions of every circuit) or a configuration number")
+    ap.add_argument("--tune-quota", type=int, default=2, help="measurement instructions the autotuner times")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window of the serving workload (the full recipe is 60 s)")
     ap.add_argument("--serve-rate", type=float, default=None, help="arrival rate of the serving workload (1/s)")
@@ -312,6 +316,14 @@ def bench_batch(args) -> int:
     seed = w["seed"]
     b = stab.Batch(ns, seed=seed)
     prog = b.compile(circs)
+    tune_s = None
+    if args.tile == "auto":
+        a0 = time.perf_counter()
+        b.autotune(prog, meas_quota=args.tune_quota, force=True)
+        tune_s = time.perf_counter() - a0
+        log(f"autotuner: tile {prog.tile:#x} in {tune_s:.2f} s")
+    else:
+        prog.tile = int(args.tile, 0)
     for _ in range(warmup):
         b.reset(seed)
         b.execute(prog)
@@ -390,7 +402,9 @@ def bench_batch(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "random_batch", "circuits": int(w["ncirc"]), "n_range": [w["n_lo"], w["n_hi"]],
                    "layers": w["layers"], "measure_every": w["meas_every"], "measure_fraction": w["meas_frac"],
-                   "measurements": nmeas, "seed": seed, "form": "batched (one launch)"},
+                   "measurements": nmeas, "seed": seed, "form": "batched (one launch)",
+                   "tile": prog.tile, "tuned": tune_s is not None,
+                   "tune_seconds": None if tune_s is None else round(tune_s, 2)},
         "circuits_per_s": round(len(circs) / ((t1 - t0) / steps), 2),
         "plain": plain,
         "roofline": roofline,

@@ -251,6 +251,40 @@ void stab_batch_program_destroy(stab_batch_program *prog);
 int stab_batch_execute(stab_batch *batch, const stab_batch_program *prog, uint8_t *out_bits,
                        float *elapsed_ms);
 
+/* Launch configuration of a batch program: the row tile of its rowsum updates.  Bits 0-7:
+ * rows each lane group keeps in flight (2, 4 or 8); bit 8 (STAB_TILE_WHOLE_WAVE): every row
+ * takes a whole 64-lane wave, else a row takes the smallest power of two of lanes that holds
+ * its x words, so one wave updates several rows of a small circuit per load.  With two x
+ * words per lane (a circuit above 4096 qubits in the batch) 8 rows in flight run as 4.  0 =
+ * the default (8 rows in flight with one x word per lane, 2 with two; lanes sized to the row).
+ * The configuration changes speed only: every configuration writes the same records and
+ * leaves the same tableaux. */
+#define STAB_TILE_WHOLE_WAVE 0x100
+#define STAB_TUNE_FORCE 1
+
+/* Autotuner: time every launch configuration on this program from the batch's current
+ * state and keep the fastest in prog (used by later stab_batch_execute calls).  Each
+ * candidate runs the first meas_quota measurement instructions of every circuit (0: the
+ * whole program) from the same saved state; the records of all candidates must agree, and
+ * the batch's tableaux, instruction counters and work counters are restored afterwards, so
+ * tuning leaves no trace in what the batch computes.  A device copy of the batch
+ * (stab_batch_bytes) is allocated for the duration of the call.  The choice is cached per
+ * process under a fingerprint of the program's shape (circuit sizes, step, gate and measured
+ * target counts) and the device's compute-unit count; when the environment variable
+ * STAB_TUNE_CACHE names a file, choices are also read from and appended to it ("<key hex>
+ * <tile>" lines).  A cached choice is used without timing unless flags has STAB_TUNE_FORCE.
+ * tile_out (may be NULL) receives the configuration.  Errors: as stab_batch_execute;
+ * STAB_EINTERNAL also when two configurations disagree (the batch is then restored). */
+int stab_batch_autotune(stab_batch *batch, stab_batch_program *prog, int32_t meas_quota,
+                        int32_t flags, int32_t *tile_out);
+
+/* Set prog's launch configuration by hand (0 or a configuration as above).  Errors:
+ * STAB_EINVAL (NULL program, unknown configuration). */
+int stab_batch_program_set_tile(stab_batch_program *prog, int32_t tile);
+
+/* prog's launch configuration, or -1 for NULL. */
+int32_t stab_batch_program_tile(const stab_batch_program *prog);
+
 /* Circuit c's tableau in the stab_get_tableau layout (x[2n][n], z[2n][n], r[2n]). */
 int stab_batch_get_tableau(stab_batch *batch, int32_t circuit, uint8_t *x, uint8_t *z, uint8_t *r);
 

@@ -60,6 +60,7 @@ struct BatchArgs {
     const uint64_t* ibase;      // per circuit: instructions it executed before this launch
     const ulonglong2* keys;     // per circuit RNG key, or NULL for (seed, circuit index)
     int meas_quota;             // stop a circuit after this many measurement steps (0: run all)
+    int tile;                   // launch configuration (kTileWholeWave and rows in flight)
     uint64_t seed;
     int* err;
     unsigned long long* counters;
@@ -309,64 +310,78 @@ __device__ int batch_list(const uint64_t* bits, int w0, int w1, int skip0, int s
     return total;
 }
 
+// Launch configuration of the batch kernel (BatchArgs::tile): bits 0-7 rows each lane group
+// keeps in flight in a rowsum (2, 4 or 8, at most 4 with two x words per lane; 0 = 8 for one
+// x word per lane, 2 for two); bit 8
+// set: every row takes the whole wave (64 lanes per row), clear: a row takes the smallest
+// power of two of lanes that covers its x words, so a wave updates 64 / lanes rows per load.
+constexpr int kTileWholeWave = 1 << 8;
+
 // rowsum(row, p) for every listed row: x|z ^= pivot, sign from the g-sum (Appendix A.2).
-// Each wave takes kBatchRows rows at a time so their loads are in flight together; lane l
-// owns x words l, l + 64, ... (NW of them) and the matching z words.
-template <int NW>
-__device__ void batch_rowsum(const BatchCirc& C, uint64_t* __restrict__ tab, const uint64_t* prow,
-                             int rp, const uint16_t* list, int nlist, uint64_t* sg, int* err)
+// A row is owned by a group of lpr lanes (lane sub of the group holds x words sub,
+// sub + lpr, ..., NW of them, and the matching z words); a wave holds 64 / lpr groups and
+// each group keeps R rows in flight so their loads overlap.  The g-sums are reduced within
+// the group, eight bits per row, four rows per int.
+template <int NW, int R>
+__device__ void batch_rowsum_tile(const BatchCirc& C, uint64_t* __restrict__ tab, const uint64_t* prow,
+                                  int rp, const uint16_t* list, int nlist, uint64_t* sg, int* err, int lpr)
 {
+    static_assert(R <= 8, "two packed ints hold eight rows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Wc = C.Wc, RS = C.RS;
+    const int sub = lane & (lpr - 1), grp = lane / lpr, groups = 64 / lpr;
     uint64_t px[NW], pz[NW];
 #pragma unroll
     for (int t = 0; t < NW; ++t) {
-        const int j = lane + 64 * t;
+        const int j = sub + lpr * t;
         px[t] = (j < Wc) ? prow[j] : 0;
         pz[t] = (j < Wc) ? prow[Wc + j] : 0;
     }
-    constexpr int kBatchRows = (NW == 1) ? 4 : 2;   // rows in flight per wave (register budget)
-    for (int base = wave * kBatchRows; base < nlist; base += kBatchWaves * kBatchRows) {
-        const int cnt = min(kBatchRows, nlist - base);
-        uint64_t x[kBatchRows][NW], z[kBatchRows][NW];
-        int row[kBatchRows];
+    const int step = R * groups;
+    for (int base = wave * step; base < nlist; base += kBatchWaves * step) {
+        uint64_t x[R][NW], z[R][NW];
+        int row[R];
+        bool ok[R];
 #pragma unroll
-        for (int r = 0; r < kBatchRows; ++r) {
-            row[r] = (r < cnt) ? (int)list[base + r] : 0;
+        for (int r = 0; r < R; ++r) {
+            const int li = base + r * groups + grp;
+            ok[r] = li < nlist;
+            row[r] = ok[r] ? (int)list[li] : 0;
 #pragma unroll
             for (int t = 0; t < NW; ++t) {
-                const int j = lane + 64 * t;
+                const int j = sub + lpr * t;
                 x[r][t] = z[r][t] = 0;
-                if (r < cnt && j < Wc) {
+                if (ok[r] && j < Wc) {
                     x[r][t] = tab[(size_t)row[r] * RS + j];
                     z[r][t] = tab[(size_t)row[r] * RS + Wc + j];
                 }
             }
         }
-        // g-sums mod 4, eight bits per row, four rows per int
         int pk[2] = {0, 0};
-        static_assert(kBatchRows <= 8, "two packed ints hold eight rows");
 #pragma unroll
-        for (int r = 0; r < kBatchRows; ++r) {
+        for (int r = 0; r < R; ++r) {
             int G = 0;
 #pragma unroll
             for (int t = 0; t < NW; ++t) G += gsum(px[t], pz[t], x[r][t], z[r][t]);
             pk[r >> 2] += (G & 3) << (8 * (r & 3));
         }
-        pk[0] = wave_sum(pk[0]);
-        pk[1] = wave_sum(pk[1]);
+        // at most 64 lanes add at most 3 each: the 8-bit fields do not carry
+        for (int m = lpr >> 1; m >= 1; m >>= 1) {
+            pk[0] += __shfl_xor(pk[0], m, 64);
+            if (R > 4) pk[1] += __shfl_xor(pk[1], m, 64);
+        }
 #pragma unroll
-        for (int r = 0; r < kBatchRows; ++r) {
-            if (r < cnt) {
+        for (int r = 0; r < R; ++r) {
+            if (ok[r]) {
 #pragma unroll
                 for (int t = 0; t < NW; ++t) {
-                    const int j = lane + 64 * t;
+                    const int j = sub + lpr * t;
                     if (j < Wc) {
                         tab[(size_t)row[r] * RS + j] = x[r][t] ^ px[t];
                         tab[(size_t)row[r] * RS + Wc + j] = z[r][t] ^ pz[t];
                     }
                 }
-                if (lane == 0) {
+                if (sub == 0) {
                     const int G = (pk[r >> 2] >> (8 * (r & 3))) & 3;
                     const int ri = (int)((sg[row[r] >> 6] >> (row[r] & 63)) & 1ull);
                     const int e = (2 * ri + 2 * rp + G) & 3;
@@ -376,6 +391,20 @@ __device__ void batch_rowsum(const BatchCirc& C, uint64_t* __restrict__ tab, con
             }
         }
     }
+}
+
+template <int NW>
+__device__ void batch_rowsum(const BatchCirc& C, uint64_t* __restrict__ tab, const uint64_t* prow, int rp,
+                             const uint16_t* list, int nlist, uint64_t* sg, int* err, int tile)
+{
+    int lpr = 64;
+    if (!(tile & kTileWholeWave))
+        while (lpr > 1 && (lpr >> 1) >= C.Wc) lpr >>= 1;
+    const int R = tile & 0xff;
+    // two x words per lane: at most 4 rows in flight (register budget)
+    if ((R == 8 || R == 0) && NW == 1) batch_rowsum_tile<NW, 8>(C, tab, prow, rp, list, nlist, sg, err, lpr);
+    else if (R == 2 || (R == 0 && NW == 2)) batch_rowsum_tile<NW, 2>(C, tab, prow, rp, list, nlist, sg, err, lpr);
+    else batch_rowsum_tile<NW, 4>(C, tab, prow, rp, list, nlist, sg, err, lpr);
 }
 
 // Sign of the product of the listed stabilizer rows (destabilizer indices i -> row NR + i):
@@ -527,7 +556,7 @@ __device__ int batch_measure_one(const BatchArgs& A, const BatchCirc& C, int a, 
         const int rp = (int)((L.sg[p >> 6] >> (p & 63)) & 1ull);
         const int nl = batch_list(L.colx, 0, NB, p, p - NR, L.list, L.s_int + 1);
         __syncthreads();    // prow staged
-        batch_rowsum<NW>(C, tab, L.prow, rp, L.list, nl, L.sg, A.err);
+        batch_rowsum<NW>(C, tab, L.prow, rp, L.list, nl, L.sg, A.err, A.tile);
         __syncthreads();
         // destabilizer p - NR <- old stabilizer p; stabilizer p <- (-1)^outcome Z_a
         const int d = p - NR;

@@ -18,6 +18,7 @@ struct stab_batch {
     uint64_t* d_ibase = nullptr;      // per-circuit instruction counters (device copy)
     std::vector<uint64_t> icount;     // instructions each circuit has executed
     double kernel_ms = 0.0;           // batch kernel time of the last execution
+    size_t bytes = 0;                 // tableaux and signs in dev_buf
 };
 
 struct stab_batch_program {
@@ -28,6 +29,8 @@ struct stab_batch_program {
     std::vector<long long> rec_byte;  // first output byte per circuit (ncirc + 1 entries)
     int lds_bytes = 0;
     int nw = 1;                       // x words per lane (kernel variant)
+    int tile = 0;                     // launch configuration (BatchArgs::tile)
+    uint64_t shape = 0;               // fingerprint of the program's shape (autotuner cache key)
     void* dev = nullptr;
     uint64_t* cols = nullptr;         // column scratch of every circuit
     BatchCirc* d_circ = nullptr;
@@ -236,6 +239,7 @@ int stab_batch_create(int32_t ncirc, const int32_t* n, uint64_t seed, void* dev_
     b->tab = (uint64_t*)dev_buf;
     b->rs = (uint64_t*)dev_buf;
     b->max_lds = lds;
+    b->bytes = L.bytes;
     b->circ.resize(ncirc);
     b->icount.assign(ncirc, 0ull);
     for (int c = 0; c < ncirc; ++c) {
@@ -360,6 +364,26 @@ int stab_batch_compile(stab_batch* b, const stab_instr* instrs, const int64_t* i
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     P->lds_bytes = batch_lds_words(maxwc) * 8;
     P->nw = maxwc <= 64 ? 1 : 2;
+    // shape fingerprint: sizes and per-circuit step, gate and measured-target counts
+    {
+        uint64_t h = 0x9E3779B97F4A7C15ull ^ (uint64_t)C;
+        auto mix = [&](uint64_t v) {
+            h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+            h *= 0xff51afd7ed558ccdull;
+        };
+        for (int c = 0; c < C; ++c) {
+            long long ng = 0, mt = 0;
+            for (int st = circ[c].step_begin; st < circ[c].step_begin + circ[c].step_count; ++st) {
+                if (steps[st].x == 0) ng += steps[st].z;
+                else if (steps[st].x == 2) mt += meas[steps[st].y].K;
+            }
+            mix((uint64_t)circ[c].n);
+            mix((uint64_t)circ[c].step_count);
+            mix((uint64_t)ng);
+            mix((uint64_t)mt);
+        }
+        P->shape = h;
+    }
 
     std::vector<char> blob;
     const size_t o_circ = put(blob, circ), o_order = put(blob, order), o_steps = put(blob, steps),
@@ -408,14 +432,12 @@ void stab_batch_program_destroy(stab_batch_program* P)
     delete P;
 }
 
-int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_bits, float* elapsed_ms)
+namespace {
+
+// Zero the record, upload the instruction counters and launch the batch kernel between the
+// batch's two events, with launch configuration tile and measurement quota (0: whole program).
+int batch_launch(stab_batch* b, const stab_batch_program* P, int tile, int quota)
 {
-    if (!b || !P) return fail(STAB_EINVAL, "NULL argument");
-    if (b->poisoned) return fail(STAB_EDEVICE, "batch poisoned by an earlier device error");
-    if (P->ncirc != b->ncirc) return fail(STAB_EINVAL, "program compiled for another batch");
-    for (int c = 0; c < b->ncirc; ++c)
-        if (P->n[c] != b->circ[c].n) return fail(STAB_EINVAL, "program compiled for other circuit sizes");
-    if (P->lds_bytes > b->max_lds) return fail(STAB_ERANGE, "program needs more LDS than the device has");
     const long long bytes = P->rec_byte[b->ncirc];
     const long long words = (bytes + 3) / 4;
     if (ensure(b->rec, (size_t)std::max<long long>(words, 1) * 4)) return STAB_ENOMEM;
@@ -441,7 +463,8 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
     A.rec = (uint32_t*)b->rec.p;
     A.ibase = b->d_ibase;
     A.keys = nullptr;
-    A.meas_quota = 0;
+    A.meas_quota = quota;
+    A.tile = tile;
     A.cols = P->cols;
     A.seed = b->seed;
     A.err = b->d_err;
@@ -450,6 +473,22 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
     else k_batch<2><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
     BHIP_CHECK(b, hipGetLastError());
     BHIP_CHECK(b, hipEventRecord(b->ev1, b->stream));
+    return STAB_OK;
+}
+
+}  // namespace
+
+int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_bits, float* elapsed_ms)
+{
+    if (!b || !P) return fail(STAB_EINVAL, "NULL argument");
+    if (b->poisoned) return fail(STAB_EDEVICE, "batch poisoned by an earlier device error");
+    if (P->ncirc != b->ncirc) return fail(STAB_EINVAL, "program compiled for another batch");
+    for (int c = 0; c < b->ncirc; ++c)
+        if (P->n[c] != b->circ[c].n) return fail(STAB_EINVAL, "program compiled for other circuit sizes");
+    if (P->lds_bytes > b->max_lds) return fail(STAB_ERANGE, "program needs more LDS than the device has");
+    const long long bytes = P->rec_byte[b->ncirc];
+    const int lrc = batch_launch(b, P, P->tile, 0);
+    if (lrc) return lrc;
     if (out_bits && bytes > 0)
         BHIP_CHECK(b, hipMemcpyAsync(out_bits, b->rec.p, (size_t)bytes, hipMemcpyDeviceToHost, b->stream));
     int err = 0;
@@ -466,6 +505,169 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
                                     "product that is not +-Z)");
     }
     return STAB_OK;
+}
+
+static_assert(kTileWholeWave == STAB_TILE_WHOLE_WAVE, "tile flag of include/stab.h");
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<uint64_t, int> g_tune;   // (program shape, device) -> launch configuration
+
+bool tile_valid(int tile)
+{
+    const int R = tile & 0xff;
+    return (tile & ~(0xff | kTileWholeWave)) == 0 && (R == 2 || R == 4 || R == 8);
+}
+
+bool tune_file_lookup(uint64_t key, int* tile)
+{
+    const char* path = std::getenv("STAB_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    unsigned long long k = 0;
+    int t = 0;
+    bool found = false;
+    while (std::fscanf(f, "%llx %d", &k, &t) == 2)
+        if (k == key && tile_valid(t)) {
+            *tile = t;   // the last entry for a key wins
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void tune_file_store(uint64_t key, int tile)
+{
+    const char* path = std::getenv("STAB_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%016llx %d\n", (unsigned long long)key, tile);
+    std::fclose(f);
+}
+
+}  // namespace
+
+int stab_batch_autotune(stab_batch* b, stab_batch_program* P, int32_t meas_quota, int32_t flags, int32_t* tile_out)
+{
+    if (!b || !P) return fail(STAB_EINVAL, "NULL argument");
+    if (b->poisoned) return fail(STAB_EDEVICE, "batch poisoned by an earlier device error");
+    if (meas_quota < 0) return fail(STAB_EINVAL, "meas_quota < 0");
+    if (flags & ~STAB_TUNE_FORCE) return fail(STAB_EINVAL, "unknown flags");
+    if (P->ncirc != b->ncirc) return fail(STAB_EINVAL, "program compiled for another batch");
+    for (int c = 0; c < b->ncirc; ++c)
+        if (P->n[c] != b->circ[c].n) return fail(STAB_EINVAL, "program compiled for other circuit sizes");
+    if (P->lds_bytes > b->max_lds) return fail(STAB_ERANGE, "program needs more LDS than the device has");
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(STAB_EDEVICE, "no HIP device");
+    const uint64_t key = P->shape ^ ((uint64_t)(P->nw * 4096 + cus) << 40);
+    if (!(flags & STAB_TUNE_FORCE)) {
+        int t = 0;
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                t = it->second;
+                hit = true;
+            }
+        }
+        if (!hit && tune_file_lookup(key, &t)) {
+            hit = true;
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            g_tune[key] = t;
+        }
+        if (hit) {
+            P->tile = t;
+            if (tile_out) *tile_out = t;
+            return STAB_OK;
+        }
+    }
+    // candidates: lanes per row sized to the circuit or the whole wave, 2, 4 or 8 rows in flight
+    std::vector<int> cand;
+    for (int wide = 0; wide < 2; ++wide)
+        for (int R : {2, 4, 8}) cand.push_back(R | (wide ? kTileWholeWave : 0));
+    const long long bytes = P->rec_byte[b->ncirc];
+    void* save = nullptr;
+    if (hipMalloc(&save, b->bytes) != hipSuccess) return fail(STAB_ENOMEM, "device allocation failed");
+    std::vector<unsigned long long> ctr(kNumCounters * kCounterStripes);
+    std::vector<uint8_t> ref((size_t)bytes), got((size_t)bytes);
+    auto done = [&](int rc) {
+        // the batch's state as it was before tuning
+        if (hipMemcpyAsync(b->tab, save, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+            hipMemcpyAsync(b->d_counters, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess) {
+            b->poisoned = true;
+            if (rc == STAB_OK) rc = fail(STAB_EDEVICE, "restoring the batch after tuning failed");
+        }
+        (void)hipFree(save);
+        return rc;
+    };
+    if (hipMemcpyAsync(save, b->tab, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(ctr.data(), b->d_counters, ctr.size() * 8, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        (void)hipFree(save);
+        b->poisoned = true;
+        return fail(STAB_EDEVICE, "saving the batch before tuning failed");
+    }
+    int best = -1;
+    float best_ms = 0.f;
+    // the first launch warms up and is not timed
+    for (int i = -1; i < (int)cand.size(); ++i) {
+        const int tile = cand[i < 0 ? 0 : i];
+        if (i >= 0 && hipMemcpyAsync(b->tab, save, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+            return done(fail(STAB_EDEVICE, "restoring the batch between candidates failed"));
+        int rc = batch_launch(b, P, tile, meas_quota);
+        if (rc) return done(rc);
+        int err = 0;
+        if ((bytes > 0 && hipMemcpyAsync(got.data(), b->rec.p, (size_t)bytes, hipMemcpyDeviceToHost, b->stream) !=
+                              hipSuccess) ||
+            hipMemcpyAsync(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess)
+            return done(fail(STAB_EDEVICE, "candidate launch failed"));
+        if (err) {
+            b->poisoned = true;
+            return done(fail(STAB_EINTERNAL, "device consistency check failed while tuning"));
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) return done(fail(STAB_EDEVICE, "event timing failed"));
+        if (i < 0) {
+            ref = got;
+            continue;
+        }
+        if (got != ref) return done(fail(STAB_EINTERNAL, "launch configurations gave different records"));
+        if (best < 0 || ms < best_ms) {
+            best = tile;
+            best_ms = ms;
+        }
+    }
+    const int rc = done(STAB_OK);
+    if (rc) return rc;
+    P->tile = best;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = best;
+    }
+    tune_file_store(key, best);
+    if (tile_out) *tile_out = best;
+    return STAB_OK;
+}
+
+int stab_batch_program_set_tile(stab_batch_program* P, int32_t tile)
+{
+    if (!P) return fail(STAB_EINVAL, "program is NULL");
+    if (tile != 0 && !tile_valid(tile)) return fail(STAB_EINVAL, "unknown launch configuration");
+    P->tile = tile;
+    return STAB_OK;
+}
+
+int32_t stab_batch_program_tile(const stab_batch_program* P)
+{
+    return P ? P->tile : -1;
 }
 
 int stab_batch_get_tableau(stab_batch* b, int32_t circuit, uint8_t* x, uint8_t* z, uint8_t* r)

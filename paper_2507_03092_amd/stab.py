@@ -27,13 +27,16 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_get_counters", "stab_set_timing", "stab_set_graph", "stab_get_kernel_times", "stab_plan_describe",
            "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
            "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
-           "stab_batch_execute", "stab_batch_get_tableau", "stab_batch_get_counters",
+           "stab_batch_execute", "stab_batch_autotune", "stab_batch_program_set_tile", "stab_batch_program_tile",
+           "stab_batch_get_tableau", "stab_batch_get_counters",
            "stab_commute", "stab_server_request_bytes", "stab_server_create", "stab_server_destroy",
            "stab_server_program", "stab_server_program_records", "stab_server_submit", "stab_server_step",
            "stab_server_poll", "stab_server_records", "stab_server_result", "stab_server_stats",
            "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
+TILE_WHOLE_WAVE = 0x100   # STAB_TILE_WHOLE_WAVE
+TUNE_FORCE = 1            # STAB_TUNE_FORCE
 KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack", "replay",
            "extract")
 
@@ -84,6 +87,9 @@ def lib():
         "stab_batch_program_records": (I64, [P, I32]),
         "stab_batch_program_destroy": (None, [P]),
         "stab_batch_execute": (C.c_int, [P, P, P, C.POINTER(C.c_float)]),
+        "stab_batch_autotune": (C.c_int, [P, P, I32, I32, C.POINTER(I32)]),
+        "stab_batch_program_set_tile": (C.c_int, [P, I32]),
+        "stab_batch_program_tile": (I32, [P]),
         "stab_batch_get_tableau": (C.c_int, [P, I32, P, P, P]),
         "stab_batch_get_counters": (C.c_int, [P, P, I32]),
         "stab_commute": (C.c_int, [P, I32, P, I32, I32, P, P, P]),
@@ -283,6 +289,15 @@ class BatchProgram:
         self.batch, self.h, self.nrec = batch, handle, nrec
         self.rec_byte = np.concatenate([[0], np.cumsum((np.asarray(nrec, dtype=np.int64) + 7) // 8)])
 
+    @property
+    def tile(self) -> int:
+        """Launch configuration (stab_batch_program_tile)."""
+        return int(lib().stab_batch_program_tile(self.h))
+
+    @tile.setter
+    def tile(self, value: int) -> None:
+        _check(lib().stab_batch_program_set_tile(self.h, int(value)))
+
     def __del__(self):
         try:
             if getattr(self, "h", None) and _lib is not None:
@@ -346,6 +361,13 @@ class Batch:
         recs = [np.unpackbits(out[prog.rec_byte[c]:prog.rec_byte[c + 1]], bitorder="little")[: prog.nrec[c]]
                 for c in range(len(prog.nrec))]
         return (recs, ms.value) if timed else recs
+
+    def autotune(self, prog: BatchProgram, meas_quota: int = 0, force: bool = False) -> int:
+        """Time every launch configuration on prog from the current state and keep the fastest
+        (stab_batch_autotune); the batch's state is left as it was.  Returns the choice."""
+        t = C.c_int32(0)
+        _check(lib().stab_batch_autotune(self.h, prog.h, int(meas_quota), TUNE_FORCE if force else 0, C.byref(t)))
+        return t.value
 
     def reset(self, seed: int) -> None:
         _check(lib().stab_batch_reset(self.h, seed))

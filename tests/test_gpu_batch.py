@@ -130,6 +130,83 @@ def test_batch_reset_and_reexecution(stab):
     b.close()
 
 
+
+TILES = [0] + [r | w for w in (0, 0x100) for r in (2, 4, 8)]
+
+
+def test_batch_every_launch_configuration(stab):
+    """Each rowsum row tile (lanes sized to the row or the whole wave; 2, 4 or 8 rows in
+    flight) writes the oracle's records and tableaux, on sizes that give every lane-group
+    width from 1 to 64 lanes and ragged lists."""
+    sizes = [1, 3, 64, 65, 130, 200, 257, 520, 1030]
+    circs = [Cc.random_layered_clifford(n, 24, (5 + n % 3, 1), meas_every=4, meas_frac=0.3) for n in sizes]
+    circs[1] = Cc.random_clifford_measure(3, depth=12, seed=9, p_meas=0.4, noise=0.05)
+    # 33 words: a whole wave per row
+    circs.append(Cc.random_layered_clifford(2100, 12, (5, 2), meas_every=6, meas_frac=0.05))
+    seed = 17
+    ns = np.array([c.n for c in circs], dtype=np.int32)
+    want = _oracle_all(circs, seed, range(len(circs)), True)
+    b = stab.Batch(ns, seed=seed)
+    prog = b.compile(circs)
+    for tile in TILES:
+        say(f"tile {tile:#x}")
+        b.reset(seed)
+        prog.tile = tile
+        assert prog.tile == tile
+        got = b.execute(prog)
+        for c in range(len(circs)):
+            (w, (tx, tz, tr)) = want[c]
+            assert np.array_equal(got[c], w[0]), f"tile {tile:#x}, circuit {c} (n={ns[c]}): record differs"
+            x, z, r = b.get_tableau(c)
+            assert np.array_equal(x, tx[0]) and np.array_equal(z, tz[0]) and np.array_equal(r, tr[0]), \
+                f"tile {tile:#x}, circuit {c}: tableau differs"
+    with pytest.raises(stab.StabError):
+        prog.tile = 3
+    b.close()
+
+
+def test_batch_launch_configurations_two_words(stab):
+    circs = [Cc.random_layered_clifford(4200, 12, (7, 0), meas_every=6, meas_frac=0.05),
+             Cc.random_layered_clifford(90, 20, (7, 1), meas_every=4, meas_frac=0.3)]
+    seed = 6
+    ns = np.array([c.n for c in circs], dtype=np.int32)
+    want = _oracle_all(circs, seed, range(2), False)
+    b = stab.Batch(ns, seed=seed)
+    prog = b.compile(circs)
+    for tile in (2, 8, 0x102, 0x108):
+        say(f"tile {tile:#x}")
+        b.reset(seed)
+        prog.tile = tile
+        got = b.execute(prog)
+        for c in range(2):
+            assert np.array_equal(got[c], want[c][0]), f"tile {tile:#x}, circuit {c}: record differs"
+    b.close()
+
+
+def test_batch_autotune_leaves_no_trace(stab):
+    """Tuning restores the batch: the run after it equals the oracle and an untuned batch's
+    counters; a second call takes the cached choice."""
+    ns, circs = Cc.random_batch(24, 40, 900, layers=30, seed=31, meas_every=5, meas_frac=0.2)
+    seed = 31
+    ref = stab.Batch(ns, seed=seed)
+    pref = ref.compile(circs)
+    want = ref.execute(pref)
+    for c in (0, 7, 23):
+        assert np.array_equal(want[c], O.run(circs[c], 1, seed, c)[0]), f"circuit {c}"
+    b = stab.Batch(ns, seed=seed)
+    prog = b.compile(circs)
+    tile = b.autotune(prog, meas_quota=2, force=True)
+    say(f"chosen tile {tile:#x}")
+    assert tile in TILES[1:] and prog.tile == tile
+    got = b.execute(prog)
+    assert all(np.array_equal(x, y) for x, y in zip(got, want))
+    assert np.array_equal(b.counters(), ref.counters())
+    prog2 = b.compile(circs)
+    assert b.autotune(prog2) == tile and prog2.tile == tile
+    b.close()
+    ref.close()
+
+
 def test_batch_random_workload_full_size_sampled(stab):
     """The 4096-circuit workload at full size, in the launch the benchmark times; the oracle
     checks the records of a sample of circuits (the smallest ones and a few random ones of
