@@ -63,15 +63,18 @@ def seg_bytes_per_launch(n: int, shots: int, mode: str, K: int, write_back: bool
     return copies * nb * (band * (2 if write_back else 1) + 2 * K * 8)
 
 
-def load_pmc(workload: str, mode: str) -> dict:
+def load_pmc(workload: str, mode: str, tile=None) -> dict:
     """HBM bytes per launch of each kernel from the committed rocprofv3 counter summary of this
     workload (FETCH_SIZE and WRITE_SIZE, scaled by what they read for a plain copy of known
-    size), if it was taken from the current kernel sources; else {}."""
+    size), if it was taken from the current kernel sources (and, for the batch, the same launch
+    configuration); else {}."""
     path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
     if not os.path.exists(path):
         return {}
     p = json.load(open(path))
     if p.get("source_digest") != kernel_source_digest() or p.get("mode") != mode:
+        return {}
+    if tile is not None and p.get("tile") != tile:
         return {}
     fs, ws = p["fetch_scale"], p["write_scale"]
     return {k: (v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024.0 for k, v in p["kernels"].items()}
@@ -345,8 +348,10 @@ def bench_batch(args) -> int:
     bytes_launch = float(dc[6] + dc[7])
     k_avg_ms = kms / steps
     achieved = bytes_launch / (k_avg_ms / 1000.0) / 1e9
+    traffic = load_pmc("random_batch", "batch", prog.tile).get("batch")
     roofline = {"kernel": "batch", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": int(traffic) if traffic is not None else None,
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(k_avg_ms * 1000.0, 1),
                 "random_measurements": int(dc[4]), "deterministic_measurements": int(dc[2]),
                 "rowsum_rows": int(dc[5])}
@@ -547,8 +552,10 @@ def bench_exact_noise(args) -> int:
     bytes_launch = float(dc[6] + dc[7])
     achieved = bytes_launch / (k_ms / 1000.0) / 1e9
     log(f"{args.workload}: {ms_step:.2f} ms/step, {shots * rounds / (ms_step / 1000.0):.1f} rounds/s")
+    traffic = load_pmc("random_batch", "batch", prog.tile).get("batch")
     roofline = {"kernel": "batch", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": int(traffic) if traffic is not None else None,
                 "bytes_per_launch": int(bytes_launch), "avg_launch_us": round(k_ms * 1000.0, 1),
                 "random_measurements": int(dc[4]), "deterministic_measurements": int(dc[2])}
     cpu = None
