@@ -133,6 +133,7 @@ struct SegPlan {
     int units = 0;
     int max_units = 0;     // largest noise instruction of the segment (units)
     long long ev_cap = 0;
+    long long ev_global = 0;   // first event slot of the segment when the whole program is drawn at once
     int meas = -1;
     long long gate_count = 0;
 };
@@ -153,6 +154,8 @@ struct stab_program {
     long long nrec = 0;
     int Kmax = 0;
     long long ev_cap_max = 0;
+    long long ev_total = 0;    // event slots of all segments
+    int max_units = 0;         // largest noise instruction of the program (units)
     int nnoise = 0;
     std::vector<SegPlan> segs;
     std::vector<MeasPlan> meas;
@@ -166,6 +169,7 @@ struct stab_program {
     int* d_unit_start = nullptr;
     int* d_ev_base = nullptr;
     int* d_ev_count = nullptr;
+    long long* d_noise_seg = nullptr;   // per noise instruction: its segment's first event slot
     int* d_mtq = nullptr;
     // geometry it was compiled for
     int n = 0, B = 0;
@@ -297,6 +301,9 @@ int compile_stream(const Geom& g, const stab_instr* ins, int ninstr, const int32
         seg.meas = meas_index;
         P.steps.push_back({0, (int)P.segs.size()});
         P.ev_cap_max = std::max(P.ev_cap_max, seg.ev_cap);
+        seg.ev_global = P.ev_total;
+        P.ev_total += seg.ev_cap;
+        P.max_units = std::max(P.max_units, seg.max_units);
         P.segs.push_back(seg);
         seg = SegPlan();
         seg.item_begin = (int)items.size();
@@ -575,6 +582,10 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     const size_t o_items = put(blob, items), o_gates = put(blob, gates), o_noise = put(blob, noise);
     const size_t o_ntg = put(blob, noise_tg), o_us = put(blob, unit_start), o_eb = put(blob, ev_base);
     const size_t o_ec = put(blob, std::vector<int>(std::max<int>(P->nnoise, 1), 0));
+    std::vector<long long> nseg(std::max<size_t>(noise.size(), 1), 0);
+    for (const SegPlan& sp : P->segs)
+        for (int i = 0; i < sp.noise_count; ++i) nseg[sp.noise_begin + i] = sp.ev_global;
+    const size_t o_nseg = put(blob, nseg);
     const size_t o_mtq = put(blob, mtq);
     if (hipMalloc(&P->dev, blob.size()) != hipSuccess) {
         delete P;
@@ -594,6 +605,7 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     P->d_unit_start = (int*)(d + o_us);
     P->d_ev_base = (int*)(d + o_eb);
     P->d_ev_count = (int*)(d + o_ec);
+    P->d_noise_seg = (long long*)(d + o_nseg);
     P->d_mtq = (int*)(d + o_mtq);
     *out = P;
     return STAB_OK;
@@ -640,11 +652,14 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     if (P->n != g.n || P->B != g.B) return fail(STAB_EINVAL, "program compiled for another geometry");
     if (P->nrec > 0 && !out_bits) return fail(STAB_EINVAL, "out_bits is NULL but the stream records outcomes");
     const size_t K = (size_t)std::max(P->Kmax, 1);
+    // the noise of every segment is drawn by one launch at the start when its event slots fit
+    // (the draws depend on the RNG key only, not on the tableau); else segment by segment
+    const bool draw_all = P->nnoise > 0 && P->nnoise <= 65535 && P->ev_total <= kDrawAllEvents;
     int rc;
     if ((rc = ensure(ctx->xcol, (size_t)g.S * g.NB * K * 8)) || (rc = ensure(ctx->zcol, (size_t)g.S * g.NB * K * 8)) ||
         (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->pend, (size_t)g.S * K * 4)) ||
         (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
-        (rc = ensure(ctx->events, (size_t)std::max<long long>(P->ev_cap_max, 1) * 8)) ||
+        (rc = ensure(ctx->events, (size_t)std::max<long long>(draw_all ? P->ev_total : P->ev_cap_max, 1) * 8)) ||
         (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
         (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))) ||
         (rc = ensure(ctx->plog_p, (size_t)g.S * K * 4)) || (rc = ensure(ctx->plog_rs, (size_t)g.S * K * 4)) ||
@@ -692,23 +707,30 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     auto enqueue = [&]() -> int {
         if (P->nnoise > 0)
             k_zero32<<<1, 256, 0, ctx->stream>>>((uint32_t*)P->d_ev_count, (long long)P->nnoise);
+        if (draw_all) {
+            const long long most = (long long)P->max_units * g.B;
+            const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock), (unsigned)P->nnoise);
+            TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
+                P->d_noise, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events, P->d_noise_seg,
+                P->d_ev_base, P->d_ev_count, ctx->d_counters)));
+        }
         for (const auto& st : P->steps) {
             if (st.first == 0) {
                 const SegPlan& sp = P->segs[st.second];
-                if (sp.noise_count > 0) {
+                if (sp.noise_count > 0 && !draw_all) {
                     const long long most = (long long)sp.max_units * g.B;
                     const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
                                     (unsigned)sp.noise_count);
                     TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
                         P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                        P->d_ev_base, P->d_ev_count, ctx->d_counters)));
+                        nullptr, P->d_ev_base, P->d_ev_count, ctx->d_counters)));
                 }
                 if (sp.item_count > 0 || sp.meas >= 0) {
                     SegArgs a{};
                     a.items = P->d_items + sp.item_begin;
                     a.nitems = sp.item_count;
                     a.gates = P->d_gates;
-                    a.events = events;
+                    a.events = events + (draw_all ? sp.ev_global : 0);
                     a.ev_count = P->d_ev_count;
                     a.ev_base = P->d_ev_base;
                     a.write_back = sp.modifies;

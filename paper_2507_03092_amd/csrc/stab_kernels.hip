@@ -190,19 +190,24 @@ __global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------
-// Noise draws for one segment: block (x, y) handles kNoiseUnitsPerBlock consecutive (shot,
-// unit) pairs of noise layer y.  Draws never depend on the tableau, so they are made up front
-// and the segment kernel applies them at their layer.  Event = (tile word index of the qubit
+// Noise draws: block (x, y) handles kNoiseUnitsPerBlock consecutive (shot, unit) pairs of noise
+// instruction y.  Draws never depend on the tableau, so they are made up front (the whole
+// program's in one launch when its event slots fit, else a segment's before it) and the
+// segment kernel applies them at their layer.  Event = (tile word index of the qubit
 // | pauli << 28, shot).  A block gathers its events in LDS and reserves space with one atomic.
 // ------------------------------------------------------------------------------------------
 constexpr int kNoiseThreads = 1024;
 constexpr int kNoiseUnitsPerBlock = 4 * kNoiseThreads;
 constexpr int kNoiseLdsEvents = 2048;
+// event slots (8 bytes each) up to which a program's noise is drawn in one launch
+constexpr long long kDrawAllEvents = 1ll << 28;
 
+// Instruction blockIdx.y of nd[].  seg_base (may be NULL): per instruction, the first event
+// slot of its segment, when every segment's events are drawn by one launch.
 __global__ void __launch_bounds__(1024)
 k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int B, uint64_t seed,
              uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
-             const int* __restrict__ ev_base, int* __restrict__ ev_count,
+             const long long* __restrict__ seg_base, const int* __restrict__ ev_base, int* __restrict__ ev_count,
              unsigned long long* __restrict__ counters)
 {
     __shared__ uint2 sev[kNoiseLdsEvents];
@@ -213,7 +218,7 @@ k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int 
     if (start >= total) return;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    uint2* gdst = events + ev_base[d.bucket];
+    uint2* gdst = events + (seg_base ? seg_base[blockIdx.y] : 0ll) + ev_base[d.bucket];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const long long idx = start + threadIdx.x + (long long)j * kNoiseThreads;
