@@ -188,14 +188,12 @@ int stab_get_counters(stab_ctx *ctx, uint64_t *counters, int32_t ncounters);
 #define STAB_NUM_KERNELS 10
 int stab_set_timing(stab_ctx *ctx, int32_t kernel_mask);
 
-/* Graph replay of stab_execute.  With enable != 0, stab_execute captures the device work of
- * a program (every kernel launch up to the record packing) into a hipGraph the first time it
- * runs it, and replays the graph while the program, the RNG seed and first shot, the
- * instruction counter, the context's buffers and the stab_set_timing mask are the same as at
- * capture (a program executed right after stab_reset, again and again, replays); any other
- * execution captures anew.  Kernels selected by stab_set_timing are bracketed by event-record
- * nodes of the graph, so their times are collected as in eager execution.  Results are those
- * of the eager launches.  The record copy
+/* Graph replay of stab_execute.  With enable != 0 (and no per-kernel timing selected),
+ * stab_execute captures the device work of a program (every kernel launch up to the record
+ * packing) into a hipGraph the first time it runs it, and replays the graph while the program,
+ * the RNG seed and first shot, the instruction counter and the context's buffers are the same
+ * as at capture (a program executed right after stab_reset, again and again, replays); any
+ * other execution captures anew.  Results are those of the eager launches.  The record copy
  * to the host and the consistency check stay outside the graph.  Errors: STAB_EINVAL (null
  * context). */
 int stab_set_graph(stab_ctx *ctx, int32_t enable);

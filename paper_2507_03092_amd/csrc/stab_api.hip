@@ -115,8 +115,7 @@ struct stab_ctx {
     hipStream_t cap_stream = nullptr;   // capture happens here (the context's stream may be the null stream)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    uint64_t gkey[6] = {0, 0, 0, 0, 0, 0};
-    std::vector<int> gevkind;     // timed pairs the captured graph records (kernel ids)
+    uint64_t gkey[5] = {0, 0, 0, 0, 0};
     uint32_t tmask = 0;           // kernel ids timed (bit k = kernel k)
     std::vector<hipEvent_t> evpool;
     std::vector<int> evkind;      // kernel id of each recorded pair
@@ -805,7 +804,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     };
 
     HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (ctx->graph_on) {
+    if (ctx->graph_on && !ctx->timing) {
         // the launches depend on the program, the RNG key, the instruction counter and the
         // buffers: replay the captured graph while they are unchanged, capture again otherwise
         uint64_t bufsig = 0;
@@ -813,27 +812,13 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                                 &ctx->packed, &ctx->pend, &ctx->plog_p, &ctx->plog_row, &ctx->plog_rs,
                                 &ctx->plog_rd, &ctx->ran, &ctx->plist, &ctx->pcnt, &ctx->povf};
         for (const DevBuf* b : bufs) bufsig = bufsig * 1099511628211ull ^ (uint64_t)(uintptr_t)b->p;
-        // timed launches are bracketed by event-record nodes of the graph, so the timing mask
-        // is part of the key
-        const uint64_t key[6] = {P->serial, ctx->seed, ctx->first_shot, base, bufsig, ctx->tmask};
+        const uint64_t key[5] = {P->serial, ctx->seed, ctx->first_shot, base, bufsig};
         if (!ctx->gexec || std::memcmp(key, ctx->gkey, sizeof(key)) != 0) {
             if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
             if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
             ctx->gexec = nullptr;
             ctx->graph = nullptr;
             if (!ctx->cap_stream) HIP_CHECK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-            // events for every timed launch exist before the capture (at most ten launches per
-            // program step, two events each)
-            ctx->evkind.clear();
-            ctx->evused = 0;
-            if (ctx->timing) {
-                const size_t need = 2 * (10 * P->steps.size() + 4);
-                while (ctx->evpool.size() < need) {
-                    hipEvent_t e;
-                    HIP_CHECK(ctx, hipEventCreate(&e));
-                    ctx->evpool.push_back(e);
-                }
-            }
             HIP_CHECK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             hipStream_t run_stream = ctx->stream;
             ctx->stream = ctx->cap_stream;          // the launches below are recorded, not run
@@ -849,11 +834,6 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             ctx->graph = gr;
             HIP_CHECK(ctx, hipGraphInstantiate(&ctx->gexec, gr, nullptr, nullptr, 0));
             std::memcpy(ctx->gkey, key, sizeof(key));
-            ctx->gevkind = ctx->evkind;
-        } else {
-            // a replay records the same event pairs as the capture did
-            ctx->evkind = ctx->gevkind;
-            ctx->evused = 2 * ctx->gevkind.size();
         }
         HIP_CHECK(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
     } else if ((rc = enqueue())) {

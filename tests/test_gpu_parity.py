@@ -325,32 +325,3 @@ def test_graph_replay_matches_eager(stab):
     ctx.reset(21)
     assert np.array_equal(ctx.execute(prog), eager)
     ctx.close()
-
-
-def test_graph_replay_with_timed_kernels(stab):
-    """Timed kernels inside a captured graph: event-record nodes bracket them, so each replay
-    reports the same launches as eager execution, with positive times, and the same record."""
-    circ, _ = Cc.surface_code_memory(5, 3, 5e-3)
-    shots = 8
-    ctx = stab.Context(circ.n, shots, mode="shared", seed=3)
-    prog = ctx.compile(circ)
-    ctx.set_timing(True, kernels=["segment", "chain"])
-    ctx.reset(3)
-    eager = ctx.execute(prog)
-    t_eager = ctx.kernel_times()
-    ctx.set_graph(True)
-    ctx.reset(3)
-    assert np.array_equal(ctx.execute(prog), eager)      # captured
-    for i in range(3):
-        ctx.set_timing(True, kernels=["segment", "chain"])
-        ctx.reset(3)
-        say(f"timed graph replay {i}")
-        assert np.array_equal(ctx.execute(prog), eager), f"replay {i}"
-        t = ctx.kernel_times()
-        for k in ("segment", "chain"):
-            assert t[k][1] == t_eager[k][1] > 0, (k, t[k], t_eager[k])
-            assert t[k][0] > 0.0, (k, t[k])
-        assert t["det"] == (0.0, 0)
-    ctx.set_graph(False)
-    ctx.set_timing(False)
-    ctx.close()
