@@ -200,6 +200,10 @@ def test_batch_argument_errors_without_gpu(L):
     assert L.stab_batch_execute(None, None, None, None) == stab.EINVAL
     assert L.stab_batch_get_tableau(None, 0, None, None, None) == stab.EINVAL
     assert L.stab_batch_program_records(None, 0) == -1
+    t = C.c_int32(-7)
+    assert L.stab_batch_autotune(None, None, 0, 0, C.byref(t)) == stab.EINVAL and t.value == -7
+    assert L.stab_batch_program_set_tile(None, 0) == stab.EINVAL
+    assert L.stab_batch_program_tile(None) == -1
     L.stab_batch_destroy(None)
     L.stab_batch_program_destroy(None)
 
