@@ -828,7 +828,7 @@ __device__ __forceinline__ void rowsum_rows(const ChainCtx& c, const uint64_t* x
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const int* rows, int nrows, int lane,
                                 int* aff = nullptr, int* aff_n = nullptr, int j = 0,
-                                bool have_rd0 = false, uint64_t rd0 = 0)
+                                bool have_rd0 = false, uint64_t rd0 = 0, uint64_t rd1 = 0)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
@@ -857,7 +857,9 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         if (b < g.bpc) {
             const int gb = c.s * g.bpc + b;
             uint64_t* rdb = c.rd + (size_t)gb * NB;
-            rdp = (((b0 == 0 && have_rd0 ? rd0 : rdb[Wr + wq]) >> (ip & 63)) & 1ull) != 0;
+            // (the first 128 shots' pivot sign words were read with the pivot row)
+            const uint64_t rw = (have_rd0 && b0 == 0) ? rd0 : (have_rd0 && b0 == 64) ? rd1 : rdb[Wr + wq];
+            rdp = ((rw >> (ip & 63)) & 1ull) != 0;
             if (rdp) {
                 uint64_t m = 0;
                 int wc = -1;
@@ -989,12 +991,14 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
         zp[t] = prow[g.Wc + cw];
     }
     const uint64_t rd0 = lane < g.bpc ? c.rd[(size_t)(c.s * g.bpc + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
+    const uint64_t rd1 =
+        lane + 64 < g.bpc ? c.rd[(size_t)(c.s * g.bpc + 64 + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
     const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t)
         if (lane + 64 * t >= g.Wc) xp[t] = zp[t] = 0ull;
     rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
-    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0);
+    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0, rd1);
 }
 
 // Whole block: one target with many stabilizer rows (dense tableaux).  Called by every thread.
