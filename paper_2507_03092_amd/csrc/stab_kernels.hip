@@ -1999,10 +1999,23 @@ __global__ void k_reset_record(Geom g, uint64_t* __restrict__ rd, const uint64_t
     const uint8_t* ob = obuf + (size_t)b * K;
     const uint64_t* Zc = Zcol + ((size_t)s * g.NB + w) * K;
     uint64_t acc = 0;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        const uint8_t o = ob[k];
-        if (do_reset && o) acc ^= Zc[k];
-        if (do_record && w == 0) record[(size_t)b * rec_stride + rec_off + k] = o;
+    // four targets per thread at a time, every load unconditional so they are all in flight
+    const int step = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < K; k0 += 4 * step) {
+        uint8_t o[4];
+        uint64_t z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * step;
+            o[u] = k < K ? ob[k] : (uint8_t)0;
+            z[u] = (do_reset && k < K) ? Zc[k] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * step;
+            if (o[u]) acc ^= z[u];
+            if (do_record && w == 0 && k < K) record[(size_t)b * rec_stride + rec_off + k] = o[u];
+        }
     }
     if (do_reset) {
         __shared__ uint64_t red[16];
