@@ -550,9 +550,22 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         return;
     }
     const uint64_t* X = Xcol + (size_t)s * NB * K;
-    for (int i = threadIdx.x; i < NB * kDetTargets; i += blockDim.x) {
-        const int w = i / kDetTargets, j = i - w * kDetTargets;
-        colw[j * NB + w] = k0 + j < K ? X[(size_t)w * K + k0 + j] : 0ull;
+    // eight words per thread at a time: all loads in flight before the LDS stores
+    const int tot = NB * kDetTargets;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 8 * (int)blockDim.x) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            const int w = i / kDetTargets, j = i - w * kDetTargets;
+            v[u] = (i < tot && k0 + j < K) ? X[(size_t)w * K + k0 + j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            const int w = i / kDetTargets, j = i - w * kDetTargets;
+            if (i < tot) colw[j * NB + w] = v[u];
+        }
     }
     __syncthreads();
     if (k >= K) return;
