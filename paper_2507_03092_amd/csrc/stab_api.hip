@@ -170,6 +170,13 @@ struct stab_program {
     int* d_ev_base = nullptr;
     int* d_ev_count = nullptr;
     long long* d_noise_seg = nullptr;   // per noise instruction: its segment's first event slot
+    int* d_mran = nullptr;              // per measurement layer: a target ran (learning execution)
+    // Per measurement layer, whether a target of it ran in an execution that started from
+    // |0...0> (instruction counter 0).  x|z never depends on outcomes or Pauli noise, so this is
+    // the same in every such execution: later ones skip the chain, the replay, the column
+    // refresh and the second deterministic pass of the layers where nothing ran.
+    std::vector<int> mran;
+    bool mran_known = false;
     int* d_mtq = nullptr;
     // geometry it was compiled for
     int n = 0, B = 0;
@@ -586,6 +593,7 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     for (const SegPlan& sp : P->segs)
         for (int i = 0; i < sp.noise_count; ++i) nseg[sp.noise_begin + i] = sp.ev_global;
     const size_t o_nseg = put(blob, nseg);
+    const size_t o_mran = put(blob, std::vector<int>(std::max<size_t>(P->meas.size(), 1), 0));
     const size_t o_mtq = put(blob, mtq);
     if (hipMalloc(&P->dev, blob.size()) != hipSuccess) {
         delete P;
@@ -606,6 +614,7 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     P->d_ev_base = (int*)(d + o_eb);
     P->d_ev_count = (int*)(d + o_ec);
     P->d_noise_seg = (long long*)(d + o_nseg);
+    P->d_mran = (int*)(d + o_mran);
     P->d_mtq = (int*)(d + o_mtq);
     *out = P;
     return STAB_OK;
@@ -702,6 +711,9 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     int* ran = (int*)ctx->ran.p;
 
     const long long nbytes = (P->nrec + 7) / 8;
+    // layers where nothing ran are known once the program has run from |0...0>
+    const bool use_mran = base == 0 && P->mran_known;
+    const bool learn_mran = base == 0 && !P->mran_known && !P->meas.empty();
     // every launch of the program, eagerly or into a graph (a fill kernel clears the event
     // counts: no memset node in a captured graph)
     auto enqueue = [&]() -> int {
@@ -755,7 +767,10 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                 const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
                 const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
                 TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 0)));
+                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 0, nullptr)));
+                // a layer where nothing ran in an earlier execution from |0...0>: the next four
+                // launches would return at once
+                if (!use_mran || P->mran[st.second]) {
                 TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                                   g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                                   (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
@@ -787,7 +802,9 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                 }
                 // targets the chain found deterministic: reduced in parallel on the final tableau
                 TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 1)));
+                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 1,
+                                                                           learn_mran ? P->d_mran + st.second : nullptr)));
+                }
                 const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
                 TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
                                   g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
@@ -804,7 +821,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     };
 
     HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (ctx->graph_on && !ctx->timing) {
+    if (ctx->graph_on && !ctx->timing && !learn_mran) {
         // the launches depend on the program, the RNG key, the instruction counter and the
         // buffers: replay the captured graph while they are unchanged, capture again otherwise
         uint64_t bufsig = 0;
@@ -855,6 +872,11 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     }
     if (elapsed_ms) HIP_CHECK(ctx, hipEventElapsedTime(elapsed_ms, ctx->ev0, ctx->ev1));
     if (ctx->timing && (rc = tcollect(ctx))) return rc;
+    if (learn_mran) {
+        P->mran.assign(P->meas.size(), 1);
+        HIP_CHECK(ctx, hipMemcpy(P->mran.data(), P->d_mran, P->meas.size() * sizeof(int), hipMemcpyDeviceToHost));
+        P->mran_known = true;
+    }
     if (P->nrec > 0) std::memcpy(out_bits, host.data(), host.size());
     ctx->instr_counter += (uint64_t)P->ninstr;
     return STAB_OK;

@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(64 * kDetTargets) __attribute__((amdgpu_waves_
 k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
       const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
       uint8_t* __restrict__ obuf, int* __restrict__ ran, int* __restrict__ err,
-      unsigned long long* __restrict__ counters, int pass)
+      unsigned long long* __restrict__ counters, int pass, int* __restrict__ ran_log)
 {
     extern __shared__ uint64_t dsm[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -546,8 +546,11 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
     if (pass == 0) {
         // the next launch (the random chain) sets this when a random target runs
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran = 0;
-    } else if (*ran == 0) {
-        return;
+    } else {
+        // (ran_log, when given: whether a target of this layer ran, for the host)
+        const int r = *ran;
+        if (ran_log && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran_log = r;
+        if (r == 0) return;
     }
     const uint64_t* X = Xcol + (size_t)s * NB * K;
     // eight words per thread at a time: all loads in flight before the LDS stores
