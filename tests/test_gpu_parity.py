@@ -325,3 +325,34 @@ def test_graph_replay_matches_eager(stab):
     ctx.reset(21)
     assert np.array_equal(ctx.execute(prog), eager)
     ctx.close()
+
+
+def test_skipped_layers_after_first_execution(stab):
+    """The first execution from |0...0> launches the chain in every measurement layer and learns
+    where a target ran; later executions from |0...0> launch it only there, with the same
+    record (the oracle's); an execution that starts elsewhere launches every layer."""
+    circ, _ = Cc.surface_code_memory(5, 3, 5e-3)
+    shots, seed = 8, 12
+    ctx = stab.Context(circ.n, shots, mode="shared", seed=seed)
+    prog = ctx.compile(circ)
+    want = O.run(circ, shots, seed)
+    nlayers = None
+    for i in range(3):
+        ctx.set_timing(True)
+        ctx.reset(seed)
+        got = ctx.execute(prog)
+        t = ctx.kernel_times()
+        say(f"execution {i}: chain launches {t['chain'][1]}, replay {t['replay'][1]}")
+        assert np.array_equal(got, want), f"execution {i}"
+        if i == 0:
+            nlayers = t["chain"][1]
+            assert nlayers == t["classify"][1] > 2
+        else:
+            assert 0 < t["chain"][1] < nlayers
+            assert t["replay"][1] == t["extract"][1] == t["det"][1] == t["chain"][1]
+    # continuing without a reset: every layer's chain is launched
+    ctx.set_timing(True)
+    ctx.execute(prog)
+    assert ctx.kernel_times()["chain"][1] == nlayers
+    ctx.set_timing(False)
+    ctx.close()
