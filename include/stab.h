@@ -134,7 +134,12 @@ int stab_compile(stab_ctx *ctx, const stab_instr *instrs, int32_t ninstr,
                  const int32_t *targets, int64_t ntargets, stab_program **out);
 
 /* Execute a compiled stream (same semantics and out_bits layout as stab_run).  If elapsed_ms
- * is not NULL it receives the device time from the first kernel to the record on the host. */
+ * is not NULL it receives the device time from the first kernel to the record on the host.
+ * The first execution of prog that starts from |0...0> (instruction counter 0) records which
+ * measurement layers had a random target; since x|z never depends on outcomes or Pauli noise
+ * this holds for every such execution, and later ones skip the random-measurement kernels of
+ * the other layers (same results, fewer launches).  prog is updated by this, so one program
+ * is not executed by two threads at once. */
 int stab_execute(stab_ctx *ctx, stab_program *prog, uint8_t *out_bits, float *elapsed_ms);
 
 /* Number of M/MR targets a compiled stream records per shot. */
