@@ -30,8 +30,8 @@ METRIC = "syndrome rounds/sec & measurements/sec at d=25/71, batched vs plain, b
 
 DEFAULTS = {  # steps, warmup, shots (circuits) timed in the plain form
     "surface_d3": (20, 2, 200),
-    "surface_d25": (10, 1, 10),
-    "surface_d71": (3, 1, 2),
+    "surface_d25": (50, 2, 10),
+    "surface_d71": (10, 1, 2),
     "random_batch": (3, 1, 64),
     "commute": (20, 2, 0),
     "surface_d25_t1t2": (3, 1, 0),
