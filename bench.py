@@ -80,24 +80,252 @@ def load_pmc(workload: str, mode: str, tile=None) -> dict:
     return {k: (v["fetch_kib"] * fs + v["write_kib"] * ws) * 1024.0 for k, v in p["kernels"].items()}
 
 
+def cpu_host() -> dict:
+    """Host CPU model and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable}
+
+
+def surface_alg_bytes(n, d, rounds, shots, mode, work, per_step) -> dict:
+    """Algorithmic bytes per step of each surface-code kernel: the per-unit figures of the
+    kernels (one band, one target, one rowsum row) times the work counters of a step."""
+    wc = (n + 63) // 64
+    row_b, nb = 2 * wc * 8, 2 * wc
+    return {
+        # one segment per round (gates change x|z) plus the noise-only segment before the final
+        # data readout; K = d*d-1 ancillas, then d*d data qubits
+        "segment": rounds * seg_bytes_per_launch(n, shots, mode, d * d - 1, True)
+        + seg_bytes_per_launch(n, shots, mode, d * d, False),
+        # per random measurement: the stabilizer half of its column, the pivot row read, logged
+        # and replaced; per stabilizer rowsum row a read and a write
+        "chain": work[4] * (wc * 8 + 3 * row_b) + work[5] * 2 * row_b,
+        # per walked destabilizer a read and a write, per applied pivot its logged row read
+        "replay": work[9] * 2 * row_b + work[8] * row_b,
+        # the final tableau read and the columns of every target written (about d*d targets)
+        "extract": per_step.get("extract", (0, 0))[1] * seg_bytes_per_launch(n, shots, mode, d * d, False),
+        # layer start: every target's column read, and every stabilizer row multiplied by a
+        # deterministic reduction (both passes; the second pass reduces few)
+        "classify": (work[2] + work[4] + work[6]) * nb * 8 + work[3] * row_b,
+        # after the chain: the columns of the targets it left deterministic
+        "det": work[6] * nb * 8,
+    }
+
+
+ROOF_KERNELS = ("segment", "classify", "chain")
+
+
+def run_surface(workload: str, mode: str, steps: int, warmup: int, graph: bool, plain_shots: int, log) -> dict:
+    """Time `steps` steps of a surface-code workload in one storage mode.  Returns the step
+    times, the record, the per-kernel breakdown, the work counters and rooflines of the dominant
+    kernel and of the segment, classify and chain kernels."""
+    import numpy as np
+    import torch
+
+    from paper_2507_03092_amd import circuits as Cc
+    from paper_2507_03092_amd import stab
+
+    w = Cc.WORKLOADS[workload]
+    circ, lay, seed, shots = Cc.workload(workload)
+    d, rounds = w["d"], w["rounds"]
+    nmeas = circ.num_measurements()
+    n = circ.n
+    log(f"{workload}: n={n} rounds={rounds} shots={shots} mode={mode}")
+    ctx = stab.Context(n, shots, mode=mode, seed=seed)
+    prog = ctx.compile(circ)
+    for _ in range(warmup):
+        ctx.reset(seed)
+        ctx.execute(prog)
+    # per-kernel breakdown from one untimed step with every launch bracketed by events; the
+    # timed eager steps then bracket only the kernels whose rooflines are reported (each
+    # event pair costs a few microseconds of the step)
+    ctx.set_timing(True)
+    ctx.reset(seed)
+    ctx.execute(prog)
+    full = ctx.kernel_times()
+    breakdown = {k: v[0] for k, v in full.items() if v[1] > 0}
+    dom = max(breakdown, key=breakdown.get)
+    timed = sorted(set(ROOF_KERNELS) | {dom})
+    ctx.set_timing(True, kernels=timed)
+    cnt0 = ctx.counters().astype(np.int64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.reset(seed)
+        rec = ctx.execute(prog)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ktimes = ctx.kernel_times()
+    ctx.set_timing(False)
+    work = (ctx.counters().astype(np.int64) - cnt0) / steps     # per step
+    eager_ms_step = (t1 - t0) * 1000.0 / steps
+    if graph:
+        # the same steps replayed as one captured graph each, no events: the throughput (the
+        # capture happens in an untimed step first)
+        ctx.set_graph(True)
+        ctx.reset(seed)
+        ctx.execute(prog)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.reset(seed)
+            grec = ctx.execute(prog)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.set_graph(False)
+        if not np.array_equal(grec, rec):
+            raise AssertionError("graph replay record differs from the eager record")
+    ms_step = (t1 - t0) * 1000.0 / steps
+    rounds_s = shots * rounds / ((t1 - t0) / steps)
+    meas_s = shots * nmeas / ((t1 - t0) / steps)
+    log(f"{workload} batched-{mode}: {ms_step:.3f} ms/step, {rounds_s:.1f} rounds/s, {meas_s:.3e} meas/s")
+
+    per_step = {k: (v[0] / steps, v[1] / steps) for k, v in ktimes.items()}
+    alg = surface_alg_bytes(n, d, rounds, shots, mode, work, per_step)
+    pmc = load_pmc(workload, mode)
+
+    def roof(kernel):
+        ms, launches = per_step[kernel]
+        if not launches or kernel not in alg:
+            return None
+        per_launch = alg[kernel] / launches
+        achieved = per_launch / (ms / launches / 1000.0) / 1e9
+        t = pmc.get(kernel)
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": int(t) if t is not None else None, "bytes_per_launch": int(per_launch),
+                "avg_launch_us": round(ms * 1000.0 / launches, 2), "launches_per_step": launches,
+                "share_of_step": round(ms / eager_ms_step, 3)}
+
+    rooflines = {k: roof(k) for k in timed if k in alg}
+    roofline = dict(rooflines[dom]) if rooflines.get(dom) else None
+    if roofline is not None:
+        roofline["timed_in"] = "eager steps (the same count, right before the graph-replayed ones)"
+
+    plain = None
+    if plain_shots > 0:
+        ctx1 = stab.Context(n, 1, mode="shared", seed=seed)
+        prog1 = ctx1.compile(circ)
+        ctx1.reset(seed, first_shot=0)
+        ctx1.execute(prog1)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        ok = True
+        for b in range(plain_shots):
+            ctx1.reset(seed, first_shot=b)
+            r1 = ctx1.execute(prog1)
+            ok &= bool(np.array_equal(r1[0], rec[b]))
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        plain = {"rounds_per_s": round(plain_shots * rounds / (p1 - p0), 2),
+                 "meas_per_s": round(plain_shots * nmeas / (p1 - p0), 1),
+                 "ms_per_shot": round((p1 - p0) * 1000.0 / plain_shots, 3),
+                 "shots_timed": plain_shots, "matches_batched": ok}
+        log(f"{workload} plain: {plain}")
+        ctx1.close()
+    ctx.close()
+    return {
+        "workload": workload, "mode": mode, "circ": circ, "seed": seed, "shots": shots, "d": d,
+        "rounds": rounds, "n": n, "nmeas": nmeas, "w": w, "rec": rec, "steps": steps,
+        "ms_step": ms_step, "eager_ms_step": eager_ms_step, "rounds_s": rounds_s, "meas_s": meas_s,
+        "breakdown": breakdown, "roofline": roofline, "rooflines": rooflines, "work": work, "plain": plain,
+        "graph": graph,
+    }
+
+
+def surface_cpu_baseline(r: dict, log) -> dict:
+    """The oracle on the host, bit-exact against the GPU record: all cores (one thread per
+    shot) and one core.  d=71 runs the first two rounds of the workload's op stream (an exact
+    prefix, so its records are a prefix of the GPU's); the smaller workloads run whole."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2507_03092_amd import circuits as Cc
+
+    circ, seed, shots, rec = r["circ"], r["seed"], r["shots"], r["rec"]
+    if r["workload"] == "surface_d71":
+        ins, tg = circ.arrays()
+        k = int(np.nonzero(ins["kind"] == Cc.MR)[0][1]) + 1            # through round 2's MR
+        sc = Cc.PackedCircuit(circ.n, ins[:k].copy(), tg[:int(ins["ntargets"][:k].sum())].copy())
+        srounds, one_shots = 2, 1
+        desc = "the first 2 rounds of the d=71 op stream (round 1 holds the random X-ancilla measurements)"
+    else:
+        sc, srounds = circ, r["rounds"]
+        one_shots = min(shots, 4)
+        desc = f"the whole {r['workload']} workload"
+    nrec = sc.num_measurements()
+    c0 = time.perf_counter()
+    orec = O.run(sc, shots, seed)
+    c1 = time.perf_counter()
+    ok_all = bool(np.array_equal(orec, rec[:, :nrec]))
+    o0 = time.perf_counter()
+    ok_one = True
+    for s in range(one_shots):
+        o = O.run(sc, 1, seed, first_shot=s)        # one shot: one thread
+        ok_one &= bool(np.array_equal(o[0], rec[s, :nrec]))
+    o1 = time.perf_counter()
+    cpu = {"value": round(shots * srounds / (c1 - c0), 4), "unit": "rounds/s",
+           "cores": min(O.threads(), shots), "kind": "oracle",
+           "sample": f"{desc}; all {shots} shots, one host thread per shot", "seconds": round(c1 - c0, 2),
+           "bit_exact_vs_gpu": ok_all and ok_one,
+           "one_core": {"value": round(one_shots * srounds / (o1 - o0), 4), "unit": "rounds/s", "cores": 1,
+                        "sample": f"{one_shots} shot(s) of the same, one after another",
+                        "seconds": round(o1 - o0, 2)}}
+    cpu.update(cpu_host())
+    log(f"{r['workload']} cpu baseline: {cpu}")
+    return cpu
+
+
+def surface_summary(r: dict) -> dict:
+    """The fields of a timed surface-code run that go into the JSON line."""
+    work = r["work"]
+    return {
+        "ms_per_step": round(r["ms_step"], 4), "eager_ms_per_step": round(r["eager_ms_step"], 4),
+        "rounds_per_s": round(r["rounds_s"], 2), "measurements_per_s": round(r["meas_s"], 1),
+        "launch": "captured graph" if r["graph"] else "eager",
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in r["breakdown"].items()},
+        "roofline": r["roofline"],
+        "rooflines": r["rooflines"],
+        "work_per_step": {"random_measurements": int(work[4]), "rowsum_rows": int(work[5]),
+                          "replay_rowsum_rows": int(work[8]), "replay_walked_rows": int(work[9]),
+                          "replay_rows_by_testing": int(work[10]), "replay_events_by_testing": int(work[11]),
+                          "deterministic_measurements": int(work[2] + work[6]),
+                          "multiplied_rows": int(work[3]), "chain_rounds": int(work[0]),
+                          "noise_events": int(work[7])},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="surface_d25", choices=sorted(DEFAULTS))
+    ap.add_argument("--workload", default="surface_d71", choices=sorted(DEFAULTS))
     ap.add_argument("--mode", default="shared", choices=["shared", "full"])
     ap.add_argument("--plain-shots", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-companions", action="store_true",
+                    help="surface_d71: skip the batched-full form and the d=25 workload that the "
+                         "default line carries beside the headline")
     ap.add_argument("--no-graph", action="store_true",
                     help="surface workloads: launch every kernel eagerly in the timed steps")
     ap.add_argument("--tile", default="auto",
                     help="random_batch launch configuration: 'auto' (autotuner, first two measurement "
                          "instructions of every circuit) or a configuration number")
     ap.add_argument("--tune-quota", type=int, default=2, help="measurement instructions the autotuner times")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="arrival window of the serving workload (the full recipe is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="arrival window of the serving workload")
     ap.add_argument("--serve-rate", type=float, default=None, help="arrival rate of the serving workload (1/s)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte "
@@ -110,9 +338,6 @@ def main() -> int:
 
     import numpy as np
     import torch
-
-    from paper_2507_03092_amd import circuits as Cc
-    from paper_2507_03092_amd import stab
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -134,184 +359,54 @@ def main() -> int:
         return bench_exact_noise(args)
     if args.workload == "serve":
         return bench_serve(args)
-    steps0, warm0, plain0 = DEFAULTS[args.workload]
-    steps = args.steps if args.steps is not None else steps0
-    warmup = args.warmup if args.warmup is not None else warm0
-    plain_shots = args.plain_shots if args.plain_shots is not None else plain0
-
-    w = Cc.WORKLOADS[args.workload]
-    circ, lay, seed, shots = Cc.workload(args.workload)
-    d, rounds = w["d"], w["rounds"]
-    nmeas = circ.num_measurements()
-    n = circ.n
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    # ---------------- batched: all shots, one launch sequence ----------------
-    log(f"{args.workload}: n={n} rounds={rounds} shots={shots} mode={args.mode}")
-    ctx = stab.Context(n, shots, mode=args.mode, seed=seed)
-    prog = ctx.compile(circ)
-    for _ in range(warmup):
-        ctx.reset(seed)
-        ctx.execute(prog)
-    # per-kernel breakdown from one untimed step with every launch bracketed by events; the
-    # timed steps then bracket only the dominant kernel's launches (each event pair costs a
-    # few microseconds of the step)
-    ctx.set_timing(True)
-    ctx.reset(seed)
-    ctx.execute(prog)
-    full = ctx.kernel_times()
-    breakdown = {k: v[0] for k, v in full.items() if v[1] > 0}
-    dom = max(breakdown, key=breakdown.get)
-    # eager steps with the dominant kernel's launches bracketed by events: the roofline
-    ctx.set_timing(True, kernels=[dom])
-    cnt0 = ctx.counters().astype(np.int64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.reset(seed)
-        rec = ctx.execute(prog)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ktimes = ctx.kernel_times()
-    ctx.set_timing(False)
-    work = (ctx.counters().astype(np.int64) - cnt0) / steps     # per step
-    eager_ms_step = (t1 - t0) * 1000.0 / steps
-    if not args.no_graph:
-        # the same steps replayed as one captured graph each, no events: the throughput (the
-        # capture happens in an untimed step first)
-        ctx.set_graph(True)
-        ctx.reset(seed)
-        ctx.execute(prog)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.reset(seed)
-            grec = ctx.execute(prog)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ctx.set_graph(False)
-        if not np.array_equal(grec, rec):
-            raise AssertionError("graph replay record differs from the eager record")
-    ms_step = (t1 - t0) * 1000.0 / steps
-    rounds_s = shots * rounds / ((t1 - t0) / steps)
-    meas_s = shots * nmeas / ((t1 - t0) / steps)
-    log(f"batched: {ms_step:.3f} ms/step, {rounds_s:.1f} rounds/s, {meas_s:.3e} meas/s")
+    def knobs(workload):
+        steps0, warm0, plain0 = DEFAULTS[workload]
+        steps = args.steps if args.steps is not None else steps0
+        warmup = args.warmup if args.warmup is not None else warm0
+        plain = 0 if args.no_plain else (args.plain_shots if args.plain_shots is not None else plain0)
+        return steps, warmup, plain
 
-    # ---------------- rooflines: the dominant kernel, and the segment kernel ----------------
-    per_step = {k: (v[0] / steps, v[1] / steps) for k, v in ktimes.items()}
-    wc = (n + 63) // 64
-    row_b, nb = 2 * wc * 8, 2 * wc
-    copies = 1 if args.mode == "shared" else shots
-    # algorithmic bytes per step of each kernel (per-unit figures times the work counters)
-    alg = {
-        # surface-code stream: one segment per round (gates change x|z) plus the noise-only
-        # segment before the final data readout; K = d*d-1 ancillas, then d*d data qubits
-        "segment": rounds * seg_bytes_per_launch(n, shots, args.mode, d * d - 1, True)
-        + seg_bytes_per_launch(n, shots, args.mode, d * d, False),
-        # per random measurement: the stabilizer half of its column, the pivot row read, logged
-        # and replaced; per stabilizer rowsum row a read and a write
-        "chain": work[4] * (wc * 8 + 3 * row_b) + work[5] * 2 * row_b,
-        # per walked destabilizer a read and a write, per applied pivot its logged row read
-        "replay": work[9] * 2 * row_b + work[8] * row_b,
-        # the final tableau read and the columns of every target written (about d*d targets)
-        "extract": per_step["extract"][1] * seg_bytes_per_launch(n, shots, args.mode, d * d, False),
-        # layer start: every target's column read, and every stabilizer row multiplied by a
-        # deterministic reduction (both passes; the second pass reduces few)
-        "classify": (work[2] + work[4] + work[6]) * nb * 8 + work[3] * row_b,
-        # after the chain: the columns of the targets it left deterministic
-        "det": work[6] * nb * 8,
-    }
-    pmc = load_pmc(args.workload, args.mode)
-
-    def roof(kernel, times=None):
-        ms, launches = (times or per_step)[kernel]
-        if not launches or kernel not in alg:
-            return None
-        per_launch = alg[kernel] / launches
-        achieved = per_launch / (ms / launches / 1000.0) / 1e9
-        t = pmc.get(kernel)
-        return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": int(t) if t is not None else None, "bytes_per_launch": int(per_launch),
-                "avg_launch_us": round(ms * 1000.0 / launches, 2), "launches_per_step": launches}
-
-    roofline = roof(dom)
-    if roofline is not None:
-        roofline["share_of_step"] = round(per_step[dom][0] / eager_ms_step, 3)
-        roofline["timed_in"] = "eager steps (the same count, right before the graph-replayed ones)"
-    # the segment kernel beside it (from the breakdown step when it is not the dominant one)
-    roofline_segment = roof("segment") if dom == "segment" else roof("segment", {"segment": full["segment"]})
-
-    # ---------------- plain: one shot at a time ----------------
-    plain = None
-    if not args.no_plain and plain_shots > 0:
-        ctx1 = stab.Context(n, 1, mode="shared", seed=seed)
-        prog1 = ctx1.compile(circ)
-        ctx1.reset(seed, first_shot=0)
-        ctx1.execute(prog1)
-        torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        ok = True
-        for b in range(plain_shots):
-            ctx1.reset(seed, first_shot=b)
-            r1 = ctx1.execute(prog1)
-            ok &= bool(np.array_equal(r1[0], rec[b]))
-        torch.cuda.synchronize()
-        p1 = time.perf_counter()
-        plain = {"rounds_per_s": round(plain_shots * rounds / (p1 - p0), 2),
-                 "meas_per_s": round(plain_shots * nmeas / (p1 - p0), 1),
-                 "ms_per_shot": round((p1 - p0) * 1000.0 / plain_shots, 3),
-                 "shots_timed": plain_shots, "matches_batched": ok}
-        log(f"plain: {plain}")
-        ctx1.close()
-
-    # ---------------- CPU baseline: the oracle on a bounded sample ----------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-
-        if args.workload == "surface_d71":
-            sc, _ = Cc.surface_code_memory(d, 2, w["p"], w["idle"])
-            sshots, srounds, desc = 1, 2, "1 shot of the d=71 circuit truncated to its first 2 rounds"
-        elif args.workload == "surface_d25":
-            sc, sshots, srounds, desc = circ, shots, rounds, "the whole d=25 workload (100 shots x 25 rounds)"
-        else:
-            sc, sshots, srounds, desc = circ, shots, rounds, "the whole d=3 workload (1000 shots x 3 rounds)"
-        c0 = time.perf_counter()
-        orec = O.run(sc, sshots, seed)
-        c1 = time.perf_counter()
-        bit_exact = None
-        if sc is circ:
-            bit_exact = bool(np.array_equal(orec, rec[:sshots]))
-        cpu = {"value": round(sshots * srounds / (c1 - c0), 3), "unit": "rounds/s",
-               "cores": O.threads(), "kind": "oracle", "sample": desc,
-               "seconds": round(c1 - c0, 2), "bit_exact_vs_gpu": bit_exact}
-        log(f"cpu baseline: {cpu}")
-
+    steps, warmup, plain_shots = knobs(args.workload)
+    head = run_surface(args.workload, args.mode, steps, warmup, not args.no_graph, plain_shots, log)
+    w = head["w"]
     line = {
-        "metric": METRIC, "value": round(rounds_s, 2), "unit": "rounds/s", "n_gpus": 1,
-        "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "metric": METRIC, "value": round(head["rounds_s"], 2), "unit": "rounds/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(head["ms_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": args.workload, "code": "rotated surface code, Z memory", "d": d,
-                   "qubits": n, "rounds": rounds, "shots": shots, "p_depolarizing": w["p"],
-                   "idle_pauli": list(w["idle"]) if w["idle"] else None, "seed": seed,
+        "config": {"workload": args.workload, "code": "rotated surface code, Z memory", "d": head["d"],
+                   "qubits": head["n"], "rounds": head["rounds"], "shots": head["shots"], "p_depolarizing": w["p"],
+                   "idle_pauli": list(w["idle"]) if w["idle"] else None, "seed": head["seed"],
                    "form": f"batched-{args.mode}", "launch": "eager" if args.no_graph else "captured graph"},
-        "eager_ms_per_step": round(eager_ms_step, 4),
-        "measurements_per_s": round(meas_s, 1),
-        "plain": plain,
-        "kernel_ms_per_step": {k: round(v, 4) for k, v in breakdown.items()},
-        "roofline": roofline,
-        "roofline_segment": roofline_segment,
-        "work_per_step": {"random_measurements": int(work[4]), "rowsum_rows": int(work[5]),
-                          "replay_rowsum_rows": int(work[8]), "replay_walked_rows": int(work[9]),
-                          "replay_rows_by_testing": int(work[10]), "replay_events_by_testing": int(work[11]),
-                          "deterministic_measurements": int(work[2] + work[6]),
-                          "multiplied_rows": int(work[3]), "chain_rounds": int(work[0]),
-                          "noise_events": int(work[7])},
-        "cpu_baseline": cpu,
     }
+    summ = surface_summary(head)
+    for k in ("eager_ms_per_step", "measurements_per_s", "kernel_ms_per_step", "roofline", "rooflines",
+              "work_per_step"):
+        line[k] = summ[k]
+    line["plain"] = head["plain"]
+    companions = args.workload == "surface_d71" and args.mode == "shared" and not args.no_companions
+    if companions:
+        # the same workload with one tableau per shot (records must equal the shared form's)
+        full = run_surface("surface_d71", "full", steps, warmup, not args.no_graph, 0, log)
+        fs = surface_summary(full)
+        fs["matches_shared"] = bool(np.array_equal(full["rec"], head["rec"]))
+        if not fs["matches_shared"]:
+            raise AssertionError("batched-full record differs from batched-shared")
+        line["full"] = fs
+        del full
+        # d=25, shared, with its plain form and its own CPU baseline
+        s25, w25, p25 = knobs("surface_d25")
+        r25 = run_surface("surface_d25", "shared", s25, w25, not args.no_graph, p25, log)
+        line["d25"] = {"config": {"workload": "surface_d25", "d": 25, "qubits": r25["n"], "rounds": r25["rounds"],
+                                  "shots": r25["shots"], "seed": r25["seed"], "form": "batched-shared",
+                                  "steps": s25},
+                       **surface_summary(r25), "plain": r25["plain"]}
+        if not args.no_cpu_baseline:
+            line["d25"]["cpu_baseline"] = surface_cpu_baseline(r25, log)
+    line["cpu_baseline"] = None if args.no_cpu_baseline else surface_cpu_baseline(head, log)
     print(json.dumps(line))
     return 0
 
@@ -499,7 +594,7 @@ def bench_serve(args) -> int:
     lat_ms = np.array(lat) * 1000.0
     p50 = float(np.percentile(lat_ms, 50)) if len(lat) else None
     p99 = float(np.percentile(lat_ms, 99)) if len(lat) else None
-    log(f"served {len(lat)} of {m} in {wall:.1f} s, p50 {p50:.1f} ms, p99 {p99:.1f} ms, {steps} steps")
+    log(f"served {len(lat)} of {m} in {wall:.1f} s, p50 {p50} ms, p99 {p99} ms, {steps} steps")
     cpu = None
     if not args.no_cpu_baseline:
         from concurrent.futures import ThreadPoolExecutor
@@ -574,7 +669,7 @@ def bench_exact_noise(args) -> int:
     bytes_launch = float(dc[6] + dc[7])
     achieved = bytes_launch / (k_ms / 1000.0) / 1e9
     log(f"{args.workload}: {ms_step:.2f} ms/step, {shots * rounds / (ms_step / 1000.0):.1f} rounds/s")
-    traffic = load_pmc("random_batch", "batch", prog.tile).get("batch")
+    traffic = load_pmc(args.workload, "batch", prog.tile).get("batch")
     roofline = {"kernel": "batch", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": int(traffic) if traffic is not None else None,

@@ -268,3 +268,51 @@ def test_batch_surface_code_exact_t1t2_shots(stab):
     for s in range(shots):
         assert np.array_equal(got[s], want[s]), f"shot {s}"
     b.close()
+
+
+def test_batch_t1t2_draw_format_circuit(stab):
+    """The circuit of the oracle's exact T1T2 draw pin (Bell pairs whose records expose the
+    reset branch, its outcome u1 >> 63 and the Z branch), 256 shots as a batch."""
+    seed, shots, pairs = 1234, 256, 3
+    n = 2 * pairs
+    a, b = list(range(0, n, 2)), list(range(1, n, 2))
+    c = Cc.Circuit(n=n)
+    c.gate(Cc.H, a)
+    c.gate(Cc.CX, [q for j in range(pairs) for q in (a[j], b[j])])
+    c.append(Cc.T1T2, a, (int(0.35 * 2 ** 64), int(0.7 * 2 ** 64), 0))
+    c.gate(Cc.CX, [q for j in range(pairs) for q in (a[j], b[j])])
+    c.gate(Cc.H, a)
+    c.append(Cc.M, a + b)
+    want = O.run(c, shots, seed)
+    bt = stab.Batch(np.full(shots, n, dtype=np.int32), seed=seed)
+    got = bt.execute(bt.compile([c] * shots))
+    for s in range(shots):
+        assert np.array_equal(got[s], want[s]), f"shot {s}"
+    assert np.stack(got)[:, pairs:].any()      # some reset drew outcome 1
+    bt.close()
+
+
+def test_batch_random_workload_largest_circuits_digests(stab):
+    """The 4096-circuit workload in the benchmark's launch: its largest circuit and five of
+    n >= 1500 against record digests written by tests/golden/make_batch_golden.py (oracle
+    only; too slow to recompute in a test, ~1-3 min per circuit on one core)."""
+    import hashlib
+    import json
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "random_batch_large_oracle.json")
+    ref = json.load(open(path))
+    w = Cc.RANDOM_BATCH
+    assert ref["seed"] == w["seed"] and ref["ncirc"] == w["ncirc"]
+    ns, circs = Cc.random_batch(w["ncirc"], w["n_lo"], w["n_hi"], w["layers"], w["seed"], w["meas_every"],
+                                w["meas_frac"])
+    say(f"full batch generated: {len(circs)} circuits")
+    b = stab.Batch(ns, seed=w["seed"])
+    prog = b.compile(circs)
+    got, ms = b.execute(prog, timed=True)
+    say(f"full batch executed in {ms:.1f} ms")
+    for e in ref["circuits"]:
+        c = e["index"]
+        assert int(ns[c]) == e["n"] and len(got[c]) == e["measurements"]
+        dig = hashlib.sha256(np.packbits(got[c], bitorder="little").tobytes()).hexdigest()
+        assert dig == e["sha256"] and int(got[c].sum()) == e["ones"], f"circuit {c} (n={ns[c]})"
+    b.close()

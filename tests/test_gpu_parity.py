@@ -210,6 +210,28 @@ def test_surface_d71_workload_against_stored_oracle_digests(stab):
         assert int(got[s].sum()) == ref["ones"][s]
 
 
+def test_surface_d71_full_mode_against_stored_oracle_digests(stab):
+    """Batched-full d=71 (ten 51 MB tableaux, 71 rounds, the benchmark's full-mode launch)
+    against the same oracle-only per-shot digests: full mode draws with the same keys."""
+    path = os.path.join(GOLDEN, "surface_d71_oracle.json")
+    ref = json.load(open(path))
+    circ, lay, seed, shots = Cc.workload("surface_d71")
+    assert ref["seed"] == seed and ref["shots"] == shots and ref["measurements"] == circ.num_measurements()
+    say(f"surface_d71 full mode: n={circ.n} shots={shots}")
+    ctx = stab.Context(circ.n, shots, mode="full", seed=seed)
+    got = ctx.run(circ)
+    for s in range(shots):
+        assert _record_digest(got[s]) == ref["sha256"][s], f"shot {s}"
+        assert int(got[s].sum()) == ref["ones"][s]
+    ctx.close()
+
+
+def test_surface_d71_full_mode_tableau(stab):
+    # full mode at n = 10081: first two rounds, two shots, every row of both tableaux
+    circ, lay, seed, shots = Cc.workload("surface_d71", rounds=2)
+    _compare(stab, circ, shots=2, seed=seed, mode="full", tableau_shots=(0, 1))
+
+
 def test_chain_ghz_layer(stab):
     # one random outcome then every other target deterministic within the same layer
     n = 300

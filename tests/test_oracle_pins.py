@@ -670,3 +670,47 @@ def test_t1t2_oracle_statistics():
     p0 = 1 - O.run(c, shots, seed=4).mean()
     want = (1 + np.exp(-t / T2)) / 2
     assert abs(p0 - want) < 4 * np.sqrt(want * (1 - want) / shots)
+
+
+def test_t1t2_draw_format_exact():
+    """T1T2's draws follow the op-stream format exactly (numpy Philox as RNG): reset iff
+    u0 < t0, with the reset's random outcome u1 >> 63; else Z iff u0 < t1.
+
+    Qubit a = 2j starts entangled with its partner 2j+1 (Bell pair), so the reset's Z
+    measurement of a is random and collapses the partner onto its outcome, which the final M
+    of the partner records; a Z (no reset) turns the pair into the other Bell state, which the
+    CX + H readout maps to a = 1.  After a reset, a is |0>, the readout leaves it in |+>, and
+    its M is the random draw of that instruction."""
+    seed, shots, pairs = 1234, 256, 3
+    n = 2 * pairs
+    a, b = list(range(0, n, 2)), list(range(1, n, 2))
+    t0, t1 = int(0.35 * 2 ** 64), int(0.7 * 2 ** 64)
+    c = Cc.Circuit(n=n)
+    c.gate(Cc.H, a)                                           # instruction 0
+    c.gate(Cc.CX, [q for j in range(pairs) for q in (a[j], b[j])])   # 1
+    c.append(Cc.T1T2, a, (t0, t1, 0))                         # 2
+    c.gate(Cc.CX, [q for j in range(pairs) for q in (a[j], b[j])])   # 3
+    c.gate(Cc.H, a)                                           # 4
+    c.append(Cc.M, a + b)                                     # 5
+    rec = O.run(c, shots, seed=seed)
+    seen = set()
+    for shot in range(shots):
+        want_a, want_b = [], []
+        for j in range(pairs):
+            u = _numpy_block(seed, shot, 2, j)
+            if u[0] < t0:
+                m = u[1] >> 63
+                want_a.append(_numpy_block(seed, shot, 5, j)[0] >> 63)
+                want_b.append(m)
+                seen.add(("reset", m))
+            elif u[0] < t1:
+                want_a.append(1)
+                want_b.append(0)
+                seen.add(("z", 0))
+            else:
+                want_a.append(0)
+                want_b.append(0)
+                seen.add(("none", 0))
+        assert list(rec[shot]) == want_a + want_b, shot
+    # every branch, and both reset outcomes, occurred
+    assert seen == {("reset", 0), ("reset", 1), ("z", 0), ("none", 0)}
