@@ -169,6 +169,25 @@ int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets
                 void *dev_buf, uint64_t buf_bytes, void *hip_stream, uint8_t *out_bits,
                 float *elapsed_ms);
 
+/* stab_sample without device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, semantics and out_bits layout as stab_sample (no elapsed time).  The
+ * caller still provides the tableaux (dev_buf, stab_tableau_bytes bytes) and the host output;
+ * every buffer stab_sample would allocate (error flag, counters, the uploaded program, target
+ * columns, noise events, pivot log, records) is carved instead from one static device array of
+ * STAB_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the process ends.
+ * Nothing is allocated or freed on the device: no hipMalloc, hipFree, event or stream creation
+ * (host-side the stream is compiled in ordinary heap memory, as by stab_sample).  Noise is drawn
+ * segment by segment unless the whole program's draws also fit.  Every call on one GPU uses
+ * that GPU's array and leaves its last contents there (each call clears what it needs), so
+ * calls that overlap on one GPU race: serialise them.  Errors: as stab_sample, and STAB_ERANGE,
+ * before the device is touched, when the workload needs more scratch than the array holds
+ * (a d=25 surface-code memory experiment with 100 shots needs about 9 MB; d=71 does not fit). */
+#define STAB_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int stab_sample_noalloc(const stab_instr *instrs, int32_t ninstr, const int32_t *targets,
+                        int64_t ntargets, int32_t n, int32_t shots, int32_t mode, uint64_t seed,
+                        void *dev_buf, uint64_t buf_bytes, void *hip_stream, uint8_t *out_bits);
+
 /* Work counters accumulated by a context since creation (for accounting and bandwidth
  * figures): [0] rounds of the random-measurement chain, [1] chain rounds run by a whole block
  * (targets touching many rows), [2] measurements deterministic at layer start, [3] stabilizer

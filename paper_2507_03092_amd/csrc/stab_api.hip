@@ -88,6 +88,7 @@ Layout layout_of(const Geom& g)
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool arena = false;   // carved from the static scratch array (never freed)
 };
 
 }  // namespace
@@ -102,6 +103,10 @@ struct stab_ctx {
     uint64_t* rd = nullptr;
     bool poisoned = false;
     int max_lds = kLdsBytes;
+    // stab_sample_noalloc: every buffer of the context and its program is carved from the
+    // static scratch array of the device (arena != NULL), nothing is allocated or freed
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     int* d_err = nullptr;
     unsigned long long* d_counters = nullptr;
     DevBuf xcol, zcol, cls, obuf, events, record, packed, pend;
@@ -162,6 +167,7 @@ struct stab_program {
     std::vector<std::pair<int, int>> steps;   // (0, segment) or (1, measurement layer)
     // device copies
     void* dev = nullptr;
+    bool dev_arena = false;   // dev lies in the static scratch (stab_sample_noalloc)
     int4* d_items = nullptr;
     uint2* d_gates = nullptr;
     NoiseDesc* d_noise = nullptr;
@@ -185,6 +191,36 @@ struct stab_program {
 
 namespace {
 
+// Carve `bytes` (256-byte aligned) from the context's static scratch; STAB_ERANGE past its end.
+int arena_take(stab_ctx* ctx, size_t bytes, void** out)
+{
+    const size_t at = align256(ctx->arena_used);
+    bytes = std::max<size_t>(align256(bytes), 256);
+    if (at + bytes > ctx->arena_cap)
+        return fail(STAB_ERANGE, "the workload needs more than the " + std::to_string(ctx->arena_cap) +
+                                     " bytes of static scratch of stab_sample_noalloc");
+    *out = ctx->arena + at;
+    ctx->arena_used = at + bytes;
+    return STAB_OK;
+}
+
+int ensure(DevBuf& b, size_t bytes);
+
+int ensure(stab_ctx* ctx, DevBuf& b, size_t bytes)
+{
+    if (!ctx->arena) return ensure(b, bytes);
+    if (bytes <= b.cap) return STAB_OK;
+    // an outgrown piece of the scratch stays unused until the call ends
+    void* p = nullptr;
+    const int rc = arena_take(ctx, bytes, &p);
+    if (rc) return rc;
+    b.p = p;
+    b.cap = bytes;
+    b.arena = true;
+    return STAB_OK;
+}
+
+// Grow b (device memory of its own) to at least `bytes`.
 int ensure(DevBuf& b, size_t bytes)
 {
     if (bytes <= b.cap) return STAB_OK;
@@ -463,8 +499,14 @@ int stab_tableau_bytes(int32_t n, int32_t shots, int32_t mode, uint64_t* bytes_o
     return STAB_OK;
 }
 
-int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot,
-                void* dev_buf, uint64_t buf_bytes, void* hip_stream, stab_ctx** out)
+}  // extern "C"
+
+namespace {
+
+// stab_create; with arena != NULL the context's own device memory (error flag, counters and,
+// later, every execution buffer) is carved from arena[0, arena_cap) and no event is created.
+int create_ctx(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot, void* dev_buf,
+               uint64_t buf_bytes, void* hip_stream, char* arena, size_t arena_cap, stab_ctx** out)
 {
     if (!out) return fail(STAB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -481,6 +523,8 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     ctx->seed = seed;
     ctx->first_shot = first_shot;
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->arena = arena;
+    ctx->arena_cap = arena ? arena_cap : 0;
     const Layout L = layout_of(ctx->g);
     char* base = (char*)dev_buf;
     ctx->tab = (uint64_t*)(base + L.tab);
@@ -508,14 +552,23 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     (void)hipFuncSetAttribute((const void*)k_replay<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipGetLastError();
 
-    bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
-              hipMalloc((void**)&ctx->d_counters, kNumCounters * kCounterStripes * sizeof(unsigned long long)) == hipSuccess &&
-              hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
-    if (!ok) {
-        stab_destroy(ctx);
-        return fail(STAB_ENOMEM, "device allocation failed");
+    const size_t counter_bytes = kNumCounters * kCounterStripes * sizeof(unsigned long long);
+    if (arena) {
+        if ((rc = arena_take(ctx, sizeof(int), (void**)&ctx->d_err)) ||
+            (rc = arena_take(ctx, counter_bytes, (void**)&ctx->d_counters))) {
+            delete ctx;
+            return rc;
+        }
+    } else {
+        bool ok = hipMalloc((void**)&ctx->d_err, sizeof(int)) == hipSuccess &&
+                  hipMalloc((void**)&ctx->d_counters, counter_bytes) == hipSuccess &&
+                  hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
+        if (!ok) {
+            stab_destroy(ctx);
+            return fail(STAB_ENOMEM, "device allocation failed");
+        }
     }
-    if (hipMemsetAsync(ctx->d_counters, 0, kNumCounters * kCounterStripes * sizeof(unsigned long long), ctx->stream) != hipSuccess) {
+    if (hipMemsetAsync(ctx->d_counters, 0, counter_bytes, ctx->stream) != hipSuccess) {
         stab_destroy(ctx);
         return fail(STAB_EDEVICE, "memset failed");
     }
@@ -529,6 +582,16 @@ int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t 
     return STAB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot,
+                void* dev_buf, uint64_t buf_bytes, void* hip_stream, stab_ctx** out)
+{
+    return create_ctx(n, shots, mode, seed, first_shot, dev_buf, buf_bytes, hip_stream, nullptr, 0, out);
+}
+
 void stab_destroy(stab_ctx* ctx)
 {
     if (!ctx) return;
@@ -538,12 +601,14 @@ void stab_destroy(stab_ctx* ctx)
                       &ctx->plog_row, &ctx->plog_rs, &ctx->plog_rd, &ctx->ran, &ctx->plist,
                       &ctx->pcnt, &ctx->povf};
     for (DevBuf* b : bufs)
-        if (b->p) (void)hipFree(b->p);
+        if (b->p && !b->arena) (void)hipFree(b->p);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->d_err) (void)hipFree(ctx->d_err);
-    if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+    if (!ctx->arena) {
+        if (ctx->d_err) (void)hipFree(ctx->d_err);
+        if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+    }
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -564,6 +629,84 @@ int stab_reset(stab_ctx* ctx, uint64_t seed, uint64_t first_shot)
     return STAB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Byte offsets of the device arrays of a program inside its uploaded blob.
+struct ProgramBlob {
+    std::vector<char> bytes;
+    size_t items, gates, noise, ntg, us, eb, ec, nseg, mran, mtq;
+};
+
+// Host half of stab_compile: validate and split the stream for geometry g into P's plan and
+// the blob of device arrays.  Touches no device.
+int compile_host(const Geom& g, const stab_instr* instrs, int32_t ninstr, const int32_t* targets,
+                 int64_t ntargets, stab_program& P, ProgramBlob& B)
+{
+    std::vector<int4> items;
+    std::vector<uint2> gates;
+    std::vector<NoiseDesc> noise;
+    std::vector<int> noise_tg, unit_start, ev_base, mtq;
+    int rc = compile_stream(g, instrs, ninstr, targets, ntargets, P, items, gates, noise, noise_tg,
+                            unit_start, ev_base, mtq);
+    if (rc) return rc;
+    P.n = g.n;
+    P.B = g.B;
+    std::vector<char>& blob = B.bytes;
+    B.items = put(blob, items);
+    B.gates = put(blob, gates);
+    B.noise = put(blob, noise);
+    B.ntg = put(blob, noise_tg);
+    B.us = put(blob, unit_start);
+    B.eb = put(blob, ev_base);
+    B.ec = put(blob, std::vector<int>(std::max<int>(P.nnoise, 1), 0));
+    std::vector<long long> nseg(std::max<size_t>(noise.size(), 1), 0);
+    for (const SegPlan& sp : P.segs)
+        for (int i = 0; i < sp.noise_count; ++i) nseg[sp.noise_begin + i] = sp.ev_global;
+    B.nseg = put(blob, nseg);
+    B.mran = put(blob, std::vector<int>(std::max<size_t>(P.meas.size(), 1), 0));
+    B.mtq = put(blob, mtq);
+    return STAB_OK;
+}
+
+// Device half: the blob goes to device memory (the context's static scratch when it has one).
+// On failure P is left without device memory.
+int upload_program(stab_ctx* ctx, stab_program& P, const ProgramBlob& B)
+{
+    const std::vector<char>& blob = B.bytes;
+    if (ctx->arena) {
+        const int rc = arena_take(ctx, blob.size(), &P.dev);
+        if (rc) return rc;
+        P.dev_arena = true;
+    } else if (hipMalloc(&P.dev, blob.size()) != hipSuccess) {
+        P.dev = nullptr;
+        return fail(STAB_ENOMEM, "device allocation failed");
+    }
+    if (hipMemcpy(P.dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        if (!P.dev_arena) (void)hipFree(P.dev);
+        P.dev = nullptr;
+        ctx->poisoned = true;
+        return fail(STAB_EDEVICE, "program upload failed");
+    }
+    char* d = (char*)P.dev;
+    P.d_items = (int4*)(d + B.items);
+    P.d_gates = (uint2*)(d + B.gates);
+    P.d_noise = (NoiseDesc*)(d + B.noise);
+    P.d_noise_tg = (int*)(d + B.ntg);
+    P.d_unit_start = (int*)(d + B.us);
+    P.d_ev_base = (int*)(d + B.eb);
+    P.d_ev_count = (int*)(d + B.ec);
+    P.d_noise_seg = (long long*)(d + B.nseg);
+    P.d_mran = (int*)(d + B.mran);
+    P.d_mtq = (int*)(d + B.mtq);
+    return STAB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const int32_t* targets,
                  int64_t ntargets, stab_program** out)
 {
@@ -573,49 +716,13 @@ int stab_compile(stab_ctx* ctx, const stab_instr* instrs, int32_t ninstr, const 
     stab_program* P = new stab_program();
     static std::atomic<uint64_t> program_serial{0};
     P->serial = ++program_serial;
-    std::vector<int4> items;
-    std::vector<uint2> gates;
-    std::vector<NoiseDesc> noise;
-    std::vector<int> noise_tg, unit_start, ev_base, mtq;
-    int rc = compile_stream(ctx->g, instrs, ninstr, targets, ntargets, *P, items, gates, noise,
-                            noise_tg, unit_start, ev_base, mtq);
+    ProgramBlob B;
+    int rc = compile_host(ctx->g, instrs, ninstr, targets, ntargets, *P, B);
+    if (rc == STAB_OK) rc = upload_program(ctx, *P, B);
     if (rc) {
         delete P;
         return rc;
     }
-    P->n = ctx->g.n;
-    P->B = ctx->g.B;
-    std::vector<char> blob;
-    const size_t o_items = put(blob, items), o_gates = put(blob, gates), o_noise = put(blob, noise);
-    const size_t o_ntg = put(blob, noise_tg), o_us = put(blob, unit_start), o_eb = put(blob, ev_base);
-    const size_t o_ec = put(blob, std::vector<int>(std::max<int>(P->nnoise, 1), 0));
-    std::vector<long long> nseg(std::max<size_t>(noise.size(), 1), 0);
-    for (const SegPlan& sp : P->segs)
-        for (int i = 0; i < sp.noise_count; ++i) nseg[sp.noise_begin + i] = sp.ev_global;
-    const size_t o_nseg = put(blob, nseg);
-    const size_t o_mran = put(blob, std::vector<int>(std::max<size_t>(P->meas.size(), 1), 0));
-    const size_t o_mtq = put(blob, mtq);
-    if (hipMalloc(&P->dev, blob.size()) != hipSuccess) {
-        delete P;
-        return fail(STAB_ENOMEM, "device allocation failed");
-    }
-    if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(P->dev);
-        delete P;
-        ctx->poisoned = true;
-        return fail(STAB_EDEVICE, "program upload failed");
-    }
-    char* d = (char*)P->dev;
-    P->d_items = (int4*)(d + o_items);
-    P->d_gates = (uint2*)(d + o_gates);
-    P->d_noise = (NoiseDesc*)(d + o_noise);
-    P->d_noise_tg = (int*)(d + o_ntg);
-    P->d_unit_start = (int*)(d + o_us);
-    P->d_ev_base = (int*)(d + o_eb);
-    P->d_ev_count = (int*)(d + o_ec);
-    P->d_noise_seg = (long long*)(d + o_nseg);
-    P->d_mran = (int*)(d + o_mran);
-    P->d_mtq = (int*)(d + o_mtq);
     *out = P;
     return STAB_OK;
 }
@@ -649,9 +756,34 @@ int stab_plan_describe(int32_t n, int32_t shots, int32_t mode, const stab_instr*
 void stab_program_destroy(stab_program* prog)
 {
     if (!prog) return;
-    if (prog->dev) (void)hipFree(prog->dev);   // implicitly waits for work that uses it
+    if (prog->dev && !prog->dev_arena) (void)hipFree(prog->dev);   // implicitly waits for work that uses it
     delete prog;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Bytes of the device buffers one execution of P needs, in the order xcol, zcol, cls, pend,
+// obuf, events, record, packed, plog_p, plog_rs, plog_row, plog_rd, ran, plist, pcnt, povf.
+constexpr int kExecBufs = 16;
+void exec_sizes(const Geom& g, const stab_program& P, bool draw_all, size_t* sizes)
+{
+    const size_t K = (size_t)std::max(P.Kmax, 1);
+    const size_t nrec = (size_t)std::max<long long>(P.nrec, 1);
+    const size_t v[kExecBufs] = {(size_t)g.S * g.NB * K * 8, (size_t)g.S * g.NB * K * 8, (size_t)g.S * K * 4,
+                                 (size_t)g.S * K * 4, (size_t)g.B * K,
+                                 (size_t)std::max<long long>(draw_all ? P.ev_total : P.ev_cap_max, 1) * 8,
+                                 (size_t)g.B * nrec, (size_t)g.B * ((nrec + 7) / 8), (size_t)g.S * K * 4,
+                                 (size_t)g.S * K * 4, (size_t)g.S * K * g.RS * 8,
+                                 (size_t)g.S * K * ((g.bpc + 63) / 64) * 8, 4, (size_t)g.S * K * kPListCap * 2,
+                                 (size_t)g.S * K * 4, (size_t)g.S * 4};
+    for (int i = 0; i < kExecBufs; ++i) sizes[i] = v[i];
+}
+
+}  // namespace
+
+extern "C" {
 
 int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elapsed_ms)
 {
@@ -663,20 +795,27 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     const size_t K = (size_t)std::max(P->Kmax, 1);
     // the noise of every segment is drawn by one launch at the start when its event slots fit
     // (the draws depend on the RNG key only, not on the tableau); else segment by segment
-    const bool draw_all = P->nnoise > 0 && P->nnoise <= 65535 && P->ev_total <= kDrawAllEvents;
+    bool draw_all = P->nnoise > 0 && P->nnoise <= 65535 && P->ev_total <= kDrawAllEvents;
     int rc;
-    if ((rc = ensure(ctx->xcol, (size_t)g.S * g.NB * K * 8)) || (rc = ensure(ctx->zcol, (size_t)g.S * g.NB * K * 8)) ||
-        (rc = ensure(ctx->cls, (size_t)g.S * K * 4)) || (rc = ensure(ctx->pend, (size_t)g.S * K * 4)) ||
-        (rc = ensure(ctx->obuf, (size_t)g.B * K)) ||
-        (rc = ensure(ctx->events, (size_t)std::max<long long>(draw_all ? P->ev_total : P->ev_cap_max, 1) * 8)) ||
-        (rc = ensure(ctx->record, (size_t)g.B * std::max<long long>(P->nrec, 1))) ||
-        (rc = ensure(ctx->packed, (size_t)g.B * ((std::max<long long>(P->nrec, 1) + 7) / 8))) ||
-        (rc = ensure(ctx->plog_p, (size_t)g.S * K * 4)) || (rc = ensure(ctx->plog_rs, (size_t)g.S * K * 4)) ||
-        (rc = ensure(ctx->plog_row, (size_t)g.S * K * g.RS * 8)) ||
-        (rc = ensure(ctx->plog_rd, (size_t)g.S * K * ((g.bpc + 63) / 64) * 8)) || (rc = ensure(ctx->ran, 4)) ||
-        (rc = ensure(ctx->plist, (size_t)g.S * K * kPListCap * 2)) || (rc = ensure(ctx->pcnt, (size_t)g.S * K * 4)) ||
-        (rc = ensure(ctx->povf, (size_t)g.S * 4)))
-        return rc;
+    {
+        DevBuf* bufs[kExecBufs] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->pend, &ctx->obuf, &ctx->events,
+                                   &ctx->record, &ctx->packed, &ctx->plog_p, &ctx->plog_rs, &ctx->plog_row,
+                                   &ctx->plog_rd, &ctx->ran, &ctx->plist, &ctx->pcnt, &ctx->povf};
+        size_t sizes[kExecBufs];
+        exec_sizes(g, *P, draw_all, sizes);
+        if (ctx->arena && draw_all) {
+            // in the static scratch the whole program's noise is drawn at once only if it fits
+            size_t at = ctx->arena_used;
+            for (int i = 0; i < kExecBufs; ++i)
+                if (bufs[i]->cap < sizes[i]) at = align256(at) + std::max<size_t>(align256(sizes[i]), 256);
+            if (at > ctx->arena_cap) {
+                draw_all = false;
+                exec_sizes(g, *P, draw_all, sizes);
+            }
+        }
+        for (int i = 0; i < kExecBufs; ++i)
+            if ((rc = ensure(ctx, *bufs[i], sizes[i]))) return rc;
+    }
     uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
     uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
     int* cls = (int*)ctx->cls.p;
@@ -820,7 +959,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         return STAB_OK;
     };
 
-    HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (ctx->ev0) HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     if (ctx->graph_on && !ctx->timing && !learn_mran) {
         // the launches depend on the program, the RNG key, the instruction counter and the
         // buffers: replay the captured graph while they are unchanged, capture again otherwise
@@ -862,7 +1001,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         host.resize((size_t)total);
         HIP_CHECK(ctx, hipMemcpyAsync(host.data(), ctx->packed.p, (size_t)total, hipMemcpyDeviceToHost, ctx->stream));
     }
-    HIP_CHECK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    if (ctx->ev1) HIP_CHECK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     int err = 0;
     HIP_CHECK(ctx, hipMemcpy(&err, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
@@ -870,7 +1009,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
         ctx->poisoned = true;
         return fail(STAB_EINTERNAL, "device consistency check failed (code " + std::to_string(err) + ")");
     }
-    if (elapsed_ms) HIP_CHECK(ctx, hipEventElapsedTime(elapsed_ms, ctx->ev0, ctx->ev1));
+    if (elapsed_ms && ctx->ev0) HIP_CHECK(ctx, hipEventElapsedTime(elapsed_ms, ctx->ev0, ctx->ev1));
     if (ctx->timing && (rc = tcollect(ctx))) return rc;
     if (learn_mran) {
         P->mran.assign(P->meas.size(), 1);
@@ -1002,6 +1141,90 @@ int stab_sample(const stab_instr* instrs, int32_t ninstr, const int32_t* targets
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// stab_sample without device allocation.  Every buffer the library would allocate (error flag,
+// counters, the uploaded program, target columns, noise events, pivot log, records) is carved
+// from `scratch`, a static device array each GPU holds for the life of the process.  Its name
+// is a host-side stand-in in host code: the device address of each GPU's copy is looked up
+// once per device with hipGetSymbolAddress and only that address is handed to kernels and
+// copies.  Calls on one GPU share the array, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STAB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device ordinal -> address of its copy of scratch
+
+// Address of the current device's copy of scratch (looked up on the first call per device).
+int scratch_address(char** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(STAB_EDEVICE, "no HIP device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return STAB_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(STAB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)ptr;
+    *out = (char*)ptr;
+    return STAB_OK;
+}
+
+// Scratch bytes stab_sample_noalloc carves for this program (noise drawn segment by segment),
+// in the order the context takes them.
+size_t noalloc_bytes(const Geom& g, const stab_program& P, size_t blob_bytes)
+{
+    auto piece = [](size_t b) { return std::max<size_t>(align256(b), 256); };
+    size_t total = piece(sizeof(int)) + piece(kNumCounters * kCounterStripes * sizeof(unsigned long long)) +
+                   piece(blob_bytes);
+    size_t sizes[kExecBufs];
+    exec_sizes(g, P, false, sizes);
+    for (size_t b : sizes) total += piece(b);
+    return total;
+}
+
+}  // namespace
+
+extern "C" int stab_sample_noalloc(const stab_instr* instrs, int32_t ninstr, const int32_t* targets,
+                                   int64_t ntargets, int32_t n, int32_t shots, int32_t mode, uint64_t seed,
+                                   void* dev_buf, uint64_t buf_bytes, void* hip_stream, uint8_t* out_bits)
+{
+    // everything that can be checked on the host is checked before the device is touched
+    uint64_t need = 0;
+    int rc = stab_tableau_bytes(n, shots, mode, &need);
+    if (rc) return rc;
+    if (!dev_buf) return fail(STAB_EINVAL, "dev_buf is NULL");
+    if (((uintptr_t)dev_buf & 255u) != 0) return fail(STAB_EINVAL, "dev_buf must be 256-byte aligned");
+    if (buf_bytes < need) return fail(STAB_ENOMEM, "dev_buf smaller than stab_tableau_bytes()");
+    const Geom g = make_geom(n, shots, mode);
+    stab_program P;
+    ProgramBlob B;
+    if ((rc = compile_host(g, instrs, ninstr, targets, ntargets, P, B))) return rc;
+    if (P.nrec > 0 && !out_bits) return fail(STAB_EINVAL, "out_bits is NULL but the stream records outcomes");
+    const size_t want = noalloc_bytes(g, P, B.bytes.size());
+    if (want > (size_t)STAB_NOALLOC_SCRATCH_BYTES)
+        return fail(STAB_ERANGE, "stab_sample_noalloc: this workload needs " + std::to_string(want) +
+                                     " bytes of scratch; the static scratch holds " +
+                                     std::to_string((size_t)STAB_NOALLOC_SCRATCH_BYTES) + " (use stab_sample)");
+    char* arena = nullptr;
+    if ((rc = scratch_address(&arena))) return rc;
+    stab_ctx* ctx = nullptr;
+    if ((rc = create_ctx(n, shots, mode, seed, 0, dev_buf, buf_bytes, hip_stream, arena,
+                         (size_t)STAB_NOALLOC_SCRATCH_BYTES, &ctx)))
+        return rc;
+    rc = upload_program(ctx, P, B);
+    if (rc == STAB_OK) rc = stab_execute(ctx, &P, out_bits, nullptr);
+    P.dev = nullptr;   // (in the scratch: nothing to free)
+    stab_destroy(ctx);
+    return rc;
+}
 
 // Pauli-string commutation (Sec. 3.2)
 extern "C" int stab_commute(const uint64_t* A, int32_t na, const uint64_t* B, int32_t nb, int32_t n,

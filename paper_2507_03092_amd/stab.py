@@ -23,7 +23,7 @@ _MODES = {"shared": MODE_SHARED, "full": MODE_FULL, MODE_SHARED: MODE_SHARED, MO
 # every function declared in include/stab.h
 EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy", "stab_run",
            "stab_apply_layer", "stab_measure", "stab_get_tableau", "stab_compile", "stab_execute",
-           "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample",
+           "stab_program_records", "stab_program_destroy", "stab_reset", "stab_sample", "stab_sample_noalloc",
            "stab_get_counters", "stab_set_timing", "stab_set_graph", "stab_get_kernel_times", "stab_plan_describe",
            "stab_batch_bytes", "stab_batch_create", "stab_batch_destroy", "stab_batch_reset",
            "stab_batch_compile", "stab_batch_program_records", "stab_batch_program_destroy",
@@ -74,6 +74,7 @@ def lib():
         "stab_program_destroy": (None, [P]),
         "stab_reset": (C.c_int, [P, U64, U64]),
         "stab_sample": (C.c_int, [P, I32, P, I64, I32, I32, I32, U64, P, U64, P, P, C.POINTER(C.c_float)]),
+        "stab_sample_noalloc": (C.c_int, [P, I32, P, I64, I32, I32, I32, U64, P, U64, P, P]),
         "stab_get_counters": (C.c_int, [P, P, I32]),
         "stab_set_timing": (C.c_int, [P, I32]),
         "stab_set_graph": (C.c_int, [P, I32]),
@@ -274,6 +275,28 @@ def sample(circ: _circ.Circuit, shots: int, seed: int, mode="shared", device: st
                              seed, C.c_void_p(buf.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream),
                              _ptr(out), C.byref(ms)))
     return unpack_record(out[: shots * ((nrec + 7) // 8)], shots, nrec), ms.value
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # STAB_NOALLOC_SCRATCH_BYTES
+
+
+def sample_noalloc(circ: _circ.Circuit, shots: int, seed: int, mode="shared", device: str = "cuda:0",
+                   buf=None):
+    """stab_sample_noalloc: the record [shots, nrec] uint8.  buf (optional): a caller-owned
+    torch uint8 device tensor of at least tableau_bytes() bytes for the tableaux."""
+    import torch
+
+    instr, tg = circ.arrays()
+    nrec = circ.num_measurements()
+    nbytes = tableau_bytes(circ.n, shots, mode)
+    if buf is None:
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    out = np.zeros(max(shots * ((nrec + 7) // 8), 1), dtype=np.uint8)
+    _check(lib().stab_sample_noalloc(_ptr(instr), len(instr), _ptr(tg), len(tg), circ.n, shots, _MODES[mode],
+                                     seed, C.c_void_p(buf.data_ptr()), buf.numel(), C.c_void_p(stream.cuda_stream),
+                                     _ptr(out)))
+    return unpack_record(out[: shots * ((nrec + 7) // 8)], shots, nrec)
 
 
 # ------------------------------------------------------------------ multi-circuit batches ---

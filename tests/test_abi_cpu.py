@@ -93,6 +93,38 @@ def test_argument_errors_without_gpu(L):
     assert L.stab_program_records(None) == -1
 
 
+def test_sample_noalloc_host_checks(L):
+    """stab_sample_noalloc checks its arguments and its scratch need before touching a device."""
+    circ = Cc.Circuit(4)
+    circ.append(Cc.H, [0])
+    circ.append(Cc.CX, [0, 1])
+    circ.append(Cc.M, [0, 1, 2, 3])
+    instr, tg = circ.arrays()
+    out = np.zeros(16, dtype=np.uint8)
+    big = C.c_void_p(0x100000)
+
+    def call(c, shots, buf, nbytes, instr=instr, tg=tg):
+        return L.stab_sample_noalloc(stab._ptr(instr), len(instr), stab._ptr(tg), len(tg), c.n, shots, 0, 1,
+                                     buf, nbytes, None, stab._ptr(out))
+
+    assert call(circ, 1, None, 1 << 20) == stab.EINVAL
+    assert call(circ, 1, C.c_void_p(0x1001), 1 << 20) == stab.EINVAL
+    assert call(circ, 1, big, 16) == stab.ENOMEM
+    bt = tg.copy()
+    bt[-1] = 4
+    assert call(circ, 1, big, 1 << 20, instr, bt) == stab.EINVAL
+    assert b"out of range" in L.stab_last_error()
+    # one Z measurement of all 10240 qubits needs two 26 MB target-column arrays and a 26 MB
+    # pivot log: more than the static scratch holds
+    wide = Cc.Circuit(stab.max_qubits())
+    wide.append(Cc.M, range(wide.n))
+    wi, wt = wide.arrays()
+    assert stab.NOALLOC_SCRATCH_BYTES == 64 << 20
+    assert call(wide, 1, big, 1 << 40, wi, wt) == stab.ERANGE
+    msg = L.stab_last_error().decode()
+    assert "stab_sample_noalloc" in msg and str(stab.NOALLOC_SCRATCH_BYTES) in msg
+
+
 def test_record_unpacking_layout():
     # shot b's bits start at byte b*ceil(nrec/8), LSB first
     rec = np.array([[1, 0, 1, 1, 0, 0, 0, 0, 1], [0, 1, 0, 0, 0, 0, 0, 1, 1]], dtype=np.uint8)
