@@ -83,7 +83,8 @@ typedef struct stab_ctx stab_ctx;
 int32_t stab_max_qubits(void);
 
 /* Bytes of device memory a context needs in dev_buf for n qubits and `shots` shots in the
- * given mode.  Writes *bytes_out.  Errors: STAB_EINVAL (n < 1, shots < 1, bad mode),
+ * given mode: the 2n-row x|z tableau plus signs of Sec. 2.3 (4n^2 + 2n bits per copy, rows
+ * padded to 64-bit words), one copy per shot in STAB_MODE_FULL.  Writes *bytes_out.  Errors: STAB_EINVAL (n < 1, shots < 1, bad mode),
  * STAB_ERANGE (n > stab_max_qubits()). */
 int stab_tableau_bytes(int32_t n, int32_t shots, int32_t mode, uint64_t *bytes_out);
 
@@ -95,7 +96,8 @@ int stab_tableau_bytes(int32_t n, int32_t shots, int32_t mode, uint64_t *bytes_o
 int stab_create(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot,
                 void *dev_buf, uint64_t buf_bytes, void *hip_stream, stab_ctx **out);
 
-/* Release the context's own scratch memory.  Never frees dev_buf.  NULL is ignored. */
+/* Release the context's own scratch memory (the column, pivot-log and record buffers the
+ * measurement steps of Sec. 2.4 use).  Never frees dev_buf.  NULL is ignored. */
 void stab_destroy(stab_ctx *ctx);
 
 /* Run an op stream on every shot of the context (the paper's sim(circuit), Sec. 3.1.4, and
@@ -118,8 +120,10 @@ int stab_apply_layer(stab_ctx *ctx, const stab_instr *instrs, int32_t ninstr,
 int stab_measure(stab_ctx *ctx, uint32_t kind, const int32_t *qubits, int32_t k,
                  uint8_t *out_bits);
 
-/* Copy one shot's tableau to the host in row-major bytes: x[2n][n], z[2n][n] (0/1 per byte),
- * r[2n]; rows 0..n-1 destabilizers, n..2n-1 stabilizers.  Any pointer may be NULL. */
+/* Copy one shot's tableau to the host in row-major bytes, in the layout of Sec. 2.3 (the
+ * tableau of Fig. 2's state): x[2n][n], z[2n][n] (0/1 per byte), r[2n]; rows 0..n-1
+ * destabilizers, n..2n-1 stabilizers.  Any pointer may be NULL.  Errors: STAB_EINVAL (NULL
+ * context, shot out of range), STAB_EDEVICE. */
 int stab_get_tableau(stab_ctx *ctx, int32_t shot, uint8_t *x, uint8_t *z, uint8_t *r);
 
 /* A compiled op stream: validated, split into gate/noise segments and measurement layers,
@@ -161,9 +165,11 @@ int stab_plan_describe(int32_t n, int32_t shots, int32_t mode, const stab_instr 
                        int32_t ninstr, const int32_t *targets, int64_t ntargets, int64_t *out,
                        int32_t nout);
 
-/* One-call sampler: create a context on dev_buf, run the stream, write the packed record
- * (shots * ceil(nrec/8) bytes) to out_bits, destroy the context.  elapsed_ms (may be NULL)
- * receives the device time from the first kernel to the record on the host. */
+/* One-call sampler: the paper's sim(circuit) of Sec. 3.1 run for `shots` shots (parallel
+ * sampling, named as future work in Sec. 6): create a context on dev_buf, run the stream,
+ * write the packed record (shots * ceil(nrec/8) bytes, the stab_run layout) to out_bits,
+ * destroy the context.  elapsed_ms (may be NULL) receives the device time from the first
+ * kernel to the record on the host.  Errors: as stab_create and stab_run. */
 int stab_sample(const stab_instr *instrs, int32_t ninstr, const int32_t *targets,
                 int64_t ntargets, int32_t n, int32_t shots, int32_t mode, uint64_t seed,
                 void *dev_buf, uint64_t buf_bytes, void *hip_stream, uint8_t *out_bits,
@@ -391,7 +397,8 @@ int stab_server_result(stab_server *server, int64_t id, uint8_t *out_bits);
  * in use, [4] arena bytes, [5] steps run, [6] requests finished.  nout <= 7. */
 int stab_server_stats(const stab_server *server, int64_t *out, int32_t nout);
 
-/* Message of the last error on this thread ("" if none). */
+/* Message of the last error on this thread ("" if none).  The paper defines no error
+ * reporting; this is the library's own convention for every call above. */
 const char *stab_last_error(void);
 
 #ifdef __cplusplus
