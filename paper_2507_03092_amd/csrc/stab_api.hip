@@ -54,9 +54,18 @@ int max_qubits_for_lds(int lds_bytes)
     return std::min(std::min(wc, 64 * kMaxWordsPerLane), 32 * kMaxBandsPerLane) * 64;
 }
 
+// STAB_REVERSE_BLOCKS set (and not "0") in the environment: kernels take their workgroups in
+// reverse order, a check that results do not depend on the order in which work runs.
+int reverse_blocks()
+{
+    const char* v = std::getenv("STAB_REVERSE_BLOCKS");
+    return (v && v[0] && !(v[0] == '0' && v[1] == 0)) ? 1 : 0;
+}
+
 Geom make_geom(int n, int shots, int mode)
 {
     Geom g{};
+    g.rev = reverse_blocks();
     g.n = n;
     g.Wc = (n + 63) / 64;
     g.Wr = g.Wc;
@@ -863,7 +872,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
             const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock), (unsigned)P->nnoise);
             TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
                 P->d_noise, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events, P->d_noise_seg,
-                P->d_ev_base, P->d_ev_count, ctx->d_counters)));
+                P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
         }
         for (const auto& st : P->steps) {
             if (st.first == 0) {
@@ -874,7 +883,7 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
                                     (unsigned)sp.noise_count);
                     TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
                         P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                        nullptr, P->d_ev_base, P->d_ev_count, ctx->d_counters)));
+                        nullptr, P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
                 }
                 if (sp.item_count > 0 || sp.meas >= 0) {
                     SegArgs a{};

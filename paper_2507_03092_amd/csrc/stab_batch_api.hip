@@ -362,6 +362,7 @@ int stab_batch_compile(stab_batch* b, const stab_instr* instrs, const int64_t* i
     std::vector<int> order(C);
     for (int c = 0; c < C; ++c) order[c] = c;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    if (reverse_blocks()) std::reverse(order.begin(), order.end());
     P->lds_bytes = batch_lds_words(maxwc) * 8;
     P->nw = maxwc <= 64 ? 1 : 2;
     // shape fingerprint: sizes and per-circuit step, gate and measured-target counts

@@ -21,7 +21,14 @@ struct Geom {
     int S;    // tableau copies
     int B;    // shots
     int bpc;  // shots per copy (B / S)
+    int rev;  // 1: kernels take their blocks in reverse order (a determinism check)
 };
+
+// Block index along x (y) in the order the kernels take blocks: reversed when g.rev is set, so a
+// run with the flag changes which work each dispatched workgroup does and the order in which the
+// work reaches the device; the results must not change.
+__device__ __forceinline__ int blk_x(const Geom& g) { return g.rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x; }
+__device__ __forceinline__ int blk_y(const Geom& g) { return g.rev ? (int)gridDim.y - 1 - (int)blockIdx.y : (int)blockIdx.y; }
 
 // One noise instruction of a segment.
 struct NoiseDesc {

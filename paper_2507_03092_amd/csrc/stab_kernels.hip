@@ -167,7 +167,7 @@ __global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict_
 {
     const size_t rows = (size_t)g.S * 2 * g.NR;
     const size_t total = rows * g.RS;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+    for (size_t idx = blk_x(g) * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const size_t row = idx / g.RS;
         const int c = (int)(idx - row * g.RS);
@@ -182,7 +182,7 @@ __global__ void k_init(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict_
         tab[idx] = v;
     }
     const size_t nrs = (size_t)g.S * g.NB, nrd = (size_t)g.B * g.NB;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nrs + nrd;
+    for (size_t idx = blk_x(g) * (size_t)blockDim.x + threadIdx.x; idx < nrs + nrd;
          idx += (size_t)gridDim.x * blockDim.x) {
         if (idx < nrs) rs[idx] = 0;
         else rd[idx - nrs] = 0;
@@ -202,23 +202,26 @@ constexpr int kNoiseLdsEvents = 2048;
 // event slots (8 bytes each) up to which a program's noise is drawn in one launch
 constexpr long long kDrawAllEvents = 1ll << 28;
 
-// Instruction blockIdx.y of nd[].  seg_base (may be NULL): per instruction, the first event
-// slot of its segment, when every segment's events are drawn by one launch.
+// Instruction y of nd[] (y = blockIdx.y, or reversed with rev).  seg_base (may be NULL): per
+// instruction, the first event slot of its segment, when every segment's events are drawn by
+// one launch.  The order of a bucket's events depends on block timing; applying them commutes.
 __global__ void __launch_bounds__(1024)
 k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int B, uint64_t seed,
              uint64_t first_shot, uint64_t instr_base, uint2* __restrict__ events,
              const long long* __restrict__ seg_base, const int* __restrict__ ev_base, int* __restrict__ ev_count,
-             unsigned long long* __restrict__ counters)
+             unsigned long long* __restrict__ counters, int rev)
 {
     __shared__ uint2 sev[kNoiseLdsEvents];
     __shared__ int s_n, s_base;
-    const NoiseDesc d = nd[blockIdx.y];
+    const int bx = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    const int by = rev ? (int)gridDim.y - 1 - (int)blockIdx.y : (int)blockIdx.y;
+    const NoiseDesc d = nd[by];
     const long long total = (long long)d.units * B;
-    const long long start = (long long)blockIdx.x * kNoiseUnitsPerBlock;
+    const long long start = (long long)bx * kNoiseUnitsPerBlock;
     if (start >= total) return;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    uint2* gdst = events + (seg_base ? seg_base[blockIdx.y] : 0ll) + ev_base[d.bucket];
+    uint2* gdst = events + (seg_base ? seg_base[by] : 0ll) + ev_base[d.bucket];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const long long idx = start + threadIdx.x + (long long)j * kNoiseThreads;
@@ -359,7 +362,8 @@ __device__ __forceinline__ uint32_t transpose32(uint32_t v, int lane)
 }
 
 // Transpose every 32x32 tile (column c of the 64 staged lanes) in place, four tiles per wave in
-// flight so that their LDS reads overlap.
+// flight so that their LDS reads overlap.  A wave's pair of tiles that is all zero (most of a
+// sparse tableau, such as a surface code's) is its own transpose and is left as it is.
 __device__ __forceinline__ void transpose_tiles(uint32_t* T, int RSP, int RS, int lane, int wave, int nwaves)
 {
     int c = wave;
@@ -368,11 +372,17 @@ __device__ __forceinline__ void transpose_tiles(uint32_t* T, int RSP, int RS, in
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = T[lane * RSP + c + u * nwaves];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = transpose32(v[u], lane);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) T[lane * RSP + c + u * nwaves] = v[u];
+        for (int u = 0; u < 4; ++u) {
+            if (__ballot(v[u] != 0u)) {
+                v[u] = transpose32(v[u], lane);
+                T[lane * RSP + c + u * nwaves] = v[u];
+            }
+        }
     }
-    for (; c < RS; c += nwaves) T[lane * RSP + c] = transpose32(T[lane * RSP + c], lane);
+    for (; c < RS; c += nwaves) {
+        const uint32_t v = T[lane * RSP + c];
+        if (__ballot(v != 0u)) T[lane * RSP + c] = transpose32(v, lane);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -389,9 +399,9 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 {
     if (a.gate && *a.gate == 0) return;   // an extraction pass with nothing to refresh
     extern __shared__ uint32_t lds32[];
-    const int hb = blockIdx.x;                   // half-band: band = hb >> 1, half = hb & 1
+    const int hb = blk_x(g);                     // half-band: band = hb >> 1, half = hb & 1
     const int band = hb >> 1, half = hb & 1;
-    const int s = blockIdx.y;
+    const int s = blk_y(g);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int RS = g.RS, RSP = g.RS + 1, Wc = g.Wc;
@@ -538,11 +548,17 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
 {
     extern __shared__ uint64_t dsm[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int k0 = blockIdx.x * kDetTargets, k = k0 + wave;
-    const int s = blockIdx.y;
+    const int k0 = blk_x(g) * kDetTargets, k = k0 + wave;
+    const int s = blk_y(g);
     const int NB = g.NB, nrdw = (g.bpc + 63) >> 6;
     uint64_t* colw = dsm;                                          // [kDetTargets][NB] columns
     uint64_t* parw = dsm + (size_t)kDetTargets * NB + (size_t)wave * nrdw;   // shot parity bits
+    // the block's work counters, flushed with one atomic each at the end
+    __shared__ unsigned int s_det, s_rows;
+    if (threadIdx.x == 0) {
+        s_det = 0;
+        s_rows = 0;
+    }
     if (pass == 0) {
         // the next launch (the random chain) sets this when a random target runs
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran = 0;
@@ -571,123 +587,131 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         }
     }
     __syncthreads();
-    if (k >= K) return;
-    if (pass == 1 && cls[s * K + k] != -2) return;
-    const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
-    const uint64_t* rsc = rs + (size_t)s * NB;
-    // the column: destabilizer words cd, stabilizer words cs (band lane + 64 u of each half)
-    uint64_t cd[kMaxStabBandsPerLane], cs[kMaxStabBandsPerLane];
-#pragma unroll
-    for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
-        const int w = lane + 64 * u;
-        cd[u] = w < g.Wr ? colw[wave * NB + w] : 0ull;
-        cs[u] = w < g.Wr && pass == 0 ? colw[wave * NB + g.Wr + w] : 0ull;
-    }
-    if (pass == 0) {
+    // one wave per target; a wave that is done returns from here
+    [&]() {
+        if (k >= K) return;
+        if (pass == 1 && cls[s * K + k] != -2) return;
+        const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
+        const uint64_t* rsc = rs + (size_t)s * NB;
+        // the column: destabilizer words cd, stabilizer words cs (band lane + 64 u of each half)
+        uint64_t cd[kMaxStabBandsPerLane], cs[kMaxStabBandsPerLane];
 #pragma unroll
         for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
-            const uint64_t m = __ballot(cs[u] != 0ull);
-            if (m) {
-                const int l = ctz64(m);
-                if (lane == 0) cls[s * K + k] = (l + 64 * u) * 64 + ctz64(readlane_u64(cs[u], l));
-                return;                              // random at layer start
-            }
+            const int w = lane + 64 * u;
+            cd[u] = w < g.Wr ? colw[wave * NB + w] : 0ull;
+            cs[u] = w < g.Wr && pass == 0 ? colw[wave * NB + g.Wr + w] : 0ull;
         }
-    }
-    if (lane == 0) cls[s * K + k] = pass == 0 ? -1 : -3;
-    for (int u = lane; u < nrdw; u += 64) parw[u] = 0;
-    const uint64_t* base = tb + (size_t)g.NR * g.RS;
-    int jc[kMaxWordsPerLane];
-    uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
+        if (pass == 0) {
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-        const int j = lane + 64 * t;
-        jc[t] = j < g.Wc ? j : 0;
-        msk[t] = j < g.Wc ? ~0ull : 0ull;
-        sx[t] = sz[t] = cr[t] = 0;
-    }
-    int G = 0, rsum = 0, cnt = 0, nc = 0, myrow = 0;
-    // multiply the nc listed rows (lane c holds the c-th) into S, and their shot sign bits
-    auto flush = [&]() {
-        rsum += __popcll(__ballot(lane < nc && ((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull)));
-        for (int u0 = 0; u0 < nc; u0 += kDetRowBatch) {
-            uint64_t rx[kDetRowBatch][kMaxWordsPerLane], rz[kDetRowBatch][kMaxWordsPerLane];
-#pragma unroll
-            for (int u = 0; u < kDetRowBatch; ++u) {
-                const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
-                const uint64_t* row = base + (size_t)i * g.RS;
-#pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                    rx[u][t] = row[jc[t]];
-                    rz[u][t] = row[g.Wc + jc[t]];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kDetRowBatch; ++u) {
-                if (u0 + u >= nc) break;
-#pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                    const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
-                    cr[t] ^= b & sx[t];
-                    G += __popcll(a & b);
-                    sx[t] ^= a;
-                    sz[t] ^= b;
+            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+                const uint64_t m = __ballot(cs[u] != 0ull);
+                if (m) {
+                    const int l = ctz64(m);
+                    if (lane == 0) cls[s * K + k] = (l + 64 * u) * 64 + ctz64(readlane_u64(cs[u], l));
+                    return;                              // random at layer start
                 }
             }
         }
-        for (int b0 = 0; b0 < g.bpc; b0 += 64) {
-            const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b0 + lane, g.bpc - 1)) * g.NB + g.Wr;
-            int par = 0;
-            for (int c = 0; c < nc; c += 8) {
-                int iu[8];
-                uint64_t wv[8];
+        if (lane == 0) cls[s * K + k] = pass == 0 ? -1 : -3;
+        for (int u = lane; u < nrdw; u += 64) parw[u] = 0;
+        const uint64_t* base = tb + (size_t)g.NR * g.RS;
+        int jc[kMaxWordsPerLane];
+        uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
-            }
-            const uint64_t pb = __ballot(par & 1);
-            if (lane == 0) parw[b0 >> 6] ^= pb;
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            const int j = lane + 64 * t;
+            jc[t] = j < g.Wc ? j : 0;
+            msk[t] = j < g.Wc ? ~0ull : 0ull;
+            sx[t] = sz[t] = cr[t] = 0;
         }
-        cnt += nc;
-        nc = 0;
-    };
+        int G = 0, rsum = 0, cnt = 0, nc = 0, myrow = 0;
+        // multiply the nc listed rows (lane c holds the c-th) into S, and their shot sign bits
+        auto flush = [&]() {
+            rsum += __popcll(__ballot(lane < nc && ((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull)));
+            for (int u0 = 0; u0 < nc; u0 += kDetRowBatch) {
+                uint64_t rx[kDetRowBatch][kMaxWordsPerLane], rz[kDetRowBatch][kMaxWordsPerLane];
 #pragma unroll
-    for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
-        uint64_t lanes = __ballot(cd[u] != 0ull);
-        while (lanes) {
-            const int l = ctz64(lanes);
-            lanes &= lanes - 1;
-            uint64_t v = readlane_u64(cd[u], l);
-            const int wb = l + 64 * u;
-            while (v) {
-                const int bit = ctz64(v);
-                v &= v - 1;
-                if (lane == nc) myrow = wb * 64 + bit;
-                if (++nc == 64) flush();
+                for (int u = 0; u < kDetRowBatch; ++u) {
+                    const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
+                    const uint64_t* row = base + (size_t)i * g.RS;
+#pragma unroll
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        rx[u][t] = row[jc[t]];
+                        rz[u][t] = row[g.Wc + jc[t]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kDetRowBatch; ++u) {
+                    if (u0 + u >= nc) break;
+#pragma unroll
+                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                        const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
+                        cr[t] ^= b & sx[t];
+                        G += __popcll(a & b);
+                        sx[t] ^= a;
+                        sz[t] ^= b;
+                    }
+                }
+            }
+            for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+                const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b0 + lane, g.bpc - 1)) * g.NB + g.Wr;
+                int par = 0;
+                for (int c = 0; c < nc; c += 8) {
+                    int iu[8];
+                    uint64_t wv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
+                }
+                const uint64_t pb = __ballot(par & 1);
+                if (lane == 0) parw[b0 >> 6] ^= pb;
+            }
+            cnt += nc;
+            nc = 0;
+        };
+#pragma unroll
+        for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+            uint64_t lanes = __ballot(cd[u] != 0ull);
+            while (lanes) {
+                const int l = ctz64(lanes);
+                lanes &= lanes - 1;
+                uint64_t v = readlane_u64(cd[u], l);
+                const int wb = l + 64 * u;
+                while (v) {
+                    const int bit = ctz64(v);
+                    v &= v - 1;
+                    if (lane == nc) myrow = wb * 64 + bit;
+                    if (++nc == 64) flush();
+                }
             }
         }
-    }
-    if (nc) flush();
-    uint64_t xres = 0;
+        if (nc) flush();
+        uint64_t xres = 0;
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-        G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
-        xres |= sx[t];
-    }
-    G = wave_sum(G);
-    xres = wave_or(xres);
-    const int e = (2 * rsum + G) & 3;
-    if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
-    const int shared = e >> 1;
-    for (int b = lane; b < g.bpc; b += 64)
-        obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ (int)((parw[b >> 6] >> (b & 63)) & 1ull));
-    if (lane == 0) {
-        count_add(counters, pass == 0 ? 2 : 6, 1ull);
-        count_add(counters, 3, (unsigned long long)cnt);
+        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
+            xres |= sx[t];
+        }
+        G = wave_sum(G);
+        xres = wave_or(xres);
+        const int e = (2 * rsum + G) & 3;
+        if (lane == 0 && ((e & 1) || xres)) atomicOr(err, 1);
+        const int shared = e >> 1;
+        for (int b = lane; b < g.bpc; b += 64)
+            obuf[(size_t)(s * g.bpc + b) * K + k] = (uint8_t)(shared ^ (int)((parw[b >> 6] >> (b & 63)) & 1ull));
+        if (lane == 0) {
+            atomicAdd(&s_det, 1u);
+            atomicAdd(&s_rows, (unsigned int)cnt);
+        }
+    }();
+    __syncthreads();
+    if (threadIdx.x == 0 && s_det) {
+        count_add(counters, pass == 0 ? 2 : 6, (unsigned long long)s_det);
+        count_add(counters, 3, (unsigned long long)s_rows);
     }
 }
 
@@ -764,6 +788,7 @@ struct ChainCtx {
     uint8_t* obuf;
     int* err;
     unsigned long long* counters;
+    unsigned int* lcnt;      // (LDS) random measurements and stabilizer rows updated, flushed at the end
 };
 
 // Pending target k2 has x in the pivot row of target k: the replay must flip that bit of a
@@ -976,8 +1001,8 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
     // this target's x column is never read again
     if (lane == 0) c.tm[a] = -1;
     if (lane == 0) {
-        count_add(c.counters, 4, 1ull);
-        count_add(c.counters, 5, (unsigned long long)nrows);
+        atomicAdd(&c.lcnt[0], 1u);
+        atomicAdd(&c.lcnt[1], (unsigned int)nrows);
     }
 }
 
@@ -1098,8 +1123,8 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
         }
     }
     if (tid == 0) {
-        count_add(c.counters, 4, 1ull);
-        count_add(c.counters, 5, (unsigned long long)idx);
+        atomicAdd(&c.lcnt[0], 1u);
+        atomicAdd(&c.lcnt[1], (unsigned int)idx);
     }
     __syncthreads();
     // signs of the rowsum rows, pending targets' x columns, the pivot log
@@ -1162,7 +1187,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         int* __restrict__ err, unsigned long long* __restrict__ counters)
 {
     extern __shared__ uint64_t sm[];
-    const int s = blockIdx.x;
+    const int s = blk_x(g);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const ChainLds L = chain_lds_layout(g);
@@ -1212,6 +1237,12 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     c.obuf = obuf;
     c.err = err;
     c.counters = counters;
+    __shared__ unsigned int s_lcnt[2];
+    c.lcnt = s_lcnt;
+    if (tid == 0) {
+        s_lcnt[0] = 0;
+        s_lcnt[1] = 0;
+    }
     int* pd = pend + (size_t)s * K;
     int* cl = cls + (size_t)s * K;
 
@@ -1521,7 +1552,11 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         }
         __syncthreads();
     }
-    if (tid == 0) count_add(counters, 0, (unsigned long long)rounds);
+    if (tid == 0) {
+        count_add(counters, 0, (unsigned long long)rounds);
+        count_add(counters, 4, (unsigned long long)s_lcnt[0]);
+        count_add(counters, 5, (unsigned long long)s_lcnt[1]);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1612,7 +1647,7 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
 {
     if (*ran == 0) return;                             // no random target ran in this layer
     extern __shared__ uint64_t rsm[];
-    const int band = blockIdx.x, s = blockIdx.y;
+    const int band = blk_x(g), s = blk_y(g);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int Wc = g.Wc, RS = g.RS, NB = g.NB;
@@ -1631,6 +1666,7 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     uint16_t* ent = lists ? (uint16_t*)(base + LL.ent) : nullptr;
     __shared__ int s_cnt[16], s_crow[64], s_ncand, s_next;
     __shared__ unsigned long long s_cand;
+    __shared__ unsigned int s_rc[4];   // work counters, flushed once per block
     const int* lp = plog_p + (size_t)s * K;
     const uint16_t* pl = plist + (size_t)s * K * kPListCap;
     const int* pc = pcnt + (size_t)s * K;
@@ -1642,6 +1678,7 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
     if (tid == 0) {
         s_cand = 0;
         s_next = 0;
+        s_rc[0] = s_rc[1] = s_rc[2] = s_rc[3] = 0;
     }
     for (int r = tid; r < 64; r += nt) prow[r] = -1;
     __syncthreads();
@@ -1992,10 +2029,17 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
         }
     }
     if (lane == 0 && nrows) {
-        if (applied) count_add(counters, 8, (unsigned long long)applied);
-        count_add(counters, 9, (unsigned long long)nrows);
-        if (trows) count_add(counters, 10, (unsigned long long)trows);
-        if (tev) count_add(counters, 11, (unsigned long long)tev);
+        atomicAdd(&s_rc[0], (unsigned int)applied);
+        atomicAdd(&s_rc[1], (unsigned int)nrows);
+        atomicAdd(&s_rc[2], (unsigned int)trows);
+        atomicAdd(&s_rc[3], (unsigned int)tev);
+    }
+    __syncthreads();
+    if (tid == 0 && s_rc[1]) {
+        if (s_rc[0]) count_add(counters, 8, (unsigned long long)s_rc[0]);
+        count_add(counters, 9, (unsigned long long)s_rc[1]);
+        if (s_rc[2]) count_add(counters, 10, (unsigned long long)s_rc[2]);
+        if (s_rc[3]) count_add(counters, 11, (unsigned long long)s_rc[3]);
     }
 }
 
@@ -2010,7 +2054,7 @@ __global__ void k_reset_record(Geom g, uint64_t* __restrict__ rd, const uint64_t
                                uint8_t* __restrict__ record, long long rec_stride, long long rec_off,
                                int do_record)
 {
-    const int w = blockIdx.x, b = blockIdx.y;
+    const int w = blk_x(g), b = blk_y(g);
     const int s = b / g.bpc;
     const uint8_t* ob = obuf + (size_t)b * K;
     const uint64_t* Zc = Zcol + ((size_t)s * g.NB + w) * K;

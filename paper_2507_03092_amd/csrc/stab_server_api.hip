@@ -367,7 +367,7 @@ int stab_server_step(stab_server* s, int32_t* finished_out)
     const int nc = (int)circ.size();
     if (nc > 0) {
         std::vector<int> order(nc);
-        for (int i = 0; i < nc; ++i) order[i] = i;
+        for (int i = 0; i < nc; ++i) order[i] = reverse_blocks() ? nc - 1 - i : i;
         std::vector<uint64_t> ib(nc, 0ull);
         if ((rc = ensure(s->d_circ, (size_t)nc * sizeof(BatchCirc))) || (rc = ensure(s->d_order, (size_t)nc * 4)) ||
             (rc = ensure(s->d_keys, (size_t)nc * sizeof(ulonglong2))) || (rc = ensure(s->d_ibase, (size_t)nc * 8)))
