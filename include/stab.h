@@ -285,11 +285,14 @@ int stab_batch_execute(stab_batch *batch, const stab_batch_program *prog, uint8_
  * rows each lane group keeps in flight (2, 4 or 8); bit 8 (STAB_TILE_WHOLE_WAVE): every row
  * takes a whole 64-lane wave, else a row takes the smallest power of two of lanes that holds
  * its x words, so one wave updates several rows of a small circuit per load.  With two x
- * words per lane (a circuit above 4096 qubits in the batch) 8 rows in flight run as 4.  0 =
- * the default (8 rows in flight with one x word per lane, 2 with two; lanes sized to the row).
+ * words per lane (a circuit above 4096 qubits in the batch) 8 rows in flight run as 4.  Bit 9
+ * (STAB_TILE_ONE_BLOCK): the kernel variant whose registers are sized for one block per compute
+ * unit (no spills), else capped so two blocks share one.  0 = the default (8 rows in flight with
+ * one x word per lane, 2 with two; lanes sized to the row; two blocks per compute unit).
  * The configuration changes speed only: every configuration writes the same records and
  * leaves the same tableaux. */
 #define STAB_TILE_WHOLE_WAVE 0x100
+#define STAB_TILE_ONE_BLOCK  0x200
 #define STAB_TUNE_FORCE 1
 
 /* Autotuner: time every launch configuration on this program from the batch's current

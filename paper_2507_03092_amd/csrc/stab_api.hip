@@ -33,7 +33,7 @@ int fail(int code, const std::string& msg)
 }
 
 constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
-constexpr int kSegThreads = 512;
+constexpr int kSegThreads = 1024;
 constexpr int kChainThreads = 512;
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel

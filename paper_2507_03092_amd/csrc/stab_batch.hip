@@ -316,6 +316,9 @@ __device__ int batch_list(const uint64_t* bits, int w0, int w1, int skip0, int s
 // set: every row takes the whole wave (64 lanes per row), clear: a row takes the smallest
 // power of two of lanes that covers its x words, so a wave updates 64 / lanes rows per load.
 constexpr int kTileWholeWave = 1 << 8;
+// bit 9 set: the kernel variant with registers for one block per compute unit (no spills);
+// clear: capped for two blocks per compute unit.
+constexpr int kTileOneBlock = 1 << 9;
 
 // rowsum(row, p) for every listed row: x|z ^= pivot, sign from the g-sum (Appendix A.2).
 // A row is owned by a group of lpr lanes (lane sub of the group holds x words sub,
@@ -809,9 +812,11 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
 }
 
 // NW = x words per lane of a row: 1 when every circuit has at most 4096 qubits, else 2.
-// Register use is capped so two blocks share a compute unit.
-template <int NW>
-__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4))) k_batch(BatchArgs A)
+// OCC = waves per SIMD the registers are sized for: 4 caps them at 128 so two blocks share a
+// compute unit (the compiler spills some values to scratch), 2 lets one block per compute unit
+// use up to 256 with no spills.  Which is faster depends on the batch; the autotuner times both.
+template <int NW, int OCC>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(OCC))) k_batch(BatchArgs A)
 {
     extern __shared__ uint64_t lds[];
     const int ci = A.order[blockIdx.x];

@@ -252,8 +252,10 @@ int stab_batch_create(int32_t ncirc, const int32_t* n, uint64_t seed, void* dev_
         C.tab_off = L.tab_off[c];
         C.rs_off = L.rs_off[c];
     }
-    (void)hipFuncSetAttribute((const void*)k_batch<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void*)k_batch<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipGetLastError();
     const bool ok = hipMalloc((void**)&b->d_circ, sizeof(BatchCirc) * ncirc) == hipSuccess &&
                     hipMalloc((void**)&b->d_err, sizeof(int)) == hipSuccess &&
@@ -470,8 +472,14 @@ int batch_launch(stab_batch* b, const stab_batch_program* P, int tile, int quota
     A.seed = b->seed;
     A.err = b->d_err;
     A.counters = b->d_counters;
-    if (P->nw == 1) k_batch<1><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
-    else k_batch<2><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
+    const bool one = (tile & kTileOneBlock) != 0;
+    if (P->nw == 1) {
+        if (one) k_batch<1, 2><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
+        else k_batch<1, 4><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
+    } else {
+        if (one) k_batch<2, 2><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
+        else k_batch<2, 4><<<b->ncirc, kBatchThreads, P->lds_bytes, b->stream>>>(A);
+    }
     BHIP_CHECK(b, hipGetLastError());
     BHIP_CHECK(b, hipEventRecord(b->ev1, b->stream));
     return STAB_OK;
@@ -509,6 +517,7 @@ int stab_batch_execute(stab_batch* b, const stab_batch_program* P, uint8_t* out_
 }
 
 static_assert(kTileWholeWave == STAB_TILE_WHOLE_WAVE, "tile flag of include/stab.h");
+static_assert(kTileOneBlock == STAB_TILE_ONE_BLOCK, "tile flag of include/stab.h");
 
 namespace {
 
@@ -518,7 +527,7 @@ std::map<uint64_t, int> g_tune;   // (program shape, device) -> launch configura
 bool tile_valid(int tile)
 {
     const int R = tile & 0xff;
-    return (tile & ~(0xff | kTileWholeWave)) == 0 && (R == 2 || R == 4 || R == 8);
+    return (tile & ~(0xff | kTileWholeWave | kTileOneBlock)) == 0 && (R == 2 || R == 4 || R == 8);
 }
 
 bool tune_file_lookup(uint64_t key, int* tile)
@@ -588,10 +597,12 @@ int stab_batch_autotune(stab_batch* b, stab_batch_program* P, int32_t meas_quota
             return STAB_OK;
         }
     }
-    // candidates: lanes per row sized to the circuit or the whole wave, 2, 4 or 8 rows in flight
+    // candidates: lanes per row sized to the circuit or the whole wave, 2, 4 or 8 rows in
+    // flight, registers capped for two blocks per compute unit or not (one block)
     std::vector<int> cand;
-    for (int wide = 0; wide < 2; ++wide)
-        for (int R : {2, 4, 8}) cand.push_back(R | (wide ? kTileWholeWave : 0));
+    for (int one = 0; one < 2; ++one)
+        for (int wide = 0; wide < 2; ++wide)
+            for (int R : {2, 4, 8}) cand.push_back(R | (wide ? kTileWholeWave : 0) | (one ? kTileOneBlock : 0));
     const long long bytes = P->rec_byte[b->ncirc];
     void* save = nullptr;
     if (hipMalloc(&save, b->bytes) != hipSuccess) return fail(STAB_ENOMEM, "device allocation failed");

@@ -264,7 +264,7 @@ k_noise_draw(const NoiseDesc* __restrict__ nd, const int* __restrict__ ntg, int 
 // Segment kernel helpers.  Column j of a staged half-band: x word at
 // T[(j & 63) * RSP + (j >> 6)], z word at + Wc (32-bit words, one bit per staged row).
 // ------------------------------------------------------------------------------------------
-constexpr int kSegPrefetch = 10;  // gates / events per thread prefetched into registers
+constexpr int kSegPrefetch = 5;   // gates / events per thread prefetched into registers
 
 // Registers holding one item's gate or noise-event list (first kSegPrefetch * blockDim.x).
 struct ItemBuf {
@@ -386,14 +386,14 @@ __device__ __forceinline__ void transpose_tiles(uint32_t* T, int RSP, int RS, in
 }
 
 // ------------------------------------------------------------------------------------------
-// Segment kernel: grid (2 * NB half-bands, S copies), 512 threads.  A block stages 32 rows
+// Segment kernel: grid (2 * NB half-bands, S copies), 1024 threads.  A block stages 32 rows
 // (half of a 64-row band) as 32-bit qubit-major words: row r's 64-bit word c is split into
 // its low half (columns 64c..64c+31, staged at lane r) and high half (lane 32 + r); each
 // half-wave then transposes its 32x32 tile, so afterwards lane L of tile c holds column
 // 64c + L for the 32 rows.  Two such blocks fit the LDS of one compute unit.  The block owns
 // the 32-bit half of every sign word and column-extract word of its band.
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
           uint64_t* __restrict__ rd, SegArgs a)
 {
@@ -415,19 +415,19 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
     ItemBuf cur, nxt;
     fetch_item(a, 0, tid, nt, cur);
 
-    // 32 rows -> LDS with 16-byte loads (RS is even, so a pair never crosses a row), 8 in
+    // 32 rows -> LDS with 16-byte loads (RS is even, so a pair never crosses a row), 4 in
     // flight; word (r, c) splits into T[r][c] (low half) and T[32 + r][c] (high half)
     const int npairs = 16 * RS;
     const ulonglong2* gb2 = (const ulonglong2*)gb;
-    for (int p0 = 0; p0 < npairs; p0 += 8 * nt) {
-        ulonglong2 v[8];
+    for (int p0 = 0; p0 < npairs; p0 += 4 * nt) {
+        ulonglong2 v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int p = p0 + u * nt + tid;
             if (p < npairs) v[u] = gb2[p];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int p = p0 + u * nt + tid;
             if (p < npairs) {
                 const int i = 2 * p;

@@ -244,8 +244,8 @@ int stab_server_create(void* dev_buf, uint64_t buf_bytes, void* hip_stream, stab
     s->bytes = (size_t)buf_bytes & ~(size_t)255;
     s->max_lds = lds;
     s->free_blocks[0] = s->bytes;
-    (void)hipFuncSetAttribute((const void*)k_batch<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void*)k_batch<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_batch<2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipGetLastError();
     if (hipMalloc((void**)&s->d_err, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&s->d_counters, kNumCounters * kCounterStripes * sizeof(unsigned long long)) != hipSuccess ||
@@ -398,8 +398,8 @@ int stab_server_step(stab_server* s, int32_t* finished_out)
         A.err = s->d_err;
         A.counters = s->d_counters;
         const size_t lds = (size_t)batch_lds_words(maxwc) * 8;
-        if (maxwc <= 64) k_batch<1><<<nc, kBatchThreads, lds, s->stream>>>(A);
-        else k_batch<2><<<nc, kBatchThreads, lds, s->stream>>>(A);
+        if (maxwc <= 64) k_batch<1, 4><<<nc, kBatchThreads, lds, s->stream>>>(A);
+        else k_batch<2, 4><<<nc, kBatchThreads, lds, s->stream>>>(A);
         SHIP_CHECK(s, hipGetLastError());
         int err = 0;
         SHIP_CHECK(s, hipMemcpyAsync(&err, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream));

@@ -36,6 +36,7 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
 TILE_WHOLE_WAVE = 0x100   # STAB_TILE_WHOLE_WAVE
+TILE_ONE_BLOCK = 0x200    # STAB_TILE_ONE_BLOCK
 TUNE_FORCE = 1            # STAB_TUNE_FORCE
 KERNELS = ("init", "noise_draw", "segment", "classify", "det", "chain", "reset_record", "pack", "replay",
            "extract")

@@ -131,13 +131,16 @@ def test_batch_reset_and_reexecution(stab):
 
 
 
-TILES = [0] + [r | w for w in (0, 0x100) for r in (2, 4, 8)]
+# row tile (lanes sized to the row or the whole wave; 2, 4 or 8 rows in flight) x register budget
+# (two blocks per compute unit, or one: STAB_TILE_ONE_BLOCK)
+TILES = [0] + [r | w | o for o in (0, 0x200) for w in (0, 0x100) for r in (2, 4, 8)]
 
 
 def test_batch_every_launch_configuration(stab):
-    """Each rowsum row tile (lanes sized to the row or the whole wave; 2, 4 or 8 rows in
-    flight) writes the oracle's records and tableaux, on sizes that give every lane-group
-    width from 1 to 64 lanes and ragged lists."""
+    """Each launch configuration (rowsum row tile: lanes sized to the row or the whole wave,
+    2, 4 or 8 rows in flight; kernel variant with registers for two blocks per compute unit or
+    one) writes the oracle's records and tableaux, on sizes that give every lane-group width
+    from 1 to 64 lanes and ragged lists."""
     sizes = [1, 3, 64, 65, 130, 200, 257, 520, 1030]
     circs = [Cc.random_layered_clifford(n, 24, (5 + n % 3, 1), meas_every=4, meas_frac=0.3) for n in sizes]
     circs[1] = Cc.random_clifford_measure(3, depth=12, seed=9, p_meas=0.4, noise=0.05)
@@ -173,7 +176,7 @@ def test_batch_launch_configurations_two_words(stab):
     want = _oracle_all(circs, seed, range(2), False)
     b = stab.Batch(ns, seed=seed)
     prog = b.compile(circs)
-    for tile in (2, 8, 0x102, 0x108):
+    for tile in (2, 8, 0x102, 0x108, 0x208, 0x302):
         say(f"tile {tile:#x}")
         b.reset(seed)
         prog.tile = tile
