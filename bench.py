@@ -327,6 +327,7 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window of the serving workload")
     ap.add_argument("--serve-rate", type=float, default=None, help="arrival rate of the serving workload (1/s)")
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0, help="device arena of the server (GB)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte "
                          "counters of a profiler against a known size) and exit")
@@ -538,7 +539,9 @@ def bench_batch(args) -> int:
 
 def bench_serve(args) -> int:
     """Continuous batching: Poisson arrivals of surface-code memory requests (d ~ U{3,...,31},
-    d rounds, shots ~ U{1..100}) served by one server; latency from arrival to records."""
+    d rounds, p = 1e-3, shots ~ U{1..100}) served by one server on a 200 GB arena; latency from
+    arrival to records.  A fixed sample of the served requests is checked afterwards against the
+    same request run alone (stab_sample), and its small ones against the oracle."""
     import numpy as np
     import torch
 
@@ -554,23 +557,27 @@ def bench_serve(args) -> int:
                                                   w["shots_hi"])
     m = len(times)
     circs = {int(d): Cc.surface_code_memory(int(d), int(d), w["p"])[0] for d in np.unique(ds)}
-    arena = 32 << 30
+    arena = (int(args.serve_arena_gb * 1e9) // 256) * 256
     srv = stab.Server(arena)
     prog = {d: srv.program(c) for d, c in circs.items()}
-    log(f"serve: {m} requests over {args.serve_seconds} s at {rate}/s, arena {arena >> 30} GiB")
+    # the requests whose records are kept and checked: every 25th, and every 5th one with d >= 25
+    keep = {j for j in range(m) if j % 25 == 0 or (ds[j] >= 25 and j % 5 == 0)}
+    log(f"serve: {m} requests over {args.serve_seconds} s at {rate}/s, arena {arena / 1e9:.0f} GB")
     torch.cuda.synchronize()
-    arrival, lat, done_work = {}, [], 0
+    arrival, lat, kept = {}, [], {}
+    done_work = 0
     i = 0
     steps = 0
-    resident_sum = 0
+    busy_sum = 0
     t0 = time.perf_counter()
     drain_limit = args.serve_seconds + 120.0
+    last_log = 0.0
     while True:
         now = time.perf_counter() - t0
         while i < m and times[i] <= now:
             d = int(ds[i])
             rid = srv.submit(prog[d], int(shots[i]), int(seeds[i]))
-            arrival[rid] = (times[i], d, int(shots[i]))
+            arrival[rid] = (times[i], i)
             i += 1
         st = srv.stats()
         if st["queued"] == 0 and st["resident_requests"] == 0:
@@ -580,26 +587,46 @@ def bench_serve(args) -> int:
             continue
         if now > drain_limit:
             break
-        srv.step()
+        nf = srv.step()
         steps += 1
-        resident_sum += st["resident_shots"]
+        busy_sum += st["resident_shots"]
         tdone = time.perf_counter() - t0
         for rid in srv.poll():
-            ta, d, sh = arrival.pop(rid)
+            ta, j = arrival.pop(rid)
             lat.append(tdone - ta)
-            done_work += sh * d
-            srv.result(rid, sh)
+            done_work += int(shots[j]) * int(ds[j])
+            rec = srv.result(rid, int(shots[j]))
+            if j in keep:
+                kept[j] = rec
+        if now - last_log > 10.0:
+            last_log = now
+            log(f"t={now:.0f} s: {len(lat)} served, {st['in_flight']} in flight, {st['queued']} queued")
+        if nf == 0 and (i == m or times[i] > tdone + 0.0002):
+            time.sleep(0.0001)
     wall = time.perf_counter() - t0
     unfinished = len(arrival) + (m - i)
     lat_ms = np.array(lat) * 1000.0
     p50 = float(np.percentile(lat_ms, 50)) if len(lat) else None
     p99 = float(np.percentile(lat_ms, 99)) if len(lat) else None
-    log(f"served {len(lat)} of {m} in {wall:.1f} s, p50 {p50} ms, p99 {p99} ms, {steps} steps")
+    st = srv.stats()
+    log(f"served {len(lat)} of {m} in {wall:.1f} s, p50 {p50} ms, p99 {p99} ms, {steps} steps, "
+        f"{st['steps']} batch launches")
+    srv.close()
+    # parity of the kept sample: the same request alone, and the oracle for the small ones
+    bad = [j for j, rec in kept.items()
+           if not np.array_equal(rec, stab.sample(circs[int(ds[j])], int(shots[j]), int(seeds[j]))[0])]
+    small = sorted(j for j in kept if ds[j] <= 7)[:24]
+    from oracle import oracle as O
+
+    bad_oracle = [j for j in small
+                  if not np.array_equal(kept[j], O.run(circs[int(ds[j])], int(shots[j]), int(seeds[j])))]
+    parity = {"checked_alone": len(kept), "checked_alone_d_ge_25": int(sum(1 for j in kept if ds[j] >= 25)),
+              "equal_alone": len(kept) - len(bad), "checked_oracle": len(small),
+              "equal_oracle": len(small) - len(bad_oracle)}
+    log(f"parity of served requests: {parity}")
     cpu = None
     if not args.no_cpu_baseline:
         from concurrent.futures import ThreadPoolExecutor
-
-        from oracle import oracle as O
 
         pick = np.random.default_rng(3).choice(m, size=min(16, m), replace=False)
         c0 = time.perf_counter()
@@ -611,7 +638,6 @@ def bench_serve(args) -> int:
                "sample": f"{len(pick)} requests drawn from the stream (4 at a time, each over its shots)",
                "seconds": round(c1 - c0, 2)}
         log(f"cpu baseline: {cpu}")
-    srv.close()
     line = {
         "metric": "continuous-batching sampling service: shot-rounds/sec served, p50/p99 request latency",
         "value": round(done_work / wall, 1), "unit": "shot-rounds/s", "n_gpus": 1, "steps": steps, "warmup": 0,
@@ -619,15 +645,16 @@ def bench_serve(args) -> int:
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serve", "rate_per_s": rate, "seconds": args.serve_seconds, "requests": m,
                    "d_range": [w["d_lo"], w["d_hi"]], "shots_max": w["shots_hi"], "p": w["p"], "seed": w["seed"],
-                   "arena_bytes": arena},
+                   "arena_bytes": arena, "lanes": "auto (every request Pauli-noise: shared lane)"},
         "latency_ms": {"p50": p50, "p99": p99, "max": float(lat_ms.max()) if len(lat) else None},
         "served": len(lat), "unfinished": unfinished, "wall_s": round(wall, 2),
-        "mean_resident_shots": round(resident_sum / max(steps, 1), 1),
+        "batch_launches": st["steps"], "mean_resident_shots": round(busy_sum / max(steps, 1), 1),
+        "parity": parity,
         "roofline": None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
-    return 0
+    return 0 if not bad and not bad_oracle else 1
 
 
 def bench_exact_noise(args) -> int:

@@ -305,7 +305,8 @@ int stab_batch_execute(stab_batch *batch, const stab_batch_program *prog, uint8_
  * process under a fingerprint of the program's shape (circuit sizes, step, gate and measured
  * target counts) and the device's compute-unit count; when the environment variable
  * STAB_TUNE_CACHE names a file, choices are also read from and appended to it ("<key hex>
- * <tile>" lines).  A cached choice is used without timing unless flags has STAB_TUNE_FORCE.
+ * <tile>" lines); when STAB_TUNE_LOG is set, each candidate's time is printed to stderr.  A
+ * cached choice is used without timing unless flags has STAB_TUNE_FORCE.
  * tile_out (may be NULL) receives the configuration.  Errors: as stab_batch_execute;
  * STAB_EINTERNAL also when two configurations disagree (the batch is then restored). */
 int stab_batch_autotune(stab_batch *batch, stab_batch_program *prog, int32_t meas_quota,
@@ -344,22 +345,34 @@ int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, i
                  uint64_t *gc, uint64_t *qwc, void *hip_stream);
 
 /* ---------------------------------------------------------------------------------------
- * Continuous batching of sampling requests.  A server owns a caller-provided device arena;
- * a request (a registered op stream, a shot count, a seed) is admitted in arrival order once
- * its bytes (stab_server_request_bytes: per shot a tableau and scratch, plus records) fit in the
- * free arena, and each stab_server_step() runs ONE launch that advances every shot of every
- * resident request by one measurement step (a round of a memory experiment): rounds of all
- * resident requests share the launch, new requests join at the next step, finished ones
- * leave and free their bytes.  Shot s of a request with seed k draws with RNG key (k, s) and
- * counts its own instructions from 0, so its records equal those of a full-mode context
- * (stab_create(..., seed = k, first_shot = 0)) running the stream alone, whatever else is
- * resident.  A server is not thread-safe; it allocates nothing per request.
+ * Continuous batching of sampling requests (the parallel sampling of Sec. 6 of the paper, run
+ * as a service).  A server owns a caller-provided device arena; a request (a registered op
+ * stream, a shot count, a seed) is admitted in arrival order once its bytes
+ * (stab_server_request_bytes) fit in the free arena.  Shot s of a request with seed k draws with
+ * RNG key (k, s) and counts its own instructions from 0, so its records equal those of
+ * stab_sample(stream, shots, seed = k) run alone, whatever else is resident.  Two lanes:
+ *   STAB_LANE_BATCH  every shot has its own tableau; each stab_server_step() runs ONE launch
+ *                    that advances every resident batch-lane shot by one measurement step (a
+ *                    round of a memory experiment): rounds of all resident requests share the
+ *                    launch, new requests join at the next step, finished ones leave.
+ *   STAB_LANE_SHARED the request's shots share one x|z tableau (STAB_MODE_SHARED; Pauli noise
+ *                    only).  Admission enqueues the request's whole stream on one of the
+ *                    server's device streams; requests on different streams overlap on the
+ *                    device, and a step retires those that completed.
+ *   STAB_LANE_AUTO   (default) SHARED for streams without T1T2 noise, else BATCH.
+ * A server is not thread-safe.  Per request it allocates nothing on the device: the shared lane
+ * compiles and uploads a stream once per power-of-two shot bucket (at its first request), and
+ * stages records in 64 MiB of pinned host memory allocated at the first shared-lane request.
  * ------------------------------------------------------------------------------------- */
 typedef struct stab_server stab_server;
 
+#define STAB_LANE_AUTO   0
+#define STAB_LANE_BATCH  1
+#define STAB_LANE_SHARED 2
 
 /* Create a server on dev_buf (buf_bytes, 256-byte aligned, owned by the caller until
- * stab_server_destroy; its size is the admission cap). */
+ * stab_server_destroy; its size is the admission cap).  hip_stream carries the batch lane; the
+ * shared lane runs on streams of the server's own. */
 int stab_server_create(void *dev_buf, uint64_t buf_bytes, void *hip_stream, stab_server **out);
 void stab_server_destroy(stab_server *server);
 
@@ -368,23 +381,36 @@ void stab_server_destroy(stab_server *server);
 int stab_server_program(stab_server *server, const stab_instr *instrs, int32_t ninstr,
                         const int32_t *targets, int64_t ntargets, int32_t n, int32_t *prog_out);
 
+/* Lane of the program's later requests (STAB_LANE_*).  Errors: STAB_EINVAL (unknown program or
+ * lane; SHARED for a stream with T1T2 noise). */
+int stab_server_set_lane(stab_server *server, int32_t prog, int32_t lane);
+
 /* Records per shot of a registered program, or -1. */
 int64_t stab_server_program_records(const stab_server *server, int32_t prog);
 
-/* Arena bytes a request of `shots` shots of a registered program occupies (per shot its
- * tableau, signs and the columns of its largest measurement instruction; then the records). */
+/* Arena bytes a request of `shots` shots of a registered program occupies in its lane (batch:
+ * per shot its tableau, signs and the columns of its largest measurement instruction, then the
+ * records; shared: one tableau with the signs of the shot bucket and the execution scratch). */
 int stab_server_request_bytes(const stab_server *server, int32_t prog, int32_t shots,
                               uint64_t *bytes_out);
 
 /* Queue a request (host only; nothing runs until stab_server_step).  *id_out receives its id.
- * Errors: STAB_EINVAL (unknown program, shots < 1), STAB_ERANGE (larger than the arena). */
+ * Errors: STAB_EINVAL (unknown program, shots < 1), STAB_ERANGE (larger than the arena, or its
+ * records larger than the pinned staging), STAB_ENOMEM (the pinned staging). */
 int stab_server_submit(stab_server *server, int32_t prog, int32_t shots, uint64_t seed,
                        int64_t *id_out);
 
-/* Admit what fits, run one launch over every resident shot, retire finished requests
- * (their records are copied to host memory and their bytes freed).  Synchronous.
- * *finished_out (may be NULL) receives the number of requests that finished. */
+/* Retire shared-lane requests that completed, admit what fits (shared-lane requests start at
+ * once), run one batch-lane launch over every resident batch-lane shot and retire the batch-lane
+ * requests that finished (their records are copied to host memory and their bytes freed).  Waits
+ * for the batch launch only.  *finished_out (may be NULL) receives the number of requests that
+ * finished. */
 int stab_server_step(stab_server *server, int32_t *finished_out);
+
+/* Drop a request: queued, resident (a shared-lane request's launches finish; its bytes are freed
+ * when they have) or finished and not taken.  It never appears in stab_server_poll afterwards.
+ * Errors: STAB_EINVAL (unknown id, or already cancelled or taken). */
+int stab_server_cancel(stab_server *server, int64_t id);
 
 /* Ids of finished requests not returned before, oldest first; returns how many it wrote. */
 int stab_server_poll(stab_server *server, int64_t *ids, int32_t max_ids);
@@ -397,7 +423,8 @@ int64_t stab_server_records(const stab_server *server, int64_t id);
 int stab_server_result(stab_server *server, int64_t id, uint8_t *out_bits);
 
 /* [0] queued requests, [1] resident requests, [2] resident unfinished shots, [3] arena bytes
- * in use, [4] arena bytes, [5] steps run, [6] requests finished.  nout <= 7. */
+ * in use, [4] arena bytes, [5] batch launches run, [6] requests finished, [7] shared-lane
+ * requests in flight, [8] requests cancelled.  nout <= 9. */
 int stab_server_stats(const stab_server *server, int64_t *out, int32_t nout);
 
 /* Message of the last error on this thread ("" if none).  The paper defines no error

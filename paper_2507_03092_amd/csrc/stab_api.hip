@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -112,8 +113,8 @@ struct stab_ctx {
     uint64_t* rd = nullptr;
     bool poisoned = false;
     int max_lds = kLdsBytes;
-    // stab_sample_noalloc: every buffer of the context and its program is carved from the
-    // static scratch array of the device (arena != NULL), nothing is allocated or freed
+    // stab_sample_noalloc and the server's shared lane: every buffer of the context (and of its
+    // program) is carved from caller-owned scratch (arena != NULL), nothing is allocated or freed
     char* arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
     int* d_err = nullptr;
@@ -207,7 +208,7 @@ int arena_take(stab_ctx* ctx, size_t bytes, void** out)
     bytes = std::max<size_t>(align256(bytes), 256);
     if (at + bytes > ctx->arena_cap)
         return fail(STAB_ERANGE, "the workload needs more than the " + std::to_string(ctx->arena_cap) +
-                                     " bytes of static scratch of stab_sample_noalloc");
+                                     " bytes of scratch given to the context");
     *out = ctx->arena + at;
     ctx->arena_used = at + bytes;
     return STAB_OK;
@@ -515,7 +516,8 @@ namespace {
 // stab_create; with arena != NULL the context's own device memory (error flag, counters and,
 // later, every execution buffer) is carved from arena[0, arena_cap) and no event is created.
 int create_ctx(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t first_shot, void* dev_buf,
-               uint64_t buf_bytes, void* hip_stream, char* arena, size_t arena_cap, stab_ctx** out)
+               uint64_t buf_bytes, void* hip_stream, char* arena, size_t arena_cap, stab_ctx** out,
+               bool wait_init = true)
 {
     if (!out) return fail(STAB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -582,7 +584,8 @@ int create_ctx(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t f
         return fail(STAB_EDEVICE, "memset failed");
     }
     rc = launch_init(ctx);
-    if (rc == STAB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(STAB_EDEVICE, "init failed");
+    if (rc == STAB_OK && wait_init && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = fail(STAB_EDEVICE, "init failed");
     if (rc) {
         stab_destroy(ctx);
         return rc;
@@ -790,6 +793,199 @@ void exec_sizes(const Geom& g, const stab_program& P, bool draw_all, size_t* siz
     for (int i = 0; i < kExecBufs; ++i) sizes[i] = v[i];
 }
 
+// Device buffers of one execution of P, grown (or carved from the context's scratch) before
+// anything is enqueued.  The noise of every segment is drawn by one launch at the start when its
+// event slots fit (the draws depend on the RNG key only, not on the tableau), else segment by
+// segment; *draw_all_out says which.
+int exec_prepare(stab_ctx* ctx, const stab_program* P, bool allow_draw_all, bool* draw_all_out)
+{
+    const Geom& g = ctx->g;
+    bool draw_all = allow_draw_all && P->nnoise > 0 && P->nnoise <= 65535 && P->ev_total <= kDrawAllEvents;
+    int rc;
+    DevBuf* bufs[kExecBufs] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->pend, &ctx->obuf, &ctx->events,
+                               &ctx->record, &ctx->packed, &ctx->plog_p, &ctx->plog_rs, &ctx->plog_row,
+                               &ctx->plog_rd, &ctx->ran, &ctx->plist, &ctx->pcnt, &ctx->povf};
+    size_t sizes[kExecBufs];
+    exec_sizes(g, *P, draw_all, sizes);
+    if (ctx->arena && draw_all) {
+        // in the static scratch the whole program's noise is drawn at once only if it fits
+        size_t at = ctx->arena_used;
+        for (int i = 0; i < kExecBufs; ++i)
+            if (bufs[i]->cap < sizes[i]) at = align256(at) + std::max<size_t>(align256(sizes[i]), 256);
+        if (at > ctx->arena_cap) {
+            draw_all = false;
+            exec_sizes(g, *P, draw_all, sizes);
+        }
+    }
+    for (int i = 0; i < kExecBufs; ++i)
+        if ((rc = ensure(ctx, *bufs[i], sizes[i]))) return rc;
+    *draw_all_out = draw_all;
+    return STAB_OK;
+}
+
+// Launch shapes of one execution that depend on the geometry and the device's LDS.
+struct ExecLds {
+    int lds_rd = 0;           // per-shot sign accumulators of the segment kernel in LDS
+    size_t seg_lds = 0, chain_lds = 0, replay_lds = 0;
+    int ent_cap = -1;         // replay list entries in LDS (-1: the replay's small form)
+};
+
+int exec_lds(const Geom& g, const stab_program& P, int max_lds, ExecLds* out)
+{
+    ExecLds E;
+    const size_t K = (size_t)std::max(P.Kmax, 1);
+    // per-shot sign accumulators in LDS only where they keep two half-band blocks per compute
+    // unit (or where even one block without them would not get two)
+    const int seg_base = seg_lds_words(g.RS) * 4, seg_acc = (seg_lds_words(g.RS) + g.bpc) * 4;
+    E.lds_rd = (seg_acc <= max_lds / 2 || (seg_base > max_lds / 2 && seg_acc <= max_lds)) ? 1 : 0;
+    E.seg_lds = (size_t)(seg_lds_words(g.RS) + (E.lds_rd ? g.bpc : 0)) * 4;
+    E.chain_lds = (size_t)chain_lds_layout(g).total;
+    if (E.chain_lds + kReplayStatic > (size_t)max_lds)   // (a bound on its static LDS too)
+        return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
+    // the replay's list form when its fixed part leaves room for list entries in LDS
+    const ReplayLds RL = replay_lds_layout((int)K, (g.bpc + 63) / 64, kReplayThreads / 64);
+    // (kReplayStatic bytes of the block's LDS are its own __shared__ variables)
+    E.replay_lds = (size_t)RL.small_bytes;
+    const int replay_room = max_lds - kReplayStatic;
+    if (replay_walk_fits((int)K) && RL.fixed_bytes + 2 * 1024 <= replay_room) {
+        E.ent_cap = std::min((replay_room - RL.fixed_bytes) / 2, (int)K * kPListCap);
+        E.replay_lds = (size_t)RL.fixed_bytes + 2 * (size_t)E.ent_cap;
+    }
+    if (E.replay_lds > (size_t)replay_room) return fail(STAB_ERANGE, "too many shots per copy for the replay kernel");
+    *out = E;
+    return STAB_OK;
+}
+
+// Every launch of one execution of P on ctx->stream, eagerly or into a graph (a fill kernel
+// clears the event counts: no memset node in a captured graph).  use_mran skips the launches of
+// measurement layers where nothing ran in an earlier execution from |0...0>; learn_mran marks,
+// in P->d_mran, the layers where something runs.
+int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, bool learn_mran)
+{
+    const Geom& g = ctx->g;
+    uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
+    uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
+    int* cls = (int*)ctx->cls.p;
+    uint8_t* obuf = (uint8_t*)ctx->obuf.p;
+    uint2* events = (uint2*)ctx->events.p;
+    uint8_t* record = (uint8_t*)ctx->record.p;
+    const uint64_t base = ctx->instr_counter;
+
+    ExecLds E;
+    int rc = exec_lds(g, *P, ctx->max_lds, &E);
+    if (rc) return rc;
+    const int lds_rd = E.lds_rd, ent_cap = E.ent_cap;
+    const size_t seg_lds = E.seg_lds, chain_lds = E.chain_lds, replay_lds = E.replay_lds;
+    int* plog_p = (int*)ctx->plog_p.p;
+    int* plog_rs = (int*)ctx->plog_rs.p;
+    uint64_t* plog_row = (uint64_t*)ctx->plog_row.p;
+    uint64_t* plog_rd = (uint64_t*)ctx->plog_rd.p;
+    int* ran = (int*)ctx->ran.p;
+
+    const long long nbytes = (P->nrec + 7) / 8;
+    if (P->nnoise > 0)
+        k_zero32<<<1, 256, 0, ctx->stream>>>((uint32_t*)P->d_ev_count, (long long)P->nnoise);
+    if (draw_all) {
+        const long long most = (long long)P->max_units * g.B;
+        const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock), (unsigned)P->nnoise);
+        TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
+            P->d_noise, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events, P->d_noise_seg,
+            P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
+    }
+    for (const auto& st : P->steps) {
+        if (st.first == 0) {
+            const SegPlan& sp = P->segs[st.second];
+            if (sp.noise_count > 0 && !draw_all) {
+                const long long most = (long long)sp.max_units * g.B;
+                const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
+                                (unsigned)sp.noise_count);
+                TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
+                    P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
+                    nullptr, P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
+            }
+            if (sp.item_count > 0 || sp.meas >= 0) {
+                SegArgs a{};
+                a.items = P->d_items + sp.item_begin;
+                a.nitems = sp.item_count;
+                a.gates = P->d_gates;
+                a.events = events + (draw_all ? sp.ev_global : 0);
+                a.ev_count = P->d_ev_count;
+                a.ev_base = P->d_ev_base;
+                a.write_back = sp.modifies;
+                a.lds_rd = lds_rd;
+                if (sp.meas >= 0) {
+                    const MeasPlan& m = P->meas[sp.meas];
+                    a.ext_q = P->d_mtq + m.tq_begin;
+                    a.K = m.K;
+                } else {
+                    a.ext_q = nullptr;
+                    a.K = 0;
+                }
+                a.Xcol = Xcol;
+                a.Zcol = Zcol;
+                TIMED(ctx, 2, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
+                                  g, ctx->tab, ctx->rs, ctx->rd, a)));
+            }
+        } else {
+            const MeasPlan& m = P->meas[st.second];
+            const int K2 = m.K;
+            // classes of the targets and the outcomes of the deterministic ones (also clears ran)
+            const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
+            const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
+            TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 0, nullptr)));
+            // a layer where nothing ran in an earlier execution from |0...0>: the next four
+            // launches would return at once
+            if (!use_mran || P->mran[st.second]) {
+            TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
+                              (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
+                              m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
+                              (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
+            // destabilizer updates of the run targets, then fresh columns of the final tableau
+            // (skipped on the device when nothing ran)
+            TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
+                              g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
+                              plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
+                              (const int*)ctx->povf.p, ran, ent_cap, ctx->d_err, ctx->d_counters)));
+            {
+                SegArgs a{};
+                a.items = P->d_items;
+                a.nitems = 0;
+                a.gates = P->d_gates;
+                a.events = events;
+                a.ev_count = P->d_ev_count;
+                a.ev_base = P->d_ev_base;
+                a.write_back = 0;
+                a.lds_rd = 0;
+                a.ext_q = P->d_mtq + m.tq_begin;
+                a.K = K2;
+                a.Xcol = Xcol;
+                a.Zcol = Zcol;
+                a.gate = ran;
+                TIMED(ctx, 9, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, (size_t)seg_lds_words(g.RS) * 4,
+                                           ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
+            }
+            // targets the chain found deterministic: reduced in parallel on the final tableau
+            TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+                                                                       obuf, ran, ctx->d_err, ctx->d_counters, 1,
+                                                                       learn_mran ? P->d_mran + st.second : nullptr)));
+            }
+            const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
+            TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
+                              g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
+                              do_record)));
+        }
+    }
+    if (P->nrec > 0) {
+        const long long total = nbytes * g.B;
+        const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
+        TIMED(ctx, 7, (k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p)));
+    }
+    HIP_CHECK(ctx, hipGetLastError());
+    return STAB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -801,172 +997,15 @@ int stab_execute(stab_ctx* ctx, stab_program* P, uint8_t* out_bits, float* elaps
     const Geom& g = ctx->g;
     if (P->n != g.n || P->B != g.B) return fail(STAB_EINVAL, "program compiled for another geometry");
     if (P->nrec > 0 && !out_bits) return fail(STAB_EINVAL, "out_bits is NULL but the stream records outcomes");
-    const size_t K = (size_t)std::max(P->Kmax, 1);
-    // the noise of every segment is drawn by one launch at the start when its event slots fit
-    // (the draws depend on the RNG key only, not on the tableau); else segment by segment
-    bool draw_all = P->nnoise > 0 && P->nnoise <= 65535 && P->ev_total <= kDrawAllEvents;
+    bool draw_all = false;
     int rc;
-    {
-        DevBuf* bufs[kExecBufs] = {&ctx->xcol, &ctx->zcol, &ctx->cls, &ctx->pend, &ctx->obuf, &ctx->events,
-                                   &ctx->record, &ctx->packed, &ctx->plog_p, &ctx->plog_rs, &ctx->plog_row,
-                                   &ctx->plog_rd, &ctx->ran, &ctx->plist, &ctx->pcnt, &ctx->povf};
-        size_t sizes[kExecBufs];
-        exec_sizes(g, *P, draw_all, sizes);
-        if (ctx->arena && draw_all) {
-            // in the static scratch the whole program's noise is drawn at once only if it fits
-            size_t at = ctx->arena_used;
-            for (int i = 0; i < kExecBufs; ++i)
-                if (bufs[i]->cap < sizes[i]) at = align256(at) + std::max<size_t>(align256(sizes[i]), 256);
-            if (at > ctx->arena_cap) {
-                draw_all = false;
-                exec_sizes(g, *P, draw_all, sizes);
-            }
-        }
-        for (int i = 0; i < kExecBufs; ++i)
-            if ((rc = ensure(ctx, *bufs[i], sizes[i]))) return rc;
-    }
-    uint64_t* Xcol = (uint64_t*)ctx->xcol.p;
-    uint64_t* Zcol = (uint64_t*)ctx->zcol.p;
-    int* cls = (int*)ctx->cls.p;
-    uint8_t* obuf = (uint8_t*)ctx->obuf.p;
-    uint2* events = (uint2*)ctx->events.p;
-    uint8_t* record = (uint8_t*)ctx->record.p;
-    const uint64_t base = ctx->instr_counter;
-
-    // per-shot sign accumulators in LDS only where they keep two half-band blocks per compute
-    // unit (or where even one block without them would not get two)
-    const int seg_base = seg_lds_words(g.RS) * 4, seg_acc = (seg_lds_words(g.RS) + g.bpc) * 4;
-    const int lds_rd = (seg_acc <= ctx->max_lds / 2 || (seg_base > ctx->max_lds / 2 && seg_acc <= ctx->max_lds)) ? 1 : 0;
-    const size_t seg_lds = (size_t)(seg_lds_words(g.RS) + (lds_rd ? g.bpc : 0)) * 4;
-    const size_t chain_lds = (size_t)chain_lds_layout(g).total;
-    if (chain_lds + kReplayStatic > (size_t)ctx->max_lds)   // (a bound on its static LDS too)
-        return fail(STAB_ERANGE, "too many shots per copy for the chain kernel");
-    // the replay's list form when its fixed part leaves room for list entries in LDS
-    const ReplayLds RL = replay_lds_layout((int)K, (g.bpc + 63) / 64, kReplayThreads / 64);
-    // (kReplayStatic bytes of the block's LDS are its own __shared__ variables)
-    int ent_cap = -1;
-    size_t replay_lds = (size_t)RL.small_bytes;
-    const int replay_room = ctx->max_lds - kReplayStatic;
-    if (replay_walk_fits((int)K) && RL.fixed_bytes + 2 * 1024 <= replay_room) {
-        ent_cap = std::min((replay_room - RL.fixed_bytes) / 2, (int)K * kPListCap);
-        replay_lds = (size_t)RL.fixed_bytes + 2 * (size_t)ent_cap;
-    }
-    if (replay_lds > (size_t)replay_room) return fail(STAB_ERANGE, "too many shots per copy for the replay kernel");
-    int* plog_p = (int*)ctx->plog_p.p;
-    int* plog_rs = (int*)ctx->plog_rs.p;
-    uint64_t* plog_row = (uint64_t*)ctx->plog_row.p;
-    uint64_t* plog_rd = (uint64_t*)ctx->plog_rd.p;
-    int* ran = (int*)ctx->ran.p;
-
+    if ((rc = exec_prepare(ctx, P, true, &draw_all))) return rc;
     const long long nbytes = (P->nrec + 7) / 8;
     // layers where nothing ran are known once the program has run from |0...0>
+    const uint64_t base = ctx->instr_counter;
     const bool use_mran = base == 0 && P->mran_known;
     const bool learn_mran = base == 0 && !P->mran_known && !P->meas.empty();
-    // every launch of the program, eagerly or into a graph (a fill kernel clears the event
-    // counts: no memset node in a captured graph)
-    auto enqueue = [&]() -> int {
-        if (P->nnoise > 0)
-            k_zero32<<<1, 256, 0, ctx->stream>>>((uint32_t*)P->d_ev_count, (long long)P->nnoise);
-        if (draw_all) {
-            const long long most = (long long)P->max_units * g.B;
-            const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock), (unsigned)P->nnoise);
-            TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
-                P->d_noise, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events, P->d_noise_seg,
-                P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
-        }
-        for (const auto& st : P->steps) {
-            if (st.first == 0) {
-                const SegPlan& sp = P->segs[st.second];
-                if (sp.noise_count > 0 && !draw_all) {
-                    const long long most = (long long)sp.max_units * g.B;
-                    const dim3 grid((unsigned)((most + kNoiseUnitsPerBlock - 1) / kNoiseUnitsPerBlock),
-                                    (unsigned)sp.noise_count);
-                    TIMED(ctx, 1, (k_noise_draw<<<grid, kNoiseThreads, 0, ctx->stream>>>(
-                        P->d_noise + sp.noise_begin, P->d_noise_tg, g.B, ctx->seed, ctx->first_shot, base, events,
-                        nullptr, P->d_ev_base, P->d_ev_count, ctx->d_counters, g.rev)));
-                }
-                if (sp.item_count > 0 || sp.meas >= 0) {
-                    SegArgs a{};
-                    a.items = P->d_items + sp.item_begin;
-                    a.nitems = sp.item_count;
-                    a.gates = P->d_gates;
-                    a.events = events + (draw_all ? sp.ev_global : 0);
-                    a.ev_count = P->d_ev_count;
-                    a.ev_base = P->d_ev_base;
-                    a.write_back = sp.modifies;
-                    a.lds_rd = lds_rd;
-                    if (sp.meas >= 0) {
-                        const MeasPlan& m = P->meas[sp.meas];
-                        a.ext_q = P->d_mtq + m.tq_begin;
-                        a.K = m.K;
-                    } else {
-                        a.ext_q = nullptr;
-                        a.K = 0;
-                    }
-                    a.Xcol = Xcol;
-                    a.Zcol = Zcol;
-                    TIMED(ctx, 2, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, seg_lds, ctx->stream>>>(
-                                      g, ctx->tab, ctx->rs, ctx->rd, a)));
-                }
-            } else {
-                const MeasPlan& m = P->meas[st.second];
-                const int K2 = m.K;
-                // classes of the targets and the outcomes of the deterministic ones (also clears ran)
-                const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
-                const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
-                TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 0, nullptr)));
-                // a layer where nothing ran in an earlier execution from |0...0>: the next four
-                // launches would return at once
-                if (!use_mran || P->mran[st.second]) {
-                TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
-                                  g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
-                                  (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
-                                  m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,
-                                  (int*)ctx->pcnt.p, (int*)ctx->povf.p, obuf, ctx->d_err, ctx->d_counters)));
-                // destabilizer updates of the run targets, then fresh columns of the final tableau
-                // (skipped on the device when nothing ran)
-                TIMED(ctx, 8, (replay_kernel(g.Wc)<<<dim3(g.Wr, g.S), kReplayThreads, replay_lds, ctx->stream>>>(
-                                  g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, P->d_mtq + m.tq_begin, plog_p, plog_row,
-                                  plog_rs, plog_rd, (const uint16_t*)ctx->plist.p, (const int*)ctx->pcnt.p,
-                                  (const int*)ctx->povf.p, ran, ent_cap, ctx->d_err, ctx->d_counters)));
-                {
-                    SegArgs a{};
-                    a.items = P->d_items;
-                    a.nitems = 0;
-                    a.gates = P->d_gates;
-                    a.events = events;
-                    a.ev_count = P->d_ev_count;
-                    a.ev_base = P->d_ev_base;
-                    a.write_back = 0;
-                    a.lds_rd = 0;
-                    a.ext_q = P->d_mtq + m.tq_begin;
-                    a.K = K2;
-                    a.Xcol = Xcol;
-                    a.Zcol = Zcol;
-                    a.gate = ran;
-                    TIMED(ctx, 9, (k_segment<<<dim3(2 * g.NB, g.S), kSegThreads, (size_t)seg_lds_words(g.RS) * 4,
-                                               ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
-                }
-                // targets the chain found deterministic: reduced in parallel on the final tableau
-                TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
-                                                                           obuf, ran, ctx->d_err, ctx->d_counters, 1,
-                                                                           learn_mran ? P->d_mran + st.second : nullptr)));
-                }
-                const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
-                TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
-                                  g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
-                                  do_record)));
-            }
-        }
-        if (P->nrec > 0) {
-            const long long total = nbytes * g.B;
-            const int blocks = (int)std::min<long long>((total + 255) / 256, 1 << 16);
-            TIMED(ctx, 7, (k_pack<<<blocks, 256, 0, ctx->stream>>>(record, P->nrec, g.B, (uint8_t*)ctx->packed.p)));
-        }
-        HIP_CHECK(ctx, hipGetLastError());
-        return STAB_OK;
-    };
+    auto enqueue = [&]() -> int { return exec_enqueue(ctx, P, draw_all, use_mran, learn_mran); };
 
     if (ctx->ev0) HIP_CHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     if (ctx->graph_on && !ctx->timing && !learn_mran) {

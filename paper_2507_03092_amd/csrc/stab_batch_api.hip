@@ -652,6 +652,7 @@ int stab_batch_autotune(stab_batch* b, stab_batch_program* P, int32_t meas_quota
             continue;
         }
         if (got != ref) return done(fail(STAB_EINTERNAL, "launch configurations gave different records"));
+        if (std::getenv("STAB_TUNE_LOG")) std::fprintf(stderr, "[stab tune] tile 0x%x: %.3f ms\n", tile, ms);
         if (best < 0 || ms < best_ms) {
             best = tile;
             best_ms = ms;

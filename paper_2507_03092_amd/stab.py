@@ -32,6 +32,7 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_commute", "stab_server_request_bytes", "stab_server_create", "stab_server_destroy",
            "stab_server_program", "stab_server_program_records", "stab_server_submit", "stab_server_step",
            "stab_server_poll", "stab_server_records", "stab_server_result", "stab_server_stats",
+           "stab_server_set_lane", "stab_server_cancel",
            "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
@@ -106,6 +107,8 @@ def lib():
         "stab_server_records": (I64, [P, I64]),
         "stab_server_result": (C.c_int, [P, I64, P]),
         "stab_server_stats": (C.c_int, [P, P, I32]),
+        "stab_server_set_lane": (C.c_int, [P, I32, I32]),
+        "stab_server_cancel": (C.c_int, [P, I64]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -451,12 +454,13 @@ def commute(A, B, n: int, device: str = "cuda:0", qubitwise: bool = True):
 
 # ------------------------------------------------------------ continuous-batching server ---
 SERVER_STATS = ("queued", "resident_requests", "resident_shots", "bytes_in_use", "arena_bytes", "steps",
-                "finished")
+                "finished", "in_flight", "cancelled")
+LANE_AUTO, LANE_BATCH, LANE_SHARED = 0, 1, 2
 
 
 class Server:
-    """stab_server_*: requests admitted by arena bytes, one round of every resident shot per
-    step."""
+    """stab_server_*: requests admitted by arena bytes; batch-lane shots advance one round per
+    step, shared-lane requests run whole on the server's streams."""
 
     def __init__(self, arena_bytes: int, device: str = "cuda:0"):
         import torch
@@ -488,6 +492,12 @@ class Server:
         _check(lib().stab_server_program(self.h, _ptr(instr), len(instr), _ptr(tg), len(tg), circ.n,
                                          C.byref(pid)))
         return pid.value
+
+    def set_lane(self, prog: int, lane: int):
+        _check(lib().stab_server_set_lane(self.h, prog, lane))
+
+    def cancel(self, rid: int):
+        _check(lib().stab_server_cancel(self.h, rid))
 
     def request_bytes(self, prog: int, shots: int) -> int:
         out = C.c_uint64(0)

@@ -271,3 +271,20 @@ def test_single_context_rejects_t1t2(L):
     with pytest.raises(stab.StabError) as e:
         stab.plan_describe(c)
     assert e.value.code == stab.EINVAL and "batch" in str(e.value)
+
+
+def test_server_argument_errors_without_gpu(L):
+    """Server calls that fail before any HIP call: NULL handles and arguments."""
+    null = C.c_void_p(None)
+    out = C.c_void_p(None)
+    assert L.stab_server_create(null, 1 << 20, null, C.byref(out)) == stab.EINVAL
+    assert L.stab_server_create(C.c_void_p(4096 + 8), 1 << 20, null, C.byref(out)) == stab.EINVAL  # misaligned
+    assert L.stab_server_set_lane(null, 0, stab.LANE_SHARED) == stab.EINVAL
+    assert L.stab_server_cancel(null, 1) == stab.EINVAL
+    assert L.stab_server_step(null, None) == stab.EINVAL
+    assert L.stab_server_poll(null, None, 0) == stab.EINVAL
+    assert L.stab_server_records(null, 1) == -1
+    assert L.stab_server_program_records(null, 0) == -1
+    v = np.zeros(9, dtype=np.int64)
+    assert L.stab_server_stats(null, v.ctypes.data_as(C.c_void_p), 9) == stab.EINVAL
+    L.stab_server_destroy(null)                 # a no-op
