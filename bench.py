@@ -323,7 +323,7 @@ def main() -> int:
     ap.add_argument("--tile", default="auto",
                     help="random_batch launch configuration: 'auto' (autotuner, first two measurement "
                          "instructions of every circuit) or a configuration number")
-    ap.add_argument("--tune-quota", type=int, default=2, help="measurement instructions the autotuner times")
+    ap.add_argument("--tune-quota", type=int, default=6, help="measurement instructions the autotuner times")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window of the serving workload")
     ap.add_argument("--serve-rate", type=float, default=None, help="arrival rate of the serving workload (1/s)")
