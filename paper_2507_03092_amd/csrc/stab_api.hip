@@ -972,7 +972,9 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
                                                                        learn_mran ? P->d_mran + st.second : nullptr)));
             }
             const int do_reset = m.kind != STAB_M, do_record = m.kind != STAB_R;
-            TIMED(ctx, 6, (k_reset_record<<<dim3(g.NB, g.B), 256, 0, ctx->stream>>>(
+            const int rshots = std::min(g.B, kResetShots);
+            const dim3 rgrid(g.NB, (g.B + rshots - 1) / rshots, std::max(1, (K2 + kResetChunk - 1) / kResetChunk));
+            TIMED(ctx, 6, (k_reset_record<<<rgrid, 64 * rshots, 0, ctx->stream>>>(
                               g, ctx->rd, Zcol, obuf, K2, do_reset, record, (long long)P->nrec, m.rec_off,
                               do_record)));
         }

@@ -538,7 +538,7 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 // of 64 gather in LDS (nrdw words per wave).
 // ------------------------------------------------------------------------------------------
 constexpr int kDetTargets = 8;                 // targets (waves) per block
-constexpr int kDetRowBatch = 2;                // rows a wave loads at once
+constexpr int kDetRowBatch = 3;                // rows a wave loads at once
 
 __global__ void __launch_bounds__(64 * kDetTargets) __attribute__((amdgpu_waves_per_eu(4)))
 k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
@@ -1293,7 +1293,9 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     __syncthreads();
     for (int k = tid; k < K; k += nt)
         if (cl[k] >= 0) c.tm[tq[k]] = (int16_t)k;
-    for (int i = tid; i < g.NR; i += nt) owner[i] = INT_MAX;
+    // owner[i]: (round << 7) | (127 - t) of the first window position t that claimed row pair i
+    // in that round; a claim from an earlier round counts as no claim, so nothing is reset
+    for (int i = tid; i < g.NR; i += nt) owner[i] = 0;
     const int w0 = min(kWin, npend);
     for (int t = tid; t < w0; t += nt) {
         sk[t] = pd[t];
@@ -1423,20 +1425,22 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int cnt = (t < nw && ty == T_RANDOM) ? scnt[sl] : -1;
             const int pv = cnt >= 0 ? spiv[sl] : 0;
             const int* rw = srows + sl * kRCap;
+            const int mine = (rounds << 7) | (127 - t);
             if (elig)
-                for (int r = 0; r <= cnt; ++r) atomicMin(&owner[r < cnt ? rw[r] % g.NR : pv], t);
+                for (int r = 0; r <= cnt; ++r) atomicMax(&owner[r < cnt ? rw[r] % g.NR : pv], mine);
             __builtin_amdgcn_wave_barrier();
             bool ok = elig;
             if (elig)
                 for (int r = 0; r <= cnt && ok; ++r)
-                    if (owner[r < cnt ? rw[r] % g.NR : pv] != t) ok = false;
+                    if (owner[r < cnt ? rw[r] % g.NR : pv] != mine) ok = false;
             const uint64_t selm = __ballot(ok);
             if (t < nw) wsel[t] = ok ? 1 : 0;
             bool st = false;
             if (!ok && cnt >= 0)
                 for (int r = 0; r <= cnt && !st; ++r) {
                     const int o = owner[r < cnt ? rw[r] % g.NR : pv];
-                    if (o != INT_MAX && o != t && ((selm >> o) & 1ull)) st = true;
+                    const int ot = 127 - (o & 127);
+                    if ((o >> 7) == rounds && ot != t && ((selm >> ot) & 1ull)) st = true;
                 }
             if (t < nw && (st || (ty == T_BIG_RANDOM && bar > 0))) stype[sl] = T_UNKNOWN;
             if (ok) selpos[__popcll(selm & ((1ull << lane) - 1ull))] = t;
@@ -1533,11 +1537,6 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 const int sl = wpos[selpos[j]];
                 wave_random(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
             }
-        }
-        for (int t = wave; t < bar; t += nwaves) {
-            const int sl = wpos[t], cnt = scnt[sl];
-            for (int r = lane; r <= cnt; r += 64)
-                owner[r < cnt ? srows[sl * kRCap + r] % g.NR : spiv[sl]] = INT_MAX;
         }
         __syncthreads();
         // ---- remove executed entries (their slots become free) ----
@@ -2047,46 +2046,49 @@ k_replay(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t
 // End of a measurement layer: resets (X on the qubit when the outcome is 1: every row with z
 // at the qubit flips sign -- applied once for the whole layer, which is exact because sign
 // flips commute with rowsum and with the other measurements of the layer) and the record.
-// Block per (sign word w, shot b), threads over targets.
+// Block per (sign word w, group of up to kResetShots shots, chunk of kResetChunk targets), a
+// wave per shot and its lanes over the chunk's targets.  The waves of a block read the same
+// column words at about the same time, so a band's column comes from L2 once per block (the
+// other waves hit in L1), not once per shot; the chunks keep enough blocks in flight.
 // ------------------------------------------------------------------------------------------
-__global__ void k_reset_record(Geom g, uint64_t* __restrict__ rd, const uint64_t* __restrict__ Zcol,
-                               const uint8_t* __restrict__ obuf, int K, int do_reset,
-                               uint8_t* __restrict__ record, long long rec_stride, long long rec_off,
-                               int do_record)
+constexpr int kResetShots = 16;
+constexpr int kResetChunk = 1024;
+
+__global__ void __launch_bounds__(64 * kResetShots)
+k_reset_record(Geom g, uint64_t* __restrict__ rd, const uint64_t* __restrict__ Zcol,
+               const uint8_t* __restrict__ obuf, int K, int do_reset, uint8_t* __restrict__ record,
+               long long rec_stride, long long rec_off, int do_record)
 {
-    const int w = blk_x(g), b = blk_y(g);
+    const int w = blk_x(g);
+    const int lane = threadIdx.x & 63;
+    const int b = blk_y(g) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (b >= g.B) return;                       // (no block barrier below)
     const int s = b / g.bpc;
+    const int kc = (g.rev ? (int)gridDim.z - 1 - (int)blockIdx.z : (int)blockIdx.z) * kResetChunk;
+    const int ke = min(K, kc + kResetChunk);
     const uint8_t* ob = obuf + (size_t)b * K;
     const uint64_t* Zc = Zcol + ((size_t)s * g.NB + w) * K;
     uint64_t acc = 0;
-    // four targets per thread at a time, every load unconditional so they are all in flight
-    const int step = blockDim.x;
-    for (int k0 = threadIdx.x; k0 < K; k0 += 4 * step) {
+    // four targets per lane at a time, every load unconditional so they are all in flight
+    for (int k0 = kc + lane; k0 < ke; k0 += 4 * 64) {
         uint8_t o[4];
         uint64_t z[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * step;
-            o[u] = k < K ? ob[k] : (uint8_t)0;
-            z[u] = (do_reset && k < K) ? Zc[k] : 0ull;
+            const int k = k0 + u * 64;
+            o[u] = k < ke ? ob[k] : (uint8_t)0;
+            z[u] = (do_reset && k < ke) ? Zc[k] : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * step;
+            const int k = k0 + u * 64;
             if (o[u]) acc ^= z[u];
-            if (do_record && w == 0 && k < K) record[(size_t)b * rec_stride + rec_off + k] = o[u];
+            if (do_record && w == 0 && k < ke) record[(size_t)b * rec_stride + rec_off + k] = o[u];
         }
     }
     if (do_reset) {
-        __shared__ uint64_t red[16];
         acc = wave_xor(acc);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t t = 0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t ^= red[i];
-            if (t) rd[(size_t)b * g.NB + w] ^= t;
-        }
+        if (lane == 0 && acc) atomicXor((unsigned long long*)&rd[(size_t)b * g.NB + w], (unsigned long long)acc);
     }
 }
 
