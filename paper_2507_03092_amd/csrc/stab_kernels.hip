@@ -869,7 +869,8 @@ __device__ __forceinline__ void rowsum_rows(const ChainCtx& c, const uint64_t* x
 __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const int* rows, int nrows, int lane,
                                 int* aff = nullptr, int* aff_n = nullptr, int j = 0,
-                                bool have_rd0 = false, uint64_t rd0 = 0, uint64_t rd1 = 0)
+                                bool have_rd0 = false, uint64_t rd0 = 0, uint64_t rd1 = 0,
+                                int out0 = -1, int out1 = -1)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
@@ -915,7 +916,8 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
                 }
                 if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
             }
-            const int out = outcome_bit(c, k, gb);
+            // (the first 128 shots' draws may have been made while the rows were loading)
+            const int out = (b0 == 0 && out0 >= 0) ? out0 : (b0 == 64 && out1 >= 0) ? out1 : outcome_bit(c, k, gb);
             atomicAnd((unsigned long long*)&rdb[Wr + wq], ~(unsigned long long)bq);
             if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
             c.obuf[(size_t)gb * K + k] = (uint8_t)out;
@@ -1035,11 +1037,15 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
     const uint64_t rd1 =
         lane + 64 < g.bpc ? c.rd[(size_t)(c.s * g.bpc + 64 + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
     const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+    // the outcome draws depend on the key and the target only: made while the loads are in flight
+    const int gb0 = c.s * g.bpc + lane;
+    const int out0 = lane < g.bpc ? outcome_bit(c, k, gb0) : 0;
+    const int out1 = lane + 64 < g.bpc ? outcome_bit(c, k, gb0 + 64) : 0;
 #pragma unroll
     for (int t = 0; t < kMaxWordsPerLane; ++t)
         if (lane + 64 * t >= g.Wc) xp[t] = zp[t] = 0ull;
     rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
-    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0, rd1);
+    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0, rd1, out0, out1);
 }
 
 // Whole block: one target with many stabilizer rows (dense tableaux).  Called by every thread.
