@@ -677,6 +677,12 @@ def bench_exact_noise(args) -> int:
     rounds, nmeas = w["rounds"], circ.num_measurements()
     b = stab.Batch(np.full(shots, circ.n, dtype=np.int32), seed=seed)
     prog = b.compile([circ] * shots)
+    if args.tile == "auto":
+        a0 = time.perf_counter()
+        b.autotune(prog, meas_quota=args.tune_quota, force=True)
+        log(f"autotuner: tile {prog.tile:#x} in {time.perf_counter() - a0:.2f} s")
+    else:
+        prog.tile = int(args.tile, 0)
     for _ in range(warmup):
         b.reset(seed)
         b.execute(prog)
@@ -723,7 +729,8 @@ def bench_exact_noise(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload, "d": w["d"], "qubits": circ.n, "rounds": rounds, "shots": shots,
                    "p_depolarizing": w["p"], "idle_exact": list(w["idle_exact"]), "seed": seed,
-                   "form": "batch of per-shot tableaux (one launch)"},
+                   "form": "batch of per-shot tableaux (one launch)", "tile": prog.tile,
+                   "tuned": args.tile == "auto"},
         "measurements_per_s": round(shots * nmeas / (ms_step / 1000.0), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
