@@ -67,6 +67,7 @@ struct ChainLds {
     int aff;     // kAffCap column-upkeep entries {code, flags, batch index}
     int win;     // window arrays: 9 x kWin ints + kWin x kRCap row indices
     int tm;      // n int16: qubit -> pending target whose x column is kept, or -1
+    int pbit;    // NR bits: row pairs that are pivots of the round's executed targets
     int total;
 };
 
@@ -83,7 +84,8 @@ __host__ __device__ inline ChainLds chain_lds_layout(const Geom& g)
     L.aff = L.words + kWide * kRCap * 12;
     L.win = L.aff + kAffCap * 12;
     L.tm = L.win + (9 * kWin + kWin * kRCap) * 4;
-    L.total = L.tm + align16i(g.n * 2);
+    L.pbit = L.tm + align16i(g.n * 2);
+    L.total = L.pbit + align16i((g.NR + 31) / 32 * 4);
     return L;
 }
 

@@ -1214,6 +1214,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     int* wlw = (int*)(wlm + kWide * kRCap);               // and their word indices
     int* aff = (int*)((char*)sm + L.aff);                 // kAffCap x {code, flags, j}
     __shared__ int s_cnt[16], s_nwin, s_tail, s_bar, s_nsel, s_na, s_aff, s_rsp[kWide], s_wln[kWide];
+    // bit i: row pair i is the pivot of a target executed this round (set and cleared in selection)
+    unsigned int* pbit = (unsigned int*)((char*)sm + L.pbit);
 
     ChainCtx c;
     c.g = g;
@@ -1302,6 +1304,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     // owner[i]: (round << 7) | (127 - t) of the first window position t that claimed row pair i
     // in that round; a claim from an earlier round counts as no claim, so nothing is reset
     for (int i = tid; i < g.NR; i += nt) owner[i] = 0;
+    for (int i = tid; i < (g.NR + 31) / 32; i += nt) pbit[i] = 0u;
     const int w0 = min(kWin, npend);
     for (int t = tid; t < w0; t += nt) {
         sk[t] = pd[t];
@@ -1419,8 +1422,10 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         if (nw == 0) break;
         // ---- selection, by wave 0 with one lane per window position t: only analysed
         // entries before the first unknown or big one are eligible; an eligible entry runs iff
-        // it is the first owner of all its row pairs.  Entries sharing a pair with a selected
-        // one must be analysed again; big entries (incomplete row lists) whenever anything runs.
+        // it is the first owner of all its row pairs.  An entry that does not run must be analysed
+        // again iff the pivot of one that runs is among its rows (a row that runs' rowsums touch
+        // changes its x at this entry's qubit only by that pivot's, which is then 0); big
+        // entries (incomplete row lists) whenever anything runs.
         if (wave == 0) {
             const int t = lane;
             const int sl = t < nw ? wpos[t] : 0;
@@ -1441,13 +1446,16 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                     if (owner[r < cnt ? rw[r] % g.NR : pv] != mine) ok = false;
             const uint64_t selm = __ballot(ok);
             if (t < nw) wsel[t] = ok ? 1 : 0;
+            if (ok) atomicOr(&pbit[pv >> 5], 1u << (pv & 31));
+            __builtin_amdgcn_wave_barrier();
             bool st = false;
             if (!ok && cnt >= 0)
                 for (int r = 0; r <= cnt && !st; ++r) {
-                    const int o = owner[r < cnt ? rw[r] % g.NR : pv];
-                    const int ot = 127 - (o & 127);
-                    if ((o >> 7) == rounds && ot != t && ((selm >> ot) & 1ull)) st = true;
+                    const int q = r < cnt ? rw[r] % g.NR : pv;
+                    if ((pbit[q >> 5] >> (q & 31)) & 1u) st = true;
                 }
+            __builtin_amdgcn_wave_barrier();
+            if (ok) atomicAnd(&pbit[pv >> 5], ~(1u << (pv & 31)));
             if (t < nw && (st || (ty == T_BIG_RANDOM && bar > 0))) stype[sl] = T_UNKNOWN;
             if (ok) selpos[__popcll(selm & ((1ull << lane) - 1ull))] = t;
             if (lane == 0) {
