@@ -72,8 +72,9 @@ __host__ __device__ inline int batch_lds_words(int Wc)
     const int RS = 2 * Wc, NB = 2 * Wc;
     const int seg = 64 * (RS + 1) + 16;
     // signs, x-column bits, pivot row, per-wave (X, Z) partial products, 32 ints, row list
-    // (uint16, one entry per row), outcome and random-at-start bits of up to 64*Wc targets
-    const int meas = 2 * NB + RS + 2 * kBatchWaves * RS + 16 + (NB * 64 * 2 + 7) / 8 + 2 * Wc;
+    // (uint16, one entry per row), outcome and random-at-start bits of up to 64*Wc targets and
+    // the list of the random-at-start ones (uint16)
+    const int meas = 2 * NB + RS + 2 * kBatchWaves * RS + 16 + (NB * 64 * 2 + 7) / 8 + 2 * Wc + 16 * Wc;
     return seg > meas ? seg : meas;
 }
 
@@ -508,6 +509,7 @@ struct MeasLds {
     uint16_t* list;    // 2 * NR row indices
     uint64_t* outb;    // outcome bits of the instruction's targets
     uint64_t* rndb;    // random-at-start bits
+    uint16_t* rlist;   // the random-at-start targets in op order
 };
 
 __device__ __forceinline__ MeasLds meas_lds(const BatchCirc& C, uint64_t* lds)
@@ -522,6 +524,7 @@ __device__ __forceinline__ MeasLds meas_lds(const BatchCirc& C, uint64_t* lds)
     L.list = (uint16_t*)(L.s_int + 32);
     L.outb = (uint64_t*)(L.s_int + 32) + 16 * NB;
     L.rndb = L.outb + C.Wc;
+    L.rlist = (uint16_t*)(L.rndb + C.Wc);
     return L;
 }
 
@@ -532,15 +535,28 @@ struct MeasWork {
 
 // Z measurement of qubit a on the live tableau (block-wide): pivot search from the x column,
 // then rowsum and row moves (random, outcome rand_bit) or the deterministic product.
+//
+// The x column is gathered from the tableau (a word per row), or, with Xs, read from column k
+// of the column scratch, which the fast form keeps current for the instruction's remaining
+// random-at-start targets (the rest targets listed in later[], qubits tq[]): after a random
+// outcome every row with x at a (the rowsum rows) flips its x at a later target's qubit by the
+// old pivot row's x there, the pivot row's becomes 0 (it is now Z_a) and its partner
+// destabilizer's becomes the old pivot row's.
 template <int NW>
 __device__ int batch_measure_one(const BatchArgs& A, const BatchCirc& C, int a, int rand_bit, const MeasLds& L,
-                                 MeasWork& W)
+                                 MeasWork& W, uint64_t* Xs = nullptr, int k = 0, const uint16_t* later = nullptr,
+                                 int rest = 0, const int* tq = nullptr)
 {
     const int tid = threadIdx.x;
-    const int Wc = C.Wc, RS = C.RS, NR = C.NR, NB = 2 * C.Wc;
+    const int Wc = C.Wc, RS = C.RS, NR = C.NR, NB = 2 * C.Wc, CK = C.col_k;
     uint64_t* tab = A.tab + C.tab_off;
-    const long long row_b = (long long)RS * 8, col_b = (long long)2 * NR * 8;
-    batch_column(tab, RS, NB, a >> 6, a & 63, L.colx, false);
+    const long long row_b = (long long)RS * 8;
+    const long long col_b = Xs ? (long long)NB * 8 : (long long)2 * NR * 8;
+    if (Xs) {
+        for (int w = tid; w < NB; w += kBatchThreads) L.colx[w] = Xs[(size_t)w * CK + k];
+    } else {
+        batch_column(tab, RS, NB, a >> 6, a & 63, L.colx, false);
+    }
     __syncthreads();
     // pivot: first stabilizer row with x at a (rows NR + n .. 2NR - 1 are zero padding)
     if (tid < 64) {
@@ -579,6 +595,33 @@ __device__ int batch_measure_one(const BatchArgs& A, const BatchCirc& C, int a, 
         W.nrows += nl;
         // column, pivot row, rowsum read+write, two row writes
         W.bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
+        if (Xs && rest > 0) {
+            // the later targets' columns (word w of every later target: consecutive threads take
+            // consecutive targets of one word); a word is written back only when it changes
+            __shared__ unsigned int s_flip;
+            if (tid == 0) s_flip = 0;
+            __syncthreads();
+            const uint64_t bp = 1ull << (p & 63), bd = 1ull << (d & 63);
+            unsigned int flips = 0;
+            for (int id = tid; id < rest * NB; id += kBatchThreads) {
+                const int w = id / rest, j = id - w * rest;
+                const int k2 = later[j], a2 = tq[k2];
+                const uint64_t b = (L.prow[a2 >> 6] >> (a2 & 63)) & 1ull;
+                const bool wp = w == (p >> 6), wd = w == (d >> 6);
+                if (!b && !wp && !wd) continue;
+                uint64_t* xw = Xs + (size_t)w * CK + k2;
+                uint64_t v = *xw;
+                if (b) v ^= L.colx[w];
+                if (wp) v &= ~bp;
+                if (wd) v = (v & ~bd) | (b ? bd : 0ull);
+                *xw = v;
+                if (b && w == 0) ++flips;
+            }
+            if (flips) atomicAdd(&s_flip, flips);
+            __syncthreads();
+            // read and write of the later columns that flip, one word each for the rest
+            W.bytes += (long long)s_flip * NB * 16 + (long long)rest * 2 * 16;
+        }
     } else {
         const int nl = batch_list(L.colx, 0, Wc, -1, -1, L.list, L.s_int + 1);
         outcome = batch_det<NW>(C, tab, L.list, nl, L.sg, L.part, L.s_int + 10, A.err);
@@ -685,20 +728,20 @@ __device__ void batch_measure(const BatchArgs& A, const BatchCirc& C, int ci, co
             count_add(A.counters, 6, (unsigned long long)((long long)ndet * NB * 8 + (long long)nrows * row_b));
         }
         __syncthreads();
-        // random at the start of the instruction: in op order, on the live tableau
-        bool ran = false;
-        for (int kw = 0; kw < KW; ++kw) {
-            uint64_t m = L.rndb[kw];
-            while (m) {
-                const int k = 64 * kw + ctz64(m);
-                m &= m - 1;
-                ran = true;
-                uint64_t u0, u1;
-                philox(A.ibase[ci] + md.instr, (uint64_t)k, key.x, key.y, u0, u1);
-                const int o = batch_measure_one<NW>(A, C, A.meas_tg[md.tq + k], (int)(u0 >> 63), L, W);
-                if (tid == 0 && o) L.outb[kw] |= 1ull << (k & 63);
-                __syncthreads();
-            }
+        // random at the start of the instruction: in op order, on the live tableau, their x
+        // columns read from the scratch and kept current there
+        uint16_t* rl = L.rlist;
+        const int nr = batch_list(L.rndb, 0, KW, -1, -1, rl, L.s_int + 1);
+        const bool ran = nr > 0;
+        uint64_t* Xw = A.cols + C.col_off;
+        for (int i = 0; i < nr; ++i) {
+            const int k = rl[i];
+            uint64_t u0, u1;
+            philox(A.ibase[ci] + md.instr, (uint64_t)k, key.x, key.y, u0, u1);
+            const int o = batch_measure_one<NW>(A, C, A.meas_tg[md.tq + k], (int)(u0 >> 63), L, W, Xw, k, rl + i + 1,
+                                                nr - i - 1, A.meas_tg + md.tq);
+            if (tid == 0 && o) L.outb[k >> 6] |= 1ull << (k & 63);
+            __syncthreads();
         }
         if (md.rec >= 0)
             for (int k = tid; k < md.K; k += kBatchThreads)
