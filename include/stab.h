@@ -353,8 +353,9 @@ int stab_commute(const uint64_t *A, int32_t na, const uint64_t *B, int32_t nb, i
  * stab_sample(stream, shots, seed = k) run alone, whatever else is resident.  Two lanes:
  *   STAB_LANE_BATCH  every shot has its own tableau; each stab_server_step() runs ONE launch
  *                    that advances every resident batch-lane shot by one measurement step (a
- *                    round of a memory experiment): rounds of all resident requests share the
- *                    launch, new requests join at the next step, finished ones leave.
+ *                    round of a memory experiment; four while no request waits for admission):
+ *                    rounds of all resident requests share the launch, new requests join at
+ *                    the next step, finished ones leave.
  *   STAB_LANE_SHARED the request's shots share one x|z tableau (STAB_MODE_SHARED; Pauli noise
  *                    only).  Admission enqueues the request's whole stream on one of the
  *                    server's device streams; requests on different streams overlap on the

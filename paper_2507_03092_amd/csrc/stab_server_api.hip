@@ -103,6 +103,7 @@ struct FreeList {
 };
 
 constexpr int kSrvStreams = 4;                      // shared-lane device streams
+constexpr int kSrvIdleQuota = 4;                    // batch-lane rounds per launch while none waits
 constexpr size_t kSrvPinnedBytes = 64ull << 20;     // pinned staging of shared-lane records
 
 // Shared-mode compile of a program for one shot bucket: the host plan and its device arrays
@@ -485,9 +486,12 @@ int srv_retire_shared(stab_server* s, int* nfin)
 }
 
 // One launch of the batch kernel over every unfinished batch-lane shot, then the retirement of
-// the batch-lane requests that finished.
+// the batch-lane requests that finished.  A launch advances each shot by one measurement step,
+// or by kSrvIdleQuota of them while no request waits for admission (fewer launches and host
+// round trips per request; a request that arrives meanwhile waits up to that many rounds).
 int srv_batch_step(stab_server* s, int* nfin)
 {
+    const int quota = s->queue.empty() ? kSrvIdleQuota : 1;
     std::vector<BatchCirc> circ;
     std::vector<ulonglong2> keys;
     int maxwc = 1;
@@ -533,7 +537,7 @@ int srv_batch_step(stab_server* s, int* nfin)
         A.ibase = (const uint64_t*)s->d_ibase.p;
         A.keys = (const ulonglong2*)s->d_keys.p;
         A.cols = (uint64_t*)s->base;
-        A.meas_quota = 1;
+        A.meas_quota = quota;
         A.seed = 0;
         A.err = s->d_err;
         A.counters = s->d_counters;
@@ -550,7 +554,7 @@ int srv_batch_step(stab_server* s, int* nfin)
         }
         ++s->iterations;
     }
-    // the kernel ran each shot to just after its next measurement step (or to the end)
+    // the kernel ran each shot to just after its next `quota` measurement steps (or to the end)
     for (size_t i = 0; i < s->resident.size();) {
         SrvRequest& r = s->resident[i];
         if (r.shared) {
@@ -561,8 +565,10 @@ int srv_batch_step(stab_server* s, int* nfin)
         for (int sh = 0; sh < r.shots && nc > 0; ++sh) {
             int& cur = r.cursor[sh];
             if (cur >= P.nsteps) continue;
-            while (cur < P.nsteps && s->steps.host[P.step_base + cur].x != 2) ++cur;
-            if (cur < P.nsteps) ++cur;
+            for (int q = 0; q < quota && cur < P.nsteps; ++q) {
+                while (cur < P.nsteps && s->steps.host[P.step_base + cur].x != 2) ++cur;
+                if (cur < P.nsteps) ++cur;
+            }
             if (cur >= P.nsteps) --r.remaining;
         }
         if (r.remaining == 0) {
