@@ -596,31 +596,50 @@ __device__ int batch_measure_one(const BatchArgs& A, const BatchCirc& C, int a, 
         // column, pivot row, rowsum read+write, two row writes
         W.bytes += col_b + row_b + 2 * nl * row_b + 2 * row_b;
         if (Xs && rest > 0) {
-            // the later targets' columns (word w of every later target: consecutive threads take
-            // consecutive targets of one word); a word is written back only when it changes
-            __shared__ unsigned int s_flip;
-            if (tid == 0) s_flip = 0;
+            // the later targets' columns.  A target whose qubit the old pivot row has x at flips
+            // at every row of the measured column (row p's bit, set in both, clears with them)
+            // and its row-d bit becomes 1; any other target keeps its column except row d's bit,
+            // which becomes 0.  The flipping targets are listed (in any order) in L.list, free
+            // since the rowsum, and their words are then updated four to a thread at a time.
+            __shared__ int s_nf;
+            if (tid == 0) s_nf = 0;
             __syncthreads();
-            const uint64_t bp = 1ull << (p & 63), bd = 1ull << (d & 63);
-            unsigned int flips = 0;
-            for (int id = tid; id < rest * NB; id += kBatchThreads) {
-                const int w = id / rest, j = id - w * rest;
+            const uint64_t bd = 1ull << (d & 63);
+            const int wdw = d >> 6;
+            for (int j = tid; j < rest; j += kBatchThreads) {
                 const int k2 = later[j], a2 = tq[k2];
-                const uint64_t b = (L.prow[a2 >> 6] >> (a2 & 63)) & 1ull;
-                const bool wp = w == (p >> 6), wd = w == (d >> 6);
-                if (!b && !wp && !wd) continue;
-                uint64_t* xw = Xs + (size_t)w * CK + k2;
-                uint64_t v = *xw;
-                if (b) v ^= L.colx[w];
-                if (wp) v &= ~bp;
-                if (wd) v = (v & ~bd) | (b ? bd : 0ull);
-                *xw = v;
-                if (b && w == 0) ++flips;
+                if ((L.prow[a2 >> 6] >> (a2 & 63)) & 1ull) {
+                    L.list[atomicAdd(&s_nf, 1)] = (uint16_t)k2;
+                } else {
+                    uint64_t* xw = Xs + (size_t)wdw * CK + k2;
+                    const uint64_t v = *xw;
+                    if (v & bd) *xw = v & ~bd;
+                }
             }
-            if (flips) atomicAdd(&s_flip, flips);
             __syncthreads();
-            // read and write of the later columns that flip, one word each for the rest
-            W.bytes += (long long)s_flip * NB * 16 + (long long)rest * 2 * 16;
+            const int nf = s_nf;
+            for (int id0 = tid; id0 < nf * NB; id0 += 4 * kBatchThreads) {
+                uint64_t v[4];
+                uint64_t* xw[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int id = id0 + u * kBatchThreads;
+                    xw[u] = nullptr;
+                    v[u] = 0;
+                    if (id < nf * NB) {
+                        const int w = id / nf, j = id - w * nf;
+                        xw[u] = Xs + (size_t)w * CK + L.list[j];
+                        v[u] = *xw[u] ^ L.colx[w];
+                        if (w == wdw) v[u] |= bd;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (xw[u]) *xw[u] = v[u];
+            }
+            __syncthreads();
+            // read and write of every word of the flipping columns, one word of the others
+            W.bytes += (long long)nf * NB * 16 + (long long)(rest - nf) * 16;
         }
     } else {
         const int nl = batch_list(L.colx, 0, Wc, -1, -1, L.list, L.s_int + 1);
