@@ -155,6 +155,14 @@ void stab_program_destroy(stab_program *prog);
  * instruction counter to 0. */
 int stab_reset(stab_ctx *ctx, uint64_t seed, uint64_t first_shot);
 
+/* Set the RNG key of later draws to (seed, first_shot + b) for shot b, leaving the tableaux and
+ * the instruction counter as they are (a draw's counter is its instruction's index in
+ * everything the context ran since stab_create or stab_reset, so a stream run after this call
+ * draws as the same stream would at that position under the new key).  The random outcomes of
+ * Sec. 2.4 and the noise draws come from this key.  Host only.  Errors: STAB_EINVAL (NULL),
+ * STAB_EDEVICE (poisoned context). */
+int stab_set_rng(stab_ctx *ctx, uint64_t seed, uint64_t first_shot);
+
 /* Host-only: validate an op stream and describe how it would be executed for n qubits and
  * `shots` shots, without touching a device.  out[0..nout) receives, in order: segments (runs of
  * gate/noise layers between measurement layers), measurement layers, gate layers, gates, noise

@@ -627,6 +627,15 @@ void stab_destroy(stab_ctx* ctx)
     delete ctx;
 }
 
+int stab_set_rng(stab_ctx* ctx, uint64_t seed, uint64_t first_shot)
+{
+    if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");
+    if (ctx->poisoned) return fail(STAB_EDEVICE, "context poisoned by an earlier device error");
+    ctx->seed = seed;
+    ctx->first_shot = first_shot;
+    return STAB_OK;
+}
+
 int stab_reset(stab_ctx* ctx, uint64_t seed, uint64_t first_shot)
 {
     if (!ctx) return fail(STAB_EINVAL, "ctx is NULL");

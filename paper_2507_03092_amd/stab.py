@@ -32,7 +32,7 @@ EXPORTS = ("stab_max_qubits", "stab_tableau_bytes", "stab_create", "stab_destroy
            "stab_commute", "stab_server_request_bytes", "stab_server_create", "stab_server_destroy",
            "stab_server_program", "stab_server_program_records", "stab_server_submit", "stab_server_step",
            "stab_server_poll", "stab_server_records", "stab_server_result", "stab_server_stats",
-           "stab_server_set_lane", "stab_server_cancel",
+           "stab_server_set_lane", "stab_server_cancel", "stab_set_rng",
            "stab_last_error")
 PLAN_FIELDS = ("segments", "measurement_layers", "gate_layers", "gates", "noise_instructions",
                "noise_units", "records", "max_layer")
@@ -109,6 +109,7 @@ def lib():
         "stab_server_stats": (C.c_int, [P, P, I32]),
         "stab_server_set_lane": (C.c_int, [P, I32, I32]),
         "stab_server_cancel": (C.c_int, [P, I64]),
+        "stab_set_rng": (C.c_int, [P, U64, U64]),
         "stab_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -236,6 +237,10 @@ class Context:
 
     def reset(self, seed: int, first_shot: int = 0) -> None:
         _check(lib().stab_reset(self.h, seed, first_shot))
+
+    def set_rng(self, seed: int, first_shot: int = 0) -> None:
+        """Key of later draws (stab_set_rng); the tableaux and the instruction counter stay."""
+        _check(lib().stab_set_rng(self.h, seed, first_shot))
 
     def set_timing(self, enable: bool, kernels=None) -> None:
         """Time every kernel (kernels=None) or the named ones, with HIP events on the stream."""

@@ -280,6 +280,7 @@ def test_server_argument_errors_without_gpu(L):
     assert L.stab_server_create(null, 1 << 20, null, C.byref(out)) == stab.EINVAL
     assert L.stab_server_create(C.c_void_p(4096 + 8), 1 << 20, null, C.byref(out)) == stab.EINVAL  # misaligned
     assert L.stab_server_set_lane(null, 0, stab.LANE_SHARED) == stab.EINVAL
+    assert L.stab_set_rng(null, 1, 0) == stab.EINVAL
     assert L.stab_server_cancel(null, 1) == stab.EINVAL
     assert L.stab_server_step(null, None) == stab.EINVAL
     assert L.stab_server_poll(null, None, 0) == stab.EINVAL

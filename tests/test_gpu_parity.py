@@ -135,6 +135,43 @@ def test_incremental_calls_match_one_stream(stab):
         assert np.array_equal(x, tx[s]) and np.array_equal(z, tz[s]) and np.array_equal(r, tr[s])
 
 
+def _concat(a, b):
+    c = Cc.Circuit(n=a.n)
+    for part in (a, b):
+        c.kinds += list(part.kinds)
+        c.ntargets += list(part.ntargets)
+        c.thresholds += list(part.thresholds)
+        c.targets += list(part.targets)
+    return c
+
+
+def test_set_rng_rekeys_later_draws(stab):
+    """stab_set_rng after a draw-free prefix run under another key: the rest draws exactly as
+    the whole stream under the new key (same instruction counter), shot offsets included; and
+    the tableaux are those of the whole stream."""
+    n, shots = 36, 5
+    prefix = Cc.Circuit(n=n)
+    prefix.gate(Cc.H, list(range(0, n, 3)))
+    prefix.gate(Cc.CX, [q for i in range(0, n - 1, 3) for q in (i, i + 1)])
+    prefix.gate(Cc.S, list(range(1, n, 4)))
+    rest = Cc.random_clifford_measure(n, depth=8, seed=21, p_meas=0.3, noise=0.03)
+    whole = _concat(prefix, rest)
+    want, (tx, tz, tr) = O.run(whole, shots, 404, want_tableau=True)
+    ctx = stab.Context(n, shots, mode="shared", seed=7)
+    ctx.apply_layer(prefix)
+    ctx.set_rng(404)
+    got = ctx.run(rest)
+    assert np.array_equal(got, want)
+    for s in range(shots):
+        x, z, r = ctx.get_tableau(s)
+        assert np.array_equal(x, tx[s]) and np.array_equal(z, tz[s]) and np.array_equal(r, tr[s])
+    # a shot offset: shots 0..4 of this context are shots 3..7 of the whole stream's key
+    ctx2 = stab.Context(n, shots, mode="full", seed=1)
+    ctx2.apply_layer(prefix)
+    ctx2.set_rng(404, first_shot=3)
+    assert np.array_equal(ctx2.run(rest), O.run(whole, shots + 3, 404)[3:])
+
+
 def test_compiled_program_reexecution_and_determinism(stab):
     circ, lay = Cc.surface_code_memory(5, 5, 0.01)
     ctx = stab.Context(circ.n, 50, mode="shared", seed=8)
