@@ -255,7 +255,7 @@ def surface_cpu_baseline(r: dict, log) -> dict:
     circ, seed, shots, rec = r["circ"], r["seed"], r["shots"], r["rec"]
     if r["workload"] == "surface_d71":
         ins, tg = circ.arrays()
-        k = int(np.nonzero(ins["kind"] == Cc.MR)[0][1]) + 1            # through round 2's MR
+        k = int(np.nonzero(ins["kind"] == Cc.MR)[0][1]) + 1            # through syndrome round 2's MR
         sc = Cc.PackedCircuit(circ.n, ins[:k].copy(), tg[:int(ins["ntargets"][:k].sum())].copy())
         srounds, one_shots = 2, 1
         desc = "the first 2 rounds of the d=71 op stream (round 1 holds the random X-ancilla measurements)"

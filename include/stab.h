@@ -51,7 +51,7 @@ extern "C" {
 #define STAB_EINVAL    -1   /* bad argument or malformed op stream */
 #define STAB_ENOMEM    -2   /* buffer too small or device allocation failed */
 #define STAB_EDEVICE   -3   /* HIP runtime error (context poisoned) */
-#define STAB_ERANGE    -4   /* size outside what this build supports */
+#define STAB_ERANGE    -4   /* size outside what the library supports */
 #define STAB_EINTERNAL -5   /* an internal consistency check failed on the device */
 
 /* instruction kinds */
@@ -76,7 +76,7 @@ typedef struct stab_instr {
 
 typedef struct stab_ctx stab_ctx;
 
-/* Largest qubit count this build supports: 10240 (160 64-bit words of x or z per row; the
+/* Largest qubit count the library supports: 10240 (160 64-bit words of x or z per row; the
  * random-measurement kernel keeps a target's column, 2 * 160 band words, in the registers of
  * one wave, and half a band of the tableau must fit in the 160 KB of LDS of one compute
  * unit). */
