@@ -190,7 +190,10 @@ class Context:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown
+            pass
 
     def compile(self, circ: _circ.Circuit) -> Program:
         instr, tg = circ.arrays()
