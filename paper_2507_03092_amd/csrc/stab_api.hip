@@ -298,6 +298,14 @@ int tcollect(stab_ctx* ctx)
     return STAB_OK;
 }
 
+// The chain and the replay instantiated for the row's words per lane.
+using ChainFn = decltype(&k_chain<1>);
+static ChainFn chain_kernel(int Wc)
+{
+    const int wpl = (Wc + 63) / 64;
+    return wpl <= 1 ? k_chain<1> : wpl == 2 ? k_chain<2> : wpl == 3 ? k_chain<3> : k_chain<4>;
+}
+
 // The replay instantiated for the row's words per lane.
 using ReplayFn = decltype(&k_replay<1>);
 static ReplayFn replay_kernel(int Wc)
@@ -555,7 +563,10 @@ int create_ctx(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t f
         return fail(STAB_ERANGE, "a half-band of the tableau does not fit in this device's LDS");
     }
     (void)hipFuncSetAttribute((const void*)k_segment, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_chain<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_chain<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_chain<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_chain<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_det, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -946,7 +957,7 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
             // a layer where nothing ran in an earlier execution from |0...0>: the next four
             // launches would return at once
             if (!use_mran || P->mran[st.second]) {
-            TIMED(ctx, 5, (k_chain<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+            TIMED(ctx, 5, (chain_kernel(g.Wc)<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
                               m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,

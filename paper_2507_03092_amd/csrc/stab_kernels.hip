@@ -159,6 +159,64 @@ __device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int j, int lane)
     }
 }
 
+// Sum over the wave, every lane active: DPP and permlane steps within each 32-lane half, then the
+// two halves' totals read out, so the result is uniform.
+__device__ __forceinline__ int wave_sum_uniform(int v, int lane)
+{
+#pragma unroll
+    for (int j = 1; j <= 16; j <<= 1) v += (int)lane_xor32((uint32_t)v, j, lane);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
+}
+
+// Sorted rows as (64-row word, bit mask) runs.  rows[64 h + lane] belongs to lane `lane` of half
+// h (nrows <= 128); a lane heads a run when its row starts a new word or the half, so one word
+// may head a run in both halves, with disjoint masks.  hm[h]: the head lanes; the head's wv[h]
+// and mv[h] are its run's word and mask (a segmented OR over the run's lanes).  Whole wave.
+__device__ __forceinline__ void row_runs(const int* rows, int nrows, int lane, uint64_t* hm, int* wv, uint64_t* mv)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        hm[h] = 0ull;
+        wv[h] = 0;
+        mv[h] = 0ull;
+        const int nv = min(nrows - 64 * h, 64);
+        if (nv <= 0) continue;
+        const int r = 64 * h + lane;
+        const bool valid = lane < nv;
+        const int row = valid ? rows[r] : 0;
+        const int w = row >> 6;
+        const bool head = valid && (lane == 0 || (rows[r - 1] >> 6) != w);
+        const uint64_t H = __ballot(head);
+        const uint64_t after = lane < 63 ? H >> (lane + 1) : 0ull;
+        const int end = after ? lane + 1 + ctz64(after) : nv;
+        uint64_t acc = valid ? 1ull << (row & 63) : 0ull;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t v = shfl_u64(acc, lane + off < 64 ? lane + off : lane);
+            if (lane + off < end) acc |= v;
+        }
+        hm[h] = H;
+        wv[h] = w;
+        mv[h] = acc;
+    }
+}
+
+// f(word, mask) for every run of row_runs, in a scalar loop over the head lanes (the words and
+// masks are read out of their lanes whatever the exec mask, so f may run under a lane mask).
+template <class F>
+__device__ __forceinline__ void for_runs(const uint64_t* hm, const int* wv, const uint64_t* mv, F f)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint64_t H = hm[h];
+        while (H) {
+            const int l = ctz64(H);
+            H &= H - 1;
+            f(__builtin_amdgcn_readlane(wv[h], l), readlane_u64(mv[h], l));
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // init: |0...0> -- destabilizer i = +X_i, stabilizer i = +Z_i, all signs 0.
 // ------------------------------------------------------------------------------------------
@@ -808,53 +866,89 @@ __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
     return (int)(u0 >> 63);
 }
 
+// An empty asm that takes v in a VGPR and may change it: the compiler waits for v's load here
+// (not at a later first use that some paths skip) and keeps work that uses v below this point.
+__device__ __forceinline__ void settle(uint64_t& v) { asm volatile("" : "+v"(v)); }
+
 // rowsum(i, p) for rows[r], r = r0, r0 + stride, ... < nrows, pivot row words in registers
-// (lane owns column words lane + 64 t).  Sign r_i <- r_i ^ r_p ^ (i-power / 2).  Loads of 4 rows
-// are issued together.
-__device__ __forceinline__ void rowsum_rows(const ChainCtx& c, const uint64_t* xp, const uint64_t* zp, int rsp,
-                                            const int* rows, int nrows, int r0, int stride, int lane)
+// (lane owns column words lane + 64 t, WPL = ceil(Wc / 64)).  Sign r_i <- r_i ^ r_p ^
+// (i-power / 2).  Every batch loads RB rows (the last row again past nrows, a stabilizer row
+// when there is none) and uses every loaded word, so the number of loads in flight never
+// depends on the path taken and no load is left pending: the first batch's loads are issued
+// before anything waits for the pivot row, whose loads (and the caller's pend[] words, loaded
+// before it) are settled right after.  r_p = bit rbit of pend[0].
+template <int WPL, int NP>
+__device__ __forceinline__ void rowsum_rows(const ChainCtx& c, uint64_t* xp, uint64_t* zp, uint64_t (&pend)[NP],
+                                            int rbit, const int* rows, int nrows, int r0, int stride, int lane)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, RS = g.RS;
-    for (int rb = r0; rb < nrows; rb += 4 * stride) {
-        // 4 rows in flight; no load depends on the pivot row (lanes past Wc read word 0 and
-        // write nothing), so they overlap its load
-        uint64_t rx[4][kMaxWordsPerLane], rz[4][kMaxWordsPerLane];
+    // rows in flight: four, three when a lane holds three or more words of a row
+    constexpr int RB = WPL <= 2 ? 4 : 3;
+    uint64_t rx[RB][WPL], rz[RB][WPL];
+    auto row_of = [&](int r) { return nrows > 0 ? rows[min(r, nrows - 1)] : g.NR; };
+    auto load = [&](int rb) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = rb + u * stride;
-            const uint64_t* row = c.tb + (size_t)rows[min(r, nrows - 1)] * RS;
+        for (int u = 0; u < RB; ++u) {
+            const uint64_t* row = c.tb + (size_t)row_of(rb + u * stride) * RS;
 #pragma unroll
-            for (int t = 0; t < kMaxWordsPerLane; ++t) {
-                const int cw = lane + 64 * t < Wc ? lane + 64 * t : 0;
+            for (int t = 0; t < WPL; ++t) {
+                // (lanes past Wc read the last word and hold a zero pivot word)
+                const int cw = min(lane + 64 * t, Wc - 1);
                 rx[u][t] = row[cw];
                 rz[u][t] = row[Wc + cw];
             }
         }
+    };
+    load(r0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+    for (int t = 0; t < WPL; ++t) {
+        settle(xp[t]);
+        settle(zp[t]);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) settle(pend[i]);
+    const int rsp = (int)((pend[0] >> rbit) & 1ull);
+    for (int rb = r0;;) {
+        // only the i-power mod 4 matters: byte u of P sums row u's per-lane residues (at most
+        // 64 x 3), so one wave sum serves the batch
+        int P = 0;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
             const int r = rb + u * stride;
-            if (r < nrows) {
-                const int i = rows[r];
-                uint64_t* row = c.tb + (size_t)i * RS;
-                int G = 0;
+            int G = 0;
 #pragma unroll
-                for (int t = 0; t < kMaxWordsPerLane; ++t) {
+            for (int t = 0; t < WPL; ++t) G += gsum(xp[t], zp[t], rx[u][t], rz[u][t]);
+            if (r < nrows) {
+                uint64_t* row = c.tb + (size_t)rows[r] * RS;
+#pragma unroll
+                for (int t = 0; t < WPL; ++t) {
                     const int cw = lane + 64 * t;
                     if (cw < Wc && (xp[t] | zp[t])) {
-                        G += gsum(xp[t], zp[t], rx[u][t], rz[u][t]);
                         row[cw] = rx[u][t] ^ xp[t];
                         row[Wc + cw] = rz[u][t] ^ zp[t];
                     }
                 }
-                G = wave_sum(G);
-                if (lane == 0) {
+                P |= (G & 3) << (8 * u);
+            }
+        }
+        P = wave_sum_uniform(P, lane);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int r = rb + u * stride;
+                if (r < nrows) {
+                    const int G = (P >> (8 * u)) & 3;
+                    const int i = rows[r];
                     if (G & 1) atomicOr(c.err, 4);
                     const uint64_t flip = (uint64_t)((rsp ^ (G >> 1)) & 1) << (i & 63);
                     if (flip) atomicXor((unsigned long long*)&c.rs[i >> 6], (unsigned long long)flip);
                 }
             }
         }
+        rb += RB * stride;
+        if (rb >= nrows) break;
+        load(rb);
     }
 }
 
@@ -866,21 +960,21 @@ __device__ __forceinline__ void rowsum_rows(const ChainCtx& c, const uint64_t* x
 // target whose x column is kept).  When `aff` is given (wide batches), the per-target column
 // work is appended there as {target, 0, batch index j} for the whole block to apply; it is
 // done in-wave otherwise or when the list is full.
-__device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const uint64_t* xp,
+template <int WPL>
+__device__ void random_epilogue(const ChainCtx& c, int k, int a, int ip, int rsp, const uint64_t* xp,
                                 const uint64_t* zp, const int* rows, int nrows, int lane,
                                 int* aff = nullptr, int* aff_n = nullptr, int j = 0,
                                 bool have_rd0 = false, uint64_t rd0 = 0, uint64_t rd1 = 0,
-                                int out0 = -1, int out1 = -1)
+                                int out0 = 0, int out1 = 0)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
-    const int a = c.tq[k];
     uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
     const int wq = ip >> 6;
     const uint64_t bq = 1ull << (ip & 63);
     uint64_t* lrow = c.lrow + (size_t)k * RS;
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+    for (int t = 0; t < WPL; ++t) {
         const int cw = lane + 64 * t;
         if (cw < Wc) {
             lrow[cw] = xp[t];
@@ -893,57 +987,48 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         *c.ran = 1;
         atomicAnd((unsigned long long*)&c.rs[Wr + wq], ~(unsigned long long)bq);
     }
-    for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+    // the rowsum rows as word runs, read out as scalars by every loop below
+    uint64_t hm[2], mv[2];
+    int wv[2];
+    row_runs(rows, nrows, lane, hm, wv, mv);
+    // 64 shots: rw = each shot's pivot sign word, out = its outcome draw
+    auto shots = [&](int b0, uint64_t rw, int out) {
         const int b = b0 + lane;
-        bool rdp = false;
-        if (b < g.bpc) {
-            const int gb = c.s * g.bpc + b;
-            uint64_t* rdb = c.rd + (size_t)gb * NB;
-            // (the first 128 shots' pivot sign words were read with the pivot row)
-            const uint64_t rw = (have_rd0 && b0 == 0) ? rd0 : (have_rd0 && b0 == 64) ? rd1 : rdb[Wr + wq];
-            rdp = ((rw >> (ip & 63)) & 1ull) != 0;
-            if (rdp) {
-                uint64_t m = 0;
-                int wc = -1;
-                for (int r = 0; r < nrows; ++r) {
-                    const int w = rows[r] >> 6;
-                    if (w != wc) {
-                        if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
-                        wc = w;
-                        m = 0;
-                    }
-                    m |= 1ull << (rows[r] & 63);
-                }
-                if (m) atomicXor((unsigned long long*)&rdb[wc], (unsigned long long)m);
-            }
-            // (the first 128 shots' draws may have been made while the rows were loading)
-            const int out = (b0 == 0 && out0 >= 0) ? out0 : (b0 == 64 && out1 >= 0) ? out1 : outcome_bit(c, k, gb);
-            atomicAnd((unsigned long long*)&rdb[Wr + wq], ~(unsigned long long)bq);
-            if (out) atomicOr((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
+        const bool in = b < g.bpc;
+        const int gb = c.s * g.bpc + min(b, g.bpc - 1);
+        uint64_t* rdb = c.rd + (size_t)gb * NB;
+        const bool rdp = in && ((rw >> (ip & 63)) & 1ull) != 0;
+        if (in) {
+            // the pivot's sign becomes the outcome (no rowsum row is the pivot)
+            if ((int)rdp != out) atomicXor((unsigned long long*)&rdb[Wr + wq], (unsigned long long)bq);
             c.obuf[(size_t)gb * K + k] = (uint8_t)out;
         }
+        for_runs(hm, wv, mv, [&](int w, uint64_t m) {
+            if (rdp) atomicXor((unsigned long long*)&rdb[w], (unsigned long long)m);
+        });
         const uint64_t m = __ballot(rdp);
         if (lane == 0) c.lrd[(size_t)k * c.nrdw + (b0 >> 6)] = m;
+    };
+    int b0 = 0;
+    if (have_rd0) {
+        // the first 128 shots' sign words and draws came with the pivot row: no load waits here
+        shots(0, rd0, out0);
+        if (g.bpc > 64) shots(64, rd1, out1);
+        b0 = 128;
+    }
+    for (; b0 < g.bpc; b0 += 64) {
+        const int gb = c.s * g.bpc + min(b0 + lane, g.bpc - 1);
+        shots(b0, c.rd[(size_t)gb * NB + Wr + wq], outcome_bit(c, k, gb));
     }
     // x columns of pending targets: rows with x at the pivot's qubits flip there; p's x clears
     auto upkeep = [&](int k2) {
         unsigned long long* X2 = (unsigned long long*)(c.X + k2);
-        uint64_t m = 0;
-        int wc = -1;
-        for (int r = 0; r <= nrows; ++r) {
-            const int w = r < nrows ? rows[r] >> 6 : -2;
-            if (w != wc) {
-                if (m) atomicXor(&X2[(size_t)wc * K], (unsigned long long)m);
-                wc = w;
-                m = 0;
-            }
-            if (r < nrows) m |= 1ull << (rows[r] & 63);
-        }
+        for_runs(hm, wv, mv, [&](int w, uint64_t m) { atomicXor(&X2[(size_t)w * K], (unsigned long long)m); });
         atomicAnd(&X2[(size_t)(Wr + wq) * K], ~(unsigned long long)bq);
     };
     if (aff) {
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        for (int t = 0; t < WPL; ++t) {
             const int cw = lane + 64 * t;
             if (cw >= Wc) continue;
             uint64_t bits = xp[t];
@@ -967,7 +1052,7 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         // this wave is the only writer of target k's list: slots by ballot rank, no atomics
         int np = 0;
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        for (int t = 0; t < WPL; ++t) {
             const int cw = lane + 64 * t;
             uint64_t bits = cw < Wc ? xp[t] : 0ull;
             while (__ballot(bits != 0ull)) {
@@ -993,7 +1078,7 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
         }
     }
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+    for (int t = 0; t < WPL; ++t) {
         const int cw = lane + 64 * t;
         if (cw < Wc) {
             gp[cw] = 0ull;
@@ -1009,10 +1094,11 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int ip, int rsp, const
 }
 
 // Load one row's words for this lane (from global or LDS).
+template <int WPL>
 __device__ __forceinline__ void load_row_lane(const uint64_t* row, int Wc, int lane, uint64_t* x, uint64_t* z)
 {
 #pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+    for (int t = 0; t < WPL; ++t) {
         const int cw = lane + 64 * t;
         const bool in = cw < Wc;
         x[t] = in ? row[cw] : 0ull;
@@ -1021,31 +1107,38 @@ __device__ __forceinline__ void load_row_lane(const uint64_t* row, int Wc, int l
 }
 
 // One wave: the whole random measurement of target k (pivot stabilizer index ip).
+template <int WPL>
 __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
 {
     const Geom& g = c.g;
-    // the pivot row, its signs and the first rowsum rows are all read at once
-    uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
-    const uint64_t* prow = c.tb + (size_t)(g.NR + ip) * g.RS;
-#pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t) {
-        const int cw = lane + 64 * t < g.Wc ? lane + 64 * t : 0;
-        xp[t] = prow[cw];
-        zp[t] = prow[g.Wc + cw];
-    }
+    // the pivot's sign words (first 128 shots), its rs bit and the target's qubit are read
+    // first, then the pivot row: waiting for the row also covers them
     const uint64_t rd0 = lane < g.bpc ? c.rd[(size_t)(c.s * g.bpc + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
     const uint64_t rd1 =
         lane + 64 < g.bpc ? c.rd[(size_t)(c.s * g.bpc + 64 + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
-    const int rsp = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
+    const uint64_t rsw = c.rs[g.Wr + (ip >> 6)];
+    const int a = c.tq[k];
+    uint64_t xp[WPL], zp[WPL];
+    const uint64_t* prow = c.tb + (size_t)(g.NR + ip) * g.RS;
+    // (lanes past Wc load nothing and hold zeros, so nothing waits for the row before the
+    // rowsum rows' loads are issued)
+#pragma unroll
+    for (int t = 0; t < WPL; ++t) {
+        xp[t] = zp[t] = 0ull;
+        if (lane + 64 * t < g.Wc) {
+            xp[t] = prow[lane + 64 * t];
+            zp[t] = prow[g.Wc + lane + 64 * t];
+        }
+    }
     // the outcome draws depend on the key and the target only: made while the loads are in flight
     const int gb0 = c.s * g.bpc + lane;
     const int out0 = lane < g.bpc ? outcome_bit(c, k, gb0) : 0;
     const int out1 = lane + 64 < g.bpc ? outcome_bit(c, k, gb0 + 64) : 0;
-#pragma unroll
-    for (int t = 0; t < kMaxWordsPerLane; ++t)
-        if (lane + 64 * t >= g.Wc) xp[t] = zp[t] = 0ull;
-    rowsum_rows(c, xp, zp, rsp, rows, nrows, 0, 1, lane);
-    random_epilogue(c, k, ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true, rd0, rd1, out0, out1);
+    uint64_t pend[4] = {rsw, rd0, rd1, (uint64_t)(uint32_t)a};
+    rowsum_rows<WPL>(c, xp, zp, pend, ip & 63, rows, nrows, 0, 1, lane);
+    const int rsp = (int)((pend[0] >> (ip & 63)) & 1ull);
+    random_epilogue<WPL>(c, k, (int)(uint32_t)pend[3], ip, rsp, xp, zp, rows, nrows, lane, nullptr, nullptr, 0, true,
+                         pend[1], pend[2], out0, out1);
 }
 
 // Whole block: one target with many stabilizer rows (dense tableaux).  Called by every thread.
@@ -1121,7 +1214,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
                 row[j] = xi ^ xp;
                 row[Wc + j] = zi ^ zp;
             }
-            G = wave_sum(G);
+            G = wave_sum_uniform(G, lane);
             if (lane == 0) {
                 if (G & 1) atomicOr(c.err, 4);
                 if (G & 2) atomicOr((unsigned long long*)&sC[w], 1ull << bit);
@@ -1183,6 +1276,10 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
     __syncthreads();
 }
 
+// WPL = column words per lane of a row, ceil(Wc / 64): the one-wave paths keep that many words
+// of the pivot and of four rows in registers, so narrow tableaux get a kernel without the
+// registers the widest one needs.
+template <int WPL>
 __global__ void __launch_bounds__(512)
 k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
@@ -1488,43 +1585,36 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
                 const int ip = spiv[wpos[selpos[tid]]];
                 s_rsp[tid] = (int)((c.rs[g.Wr + (ip >> 6)] >> (ip & 63)) & 1ull);
             }
-            // word lists of the rowsum rows (rows are sorted): a run head starts a word
-            for (int j = 0; j < nsel; ++j) {
-                const int sl = wpos[selpos[j]], cnt = scnt[sl];
-                const int* rw = srows + sl * kRCap;
-                for (int r = tid; r < cnt; r += nt) {
-                    const int w = rw[r] >> 6;
-                    const bool head = r == 0 || (rw[r - 1] >> 6) != w;
-                    if (head) {
-                        // position = number of heads before r
-                        int pos = 0;
-                        for (int q = 1; q <= r; ++q) pos += ((rw[q] >> 6) != (rw[q - 1] >> 6)) ? 1 : 0;
-                        uint64_t m = 0;
-                        for (int q = r; q < cnt && (rw[q] >> 6) == w; ++q) m |= 1ull << (rw[q] & 63);
-                        wlw[j * kRCap + pos] = w;
-                        wlm[j * kRCap + pos] = m;
+            // word lists of the rowsum rows: wave j writes target j's runs
+            for (int j = wave; j < nsel; j += nwaves) {
+                const int sl = wpos[selpos[j]];
+                uint64_t hm[2], mv[2];
+                int wv[2];
+                row_runs(srows + sl * kRCap, scnt[sl], lane, hm, wv, mv);
+                const int n0 = __popcll(hm[0]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if ((hm[h] >> lane) & 1ull) {
+                        const int pos = (h ? n0 : 0) + __popcll(hm[h] & ((1ull << lane) - 1ull));
+                        wlw[j * kRCap + pos] = wv[h];
+                        wlm[j * kRCap + pos] = mv[h];
                     }
-                    if (r == cnt - 1) {
-                        int nh = 1;
-                        for (int q = 1; q < cnt; ++q) nh += ((rw[q] >> 6) != (rw[q - 1] >> 6)) ? 1 : 0;
-                        s_wln[j] = nh;
-                    }
-                }
-                if (tid == 0 && cnt == 0) s_wln[j] = 0;
+                if (lane == 0) s_wln[j] = n0 + __popcll(hm[1]);
             }
             __syncthreads();
             for (int j = 0; j < nsel; ++j) {
                 const int sl = wpos[selpos[j]];
                 if (wave >= scnt[sl]) continue;
-                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
-                load_row_lane(wideP + j * g.RS, g.Wc, lane, xp, zp);
-                rowsum_rows(c, xp, zp, s_rsp[j], srows + sl * kRCap, scnt[sl], wave, nwaves, lane);
+                uint64_t xp[WPL], zp[WPL];
+                load_row_lane<WPL>(wideP + j * g.RS, g.Wc, lane, xp, zp);
+                uint64_t pend[1] = {(uint64_t)s_rsp[j]};
+                rowsum_rows<WPL>(c, xp, zp, pend, 0, srows + sl * kRCap, scnt[sl], wave, nwaves, lane);
             }
             for (int j = wave; j < nsel; j += nwaves) {
                 const int sl = wpos[selpos[j]];
-                uint64_t xp[kMaxWordsPerLane], zp[kMaxWordsPerLane];
-                load_row_lane(wideP + j * g.RS, g.Wc, lane, xp, zp);
-                random_epilogue(c, sk[sl], spiv[sl], s_rsp[j], xp, zp, srows + sl * kRCap, scnt[sl], lane,
+                uint64_t xp[WPL], zp[WPL];
+                load_row_lane<WPL>(wideP + j * g.RS, g.Wc, lane, xp, zp);
+                random_epilogue<WPL>(c, sk[sl], c.tq[sk[sl]], spiv[sl], s_rsp[j], xp, zp, srows + sl * kRCap, scnt[sl], lane,
                                 aff, &s_aff, j);
             }
             __syncthreads();
@@ -1549,7 +1639,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         } else {
             for (int j = wave; j < nsel; j += nwaves) {
                 const int sl = wpos[selpos[j]];
-                wave_random(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
+                wave_random<WPL>(c, sk[sl], spiv[sl], srows + sl * kRCap, scnt[sl], lane);
             }
         }
         __syncthreads();
