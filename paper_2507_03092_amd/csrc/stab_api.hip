@@ -35,7 +35,6 @@ int fail(int code, const std::string& msg)
 
 constexpr int kLdsBytes = 160 * 1024;     // LDS of one gfx950 compute unit
 constexpr int kSegThreads = 1024;
-constexpr int kChainThreads = 512;
 constexpr int kRedWords = 16;
 constexpr int kMaxShots = 65535;          // grid y dimension of the reset kernel
 constexpr int kReplayThreads = 512;
@@ -957,7 +956,7 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
             // a layer where nothing ran in an earlier execution from |0...0>: the next four
             // launches would return at once
             if (!use_mran || P->mran[st.second]) {
-            TIMED(ctx, 5, (chain_kernel(g.Wc)<<<g.S, kChainThreads, chain_lds, ctx->stream>>>(
+            TIMED(ctx, 5, (chain_kernel(g.Wc)<<<g.S, chain_threads((g.Wc + 63) / 64), chain_lds, ctx->stream>>>(
                               g, ctx->tab, ctx->rs, ctx->rd, Xcol, Zcol, K2, cls, P->d_mtq + m.tq_begin,
                               (int*)ctx->pend.p, ctx->seed, ctx->first_shot, base + m.instr,
                               m.pos_base, plog_p, plog_row, plog_rs, plog_rd, ran, (uint16_t*)ctx->plist.p,

@@ -866,6 +866,10 @@ __device__ __forceinline__ int outcome_bit(const ChainCtx& c, int k, int b)
     return (int)(u0 >> 63);
 }
 
+// v is the same in every lane (the compiler cannot see that for values read from LDS): keeping
+// it in a scalar register makes loops over it scalar loops.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // An empty asm that takes v in a VGPR and may change it: the compiler waits for v's load here
 // (not at a later first use that some paths skip) and keeps work that uses v below this point.
 __device__ __forceinline__ void settle(uint64_t& v) { asm volatile("" : "+v"(v)); }
@@ -873,16 +877,20 @@ __device__ __forceinline__ void settle(uint64_t& v) { asm volatile("" : "+v"(v))
 // rowsum(i, p) for rows[r], r = r0, r0 + stride, ... < nrows, pivot row words in registers
 // (lane owns column words lane + 64 t, WPL = ceil(Wc / 64)).  Sign r_i <- r_i ^ r_p ^
 // (i-power / 2).  Every batch loads RB rows (the last row again past nrows, a stabilizer row
-// when there is none) and uses every loaded word, so the number of loads in flight never
-// depends on the path taken and no load is left pending: the first batch's loads are issued
-// before anything waits for the pivot row, whose loads (and the caller's pend[] words, loaded
-// before it) are settled right after.  r_p = bit rbit of pend[0].
+// when there is none) and settles every loaded word, so the number of loads in flight never
+// depends on the path taken and no load is left pending for a later loop to wait on: the
+// first batch's loads are issued before anything waits for the pivot row, whose loads (and the
+// caller's pend[] words, loaded before it) are settled right after.  r_p = bit rbit of pend[0].
 template <int WPL, int NP>
 __device__ __forceinline__ void rowsum_rows(const ChainCtx& c, uint64_t* xp, uint64_t* zp, uint64_t (&pend)[NP],
                                             int rbit, const int* rows, int nrows, int r0, int stride, int lane)
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, RS = g.RS;
+    nrows = uni(nrows);
+    r0 = uni(r0);
+    stride = uni(stride);
+    rbit = uni(rbit);
     // rows in flight: four, three when a lane holds three or more words of a row
     constexpr int RB = WPL <= 2 ? 4 : 3;
     uint64_t rx[RB][WPL], rz[RB][WPL];
@@ -910,6 +918,14 @@ __device__ __forceinline__ void rowsum_rows(const ChainCtx& c, uint64_t* xp, uin
     for (int i = 0; i < NP; ++i) settle(pend[i]);
     const int rsp = (int)((pend[0] >> rbit) & 1ull);
     for (int rb = r0;;) {
+        // the batch's words are taken here, whether or not a row is past nrows
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int t = 0; t < WPL; ++t) {
+                settle(rx[u][t]);
+                settle(rz[u][t]);
+            }
         // only the i-power mod 4 matters: byte u of P sums row u's per-lane residues (at most
         // 64 x 3), so one wave sum serves the batch
         int P = 0;
@@ -969,6 +985,12 @@ __device__ void random_epilogue(const ChainCtx& c, int k, int a, int ip, int rsp
 {
     const Geom& g = c.g;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
+    k = uni(k);
+    a = uni(a);
+    ip = uni(ip);
+    rsp = uni(rsp);
+    nrows = uni(nrows);
+    j = uni(j);
     uint64_t* gp = c.tb + (size_t)(g.NR + ip) * RS;
     const int wq = ip >> 6;
     const uint64_t bq = 1ull << (ip & 63);
@@ -1111,6 +1133,9 @@ template <int WPL>
 __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, int nrows, int lane)
 {
     const Geom& g = c.g;
+    k = uni(k);
+    ip = uni(ip);
+    nrows = uni(nrows);
     // the pivot's sign words (first 128 shots), its rs bit and the target's qubit are read
     // first, then the pivot row: waiting for the row also covers them
     const uint64_t rd0 = lane < g.bpc ? c.rd[(size_t)(c.s * g.bpc + lane) * g.NB + g.Wr + (ip >> 6)] : 0ull;
@@ -1145,7 +1170,7 @@ __device__ void wave_random(const ChainCtx& c, int k, int ip, const int* rows, i
 __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int nt)
 {
     const Geom& g = c.g;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int lane = tid & 63, wave = uni(tid >> 6), nwaves = nt >> 6;
     const int Wc = g.Wc, Wr = g.Wr, NB = g.NB, RS = g.RS, K = c.K;
     const int nrdw = c.nrdw;
     uint64_t* rowp = sm;
@@ -1168,7 +1193,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
         if (v) atomicMin(&s_piv, w * 64 + ctz64(v));
     }
     __syncthreads();
-    const int ip = s_piv;
+    const int ip = uni(s_piv);
     if (ip == INT_MAX) {
         // deterministic now: reduced after the layer on the final tableau
         if (tid == 0) c.cl[k] = -2;
@@ -1195,7 +1220,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
         const uint64_t bit = (c.rd[(size_t)(c.s * g.bpc + b) * NB + Wr + wq] >> (ip & 63)) & 1ull;
         if (bit) atomicOr((unsigned long long*)&sRdp[b >> 6], 1ull << (b & 63));
     }
-    const int nnz = s_nnz;
+    const int nnz = uni(s_nnz);
     int idx = 0;
     for (int t = 0; t < nnz; ++t) {
         const int w = nz[t];
@@ -1227,7 +1252,7 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
     }
     __syncthreads();
     // signs of the rowsum rows, pending targets' x columns, the pivot log
-    const int rsp = s_rsp;
+    const int rsp = uni(s_rsp);
     for (int t = tid; t < nnz; t += nt) {
         const int w = nz[t];
         c.rs[Wr + w] ^= (rsp ? sM[w] : 0ull) ^ sC[w];
@@ -1276,11 +1301,13 @@ __device__ void block_solo(const ChainCtx& c, int k, uint64_t* sm, int tid, int 
     __syncthreads();
 }
 
-// WPL = column words per lane of a row, ceil(Wc / 64): the one-wave paths keep that many words
-// of the pivot and of four rows in registers, so narrow tableaux get a kernel without the
-// registers the widest one needs.
+// WPL = column words per lane of a row, ceil(Wc / 64) (= stabilizer bands per lane): the
+// one-wave paths keep that many words of the pivot and of a batch of rows in registers, so
+// narrow tableaux get a kernel without the registers the widest one needs, and room for twelve
+// waves instead of eight (more of a round's targets run at once).
+constexpr int chain_threads(int wpl) { return wpl == 1 ? 768 : 512; }
 template <int WPL>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(chain_threads(WPL))
 k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t* __restrict__ rd,
         uint64_t* __restrict__ Xcol, uint64_t* __restrict__ Zcol, int K,
         int* __restrict__ cls, const int* __restrict__ tq, int* __restrict__ pend, uint64_t seed, uint64_t first_shot, uint64_t instr, int pos_base,
@@ -1292,7 +1319,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     extern __shared__ uint64_t sm[];
     const int s = blk_x(g);
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int lane = tid & 63, wave = uni(tid >> 6), nwaves = nt >> 6;
     const ChainLds L = chain_lds_layout(g);
     int* owner = (int*)((char*)sm + L.owner);
     // window entries live in fixed slots; wpos[] lists the slots in op order
@@ -1418,7 +1445,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
     // a round can empty the window; the refill below brings in the next pending targets
     while (s_nwin > 0 || s_tail < npend) {
         ++rounds;
-        const int nwin = s_nwin;
+        const int nwin = uni(s_nwin);
         // ---- analysis: the first kAnalyze entries not yet analysed (new, or touched) ----
         if (wave == 0) {
             const bool un = lane < nwin && stype[wpos[lane]] == T_UNKNOWN;
@@ -1431,29 +1458,29 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
         // the stabilizer half of an entry's column (band Wr + lane + 64 u), all words at once;
         // a wave's next entry is read while it works on the current one (lanes past Wr read
         // band Wr and are masked)
-        const int na = s_na;
+        const int na = uni(s_na);
         auto load_col = [&](int a_i, uint64_t* cw) {
             const int kk = a_i < na ? sk[alist[a_i]] : 0;
 #pragma unroll
-            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+            for (int u = 0; u < WPL; ++u) {
                 const int w = lane + 64 * u;
                 cw[u] = c.X[(size_t)(g.Wr + (w < g.Wr ? w : 0)) * K + kk];
             }
         };
-        uint64_t cwn[kMaxStabBandsPerLane];
+        uint64_t cwn[WPL];
         if (wave < na) load_col(wave, cwn);
         for (int a_i = wave; a_i < na; a_i += nwaves) {
             const int sl = alist[a_i];
             const int k = sk[sl];
-            uint64_t cw[kMaxStabBandsPerLane];
+            uint64_t cw[WPL];
 #pragma unroll
-            for (int u = 0; u < kMaxStabBandsPerLane; ++u) cw[u] = lane + 64 * u < g.Wr ? cwn[u] : 0ull;
+            for (int u = 0; u < WPL; ++u) cw[u] = lane + 64 * u < g.Wr ? cwn[u] : 0ull;
             if (a_i + nwaves < na) load_col(a_i + nwaves, cwn);
             // pivot = first set bit in band order, the other set bits are the rowsum rows
             // (ascending); the few nonzero words are read out one by one with scalar loops
             int pv = INT_MAX, cnt = 0;
 #pragma unroll
-            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+            for (int u = 0; u < WPL; ++u) {
                 uint64_t lanes = __ballot(cw[u] != 0ull);
                 while (lanes) {
                     const int l = ctz64(lanes);
@@ -1495,7 +1522,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const uint64_t m = __ballot(keep);
             const int nkeep = __popcll(m);
             const uint64_t usedmask = wave_or(keep ? (1ull << sl) : 0ull);
-            const int tail = s_tail;
+            const int tail = uni(s_tail);
             const int nnew = min(kWin - nkeep, npend - tail);
             const uint64_t freem = ~usedmask;
             const bool fr = (freem >> lane) & 1ull;                   // lane = a free slot
@@ -1515,7 +1542,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             }
         }
         __syncthreads();
-        const int nw = s_nwin;
+        const int nw = uni(s_nwin);
         if (nw == 0) break;
         // ---- selection, by wave 0 with one lane per window position t: only analysed
         // entries before the first unknown or big one are eligible; an eligible entry runs iff
@@ -1562,8 +1589,8 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             }
         }
         __syncthreads();
-        const int bar = s_bar;
-        const int nsel = s_nsel;
+        const int bar = uni(s_bar);
+        const int nsel = uni(s_nsel);
         // ---- execution ----
         if (bar == 0 && stype[wpos[0]] == T_BIG_RANDOM) {
             block_solo(c, sk[wpos[0]], sm, tid, nt);
