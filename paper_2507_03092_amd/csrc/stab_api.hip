@@ -297,7 +297,14 @@ int tcollect(stab_ctx* ctx)
     return STAB_OK;
 }
 
-// The chain and the replay instantiated for the row's words per lane.
+// The classify/product pass, the chain and the replay instantiated for the row's words per lane.
+using DetFn = decltype(&k_det<1>);
+static DetFn det_kernel(int Wc)
+{
+    const int wpl = (Wc + 63) / 64;
+    return wpl <= 1 ? k_det<1> : wpl == 2 ? k_det<2> : wpl == 3 ? k_det<3> : k_det<4>;
+}
+
 using ChainFn = decltype(&k_chain<1>);
 static ChainFn chain_kernel(int Wc)
 {
@@ -566,7 +573,10 @@ int create_ctx(int32_t n, int32_t shots, int32_t mode, uint64_t seed, uint64_t f
     (void)hipFuncSetAttribute((const void*)k_chain<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_chain<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_chain<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void*)k_det, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_det<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_det<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_det<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_det<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void*)k_replay<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -951,7 +961,7 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
             // classes of the targets and the outcomes of the deterministic ones (also clears ran)
             const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
             const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
-            TIMED(ctx, 3, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+            TIMED(ctx, 3, (det_kernel(g.Wc)<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
                                                                        obuf, ran, ctx->d_err, ctx->d_counters, 0, nullptr)));
             // a layer where nothing ran in an earlier execution from |0...0>: the next four
             // launches would return at once
@@ -986,7 +996,7 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
                                            ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
             // targets the chain found deterministic: reduced in parallel on the final tableau
-            TIMED(ctx, 4, (k_det<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+            TIMED(ctx, 4, (det_kernel(g.Wc)<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
                                                                        obuf, ran, ctx->d_err, ctx->d_counters, 1,
                                                                        learn_mran ? P->d_mran + st.second : nullptr)));
             }

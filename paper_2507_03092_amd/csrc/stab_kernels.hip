@@ -598,6 +598,8 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 constexpr int kDetTargets = 8;                 // targets (waves) per block
 constexpr int kDetRowBatch = 3;                // rows a wave loads at once
 
+// WPL = ceil(Wc / 64): column words (and stabilizer bands) a lane holds of a row.
+template <int WPL>
 __global__ void __launch_bounds__(64 * kDetTargets) __attribute__((amdgpu_waves_per_eu(4)))
 k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
       const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
@@ -605,7 +607,7 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
       unsigned long long* __restrict__ counters, int pass, int* __restrict__ ran_log)
 {
     extern __shared__ uint64_t dsm[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k0 = blk_x(g) * kDetTargets, k = k0 + wave;
     const int s = blk_y(g);
     const int NB = g.NB, nrdw = (g.bpc + 63) >> 6;
@@ -652,16 +654,16 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         const uint64_t* tb = tab + (size_t)s * 2 * g.NR * g.RS;
         const uint64_t* rsc = rs + (size_t)s * NB;
         // the column: destabilizer words cd, stabilizer words cs (band lane + 64 u of each half)
-        uint64_t cd[kMaxStabBandsPerLane], cs[kMaxStabBandsPerLane];
+        uint64_t cd[WPL], cs[WPL];
 #pragma unroll
-        for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+        for (int u = 0; u < WPL; ++u) {
             const int w = lane + 64 * u;
             cd[u] = w < g.Wr ? colw[wave * NB + w] : 0ull;
             cs[u] = w < g.Wr && pass == 0 ? colw[wave * NB + g.Wr + w] : 0ull;
         }
         if (pass == 0) {
 #pragma unroll
-            for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+            for (int u = 0; u < WPL; ++u) {
                 const uint64_t m = __ballot(cs[u] != 0ull);
                 if (m) {
                     const int l = ctz64(m);
@@ -673,10 +675,10 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         if (lane == 0) cls[s * K + k] = pass == 0 ? -1 : -3;
         for (int u = lane; u < nrdw; u += 64) parw[u] = 0;
         const uint64_t* base = tb + (size_t)g.NR * g.RS;
-        int jc[kMaxWordsPerLane];
-        uint64_t msk[kMaxWordsPerLane], sx[kMaxWordsPerLane], sz[kMaxWordsPerLane], cr[kMaxWordsPerLane];
+        int jc[WPL];
+        uint64_t msk[WPL], sx[WPL], sz[WPL], cr[WPL];
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        for (int t = 0; t < WPL; ++t) {
             const int j = lane + 64 * t;
             jc[t] = j < g.Wc ? j : 0;
             msk[t] = j < g.Wc ? ~0ull : 0ull;
@@ -685,24 +687,59 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         int G = 0, rsum = 0, cnt = 0, nc = 0, myrow = 0;
         // multiply the nc listed rows (lane c holds the c-th) into S, and their shot sign bits
         auto flush = [&]() {
-            rsum += __popcll(__ballot(lane < nc && ((rsc[g.Wr + (myrow >> 6)] >> (myrow & 63)) & 1ull)));
-            for (int u0 = 0; u0 < nc; u0 += kDetRowBatch) {
-                uint64_t rx[kDetRowBatch][kMaxWordsPerLane], rz[kDetRowBatch][kMaxWordsPerLane];
+            // nothing below depends on a row's contents except the product itself, so with
+            // one-word rows the first batch of rows, the listed rows' shared sign words and the
+            // shots' sign words are requested together: one round trip instead of three.  With
+            // wider rows the registers that holds cost more occupancy than the round trips save
+            // (d=71: 71 -> 90 VGPRs and the pass 18 % slower), so they go one after another.
+            uint64_t rx[kDetRowBatch][WPL], rz[kDetRowBatch][WPL];
+            auto load = [&](int u0) {
 #pragma unroll
                 for (int u = 0; u < kDetRowBatch; ++u) {
                     const int i = __shfl(myrow, min(u0 + u, nc - 1), 64);
                     const uint64_t* row = base + (size_t)i * g.RS;
 #pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    for (int t = 0; t < WPL; ++t) {
                         rx[u][t] = row[jc[t]];
                         rz[u][t] = row[g.Wc + jc[t]];
                     }
                 }
+            };
+            auto parity = [&]() {
+                for (int b0 = 0; b0 < g.bpc; b0 += 64) {
+                    const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b0 + lane, g.bpc - 1)) * g.NB + g.Wr;
+                    int par = 0;
+                    for (int c = 0; c < nc; c += 8) {
+                        int iu[8];
+                        uint64_t wv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
+                    }
+                    const uint64_t pb = __ballot(par & 1);
+                    if (lane == 0) parw[b0 >> 6] ^= pb;
+                }
+            };
+            uint64_t rsw;
+            if (WPL == 1) {
+                load(0);
+                rsw = rsc[g.Wr + ((lane < nc ? myrow : 0) >> 6)];
+                parity();
+            } else {
+                rsw = rsc[g.Wr + ((lane < nc ? myrow : 0) >> 6)];
+            }
+            rsum += __popcll(__ballot(lane < nc && ((rsw >> (myrow & 63)) & 1ull)));
+            for (int u0 = 0; u0 < nc; u0 += kDetRowBatch) {
+                if (u0 > 0 || WPL != 1) load(u0);
 #pragma unroll
                 for (int u = 0; u < kDetRowBatch; ++u) {
                     if (u0 + u >= nc) break;
 #pragma unroll
-                    for (int t = 0; t < kMaxWordsPerLane; ++t) {
+                    for (int t = 0; t < WPL; ++t) {
                         const uint64_t a = rx[u][t] & msk[t], b = rz[u][t] & msk[t];
                         cr[t] ^= b & sx[t];
                         G += __popcll(a & b);
@@ -711,28 +748,12 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
                     }
                 }
             }
-            for (int b0 = 0; b0 < g.bpc; b0 += 64) {
-                const uint64_t* rdb = rd + (size_t)(s * g.bpc + min(b0 + lane, g.bpc - 1)) * g.NB + g.Wr;
-                int par = 0;
-                for (int c = 0; c < nc; c += 8) {
-                    int iu[8];
-                    uint64_t wv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) iu[u] = __shfl(myrow, min(c + u, nc - 1), 64);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) wv[u] = rdb[iu[u] >> 6];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (c + u < nc) par ^= (int)((wv[u] >> (iu[u] & 63)) & 1ull);
-                }
-                const uint64_t pb = __ballot(par & 1);
-                if (lane == 0) parw[b0 >> 6] ^= pb;
-            }
+            if (WPL != 1) parity();
             cnt += nc;
             nc = 0;
         };
 #pragma unroll
-        for (int u = 0; u < kMaxStabBandsPerLane; ++u) {
+        for (int u = 0; u < WPL; ++u) {
             uint64_t lanes = __ballot(cd[u] != 0ull);
             while (lanes) {
                 const int l = ctz64(lanes);
@@ -750,7 +771,7 @@ k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
         if (nc) flush();
         uint64_t xres = 0;
 #pragma unroll
-        for (int t = 0; t < kMaxWordsPerLane; ++t) {
+        for (int t = 0; t < WPL; ++t) {
             G += 2 * __popcll(cr[t]) - __popcll(sx[t] & sz[t]);
             xres |= sx[t];
         }
@@ -1562,12 +1583,12 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             const int* rw = srows + sl * kRCap;
             const int mine = (rounds << 7) | (127 - t);
             if (elig)
-                for (int r = 0; r <= cnt; ++r) atomicMax(&owner[r < cnt ? rw[r] % g.NR : pv], mine);
+                for (int r = 0; r <= cnt; ++r) atomicMax(&owner[r < cnt ? rw[r] - g.NR : pv], mine);
             __builtin_amdgcn_wave_barrier();
             bool ok = elig;
             if (elig)
                 for (int r = 0; r <= cnt && ok; ++r)
-                    if (owner[r < cnt ? rw[r] % g.NR : pv] != mine) ok = false;
+                    if (owner[r < cnt ? rw[r] - g.NR : pv] != mine) ok = false;
             const uint64_t selm = __ballot(ok);
             if (t < nw) wsel[t] = ok ? 1 : 0;
             if (ok) atomicOr(&pbit[pv >> 5], 1u << (pv & 31));
@@ -1575,7 +1596,7 @@ k_chain(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs, uint64_t*
             bool st = false;
             if (!ok && cnt >= 0)
                 for (int r = 0; r <= cnt && !st; ++r) {
-                    const int q = r < cnt ? rw[r] % g.NR : pv;
+                    const int q = r < cnt ? rw[r] - g.NR : pv;
                     if ((pbit[q >> 5] >> (q & 31)) & 1u) st = true;
                 }
             __builtin_amdgcn_wave_barrier();
