@@ -959,9 +959,10 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
             const MeasPlan& m = P->meas[st.second];
             const int K2 = m.K;
             // classes of the targets and the outcomes of the deterministic ones (also clears ran)
-            const dim3 dgrid((K2 + kDetTargets - 1) / kDetTargets, g.S);
-            const size_t det_lds = (size_t)kDetTargets * (g.NB + (g.bpc + 63) / 64) * 8;
-            TIMED(ctx, 3, (det_kernel(g.Wc)<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+            const int dt = det_targets((g.Wc + 63) / 64);
+            const dim3 dgrid((K2 + dt - 1) / dt, g.S);
+            const size_t det_lds = (size_t)dt * (g.NB + (g.bpc + 63) / 64) * 8;
+            TIMED(ctx, 3, (det_kernel(g.Wc)<<<dgrid, 64 * dt, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
                                                                        obuf, ran, ctx->d_err, ctx->d_counters, 0, nullptr)));
             // a layer where nothing ran in an earlier execution from |0...0>: the next four
             // launches would return at once
@@ -996,7 +997,7 @@ int exec_enqueue(stab_ctx* ctx, stab_program* P, bool draw_all, bool use_mran, b
                                            ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, a)));
             }
             // targets the chain found deterministic: reduced in parallel on the final tableau
-            TIMED(ctx, 4, (det_kernel(g.Wc)<<<dgrid, 64 * kDetTargets, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
+            TIMED(ctx, 4, (det_kernel(g.Wc)<<<dgrid, 64 * dt, det_lds, ctx->stream>>>(g, ctx->tab, ctx->rs, ctx->rd, Xcol, K2, cls,
                                                                        obuf, ran, ctx->d_err, ctx->d_counters, 1,
                                                                        learn_mran ? P->d_mran + st.second : nullptr)));
             }

@@ -595,18 +595,21 @@ k_segment(Geom g, uint64_t* __restrict__ tab, uint64_t* __restrict__ rs,
 // the sign is the parity of each shot's sign bits over the same rows; the bits of a shot group
 // of 64 gather in LDS (nrdw words per wave).
 // ------------------------------------------------------------------------------------------
-constexpr int kDetTargets = 8;                 // targets (waves) per block
+// targets (waves) per block: four with one-word rows (small tableaux: more blocks in flight),
+// eight otherwise (a band's eight column words are one coalesced 64-byte read)
+constexpr int det_targets(int wpl) { return wpl == 1 ? 4 : 8; }
 constexpr int kDetRowBatch = 3;                // rows a wave loads at once
 
 // WPL = ceil(Wc / 64): column words (and stabilizer bands) a lane holds of a row.
 template <int WPL>
-__global__ void __launch_bounds__(64 * kDetTargets) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64 * det_targets(WPL)) __attribute__((amdgpu_waves_per_eu(4)))
 k_det(Geom g, const uint64_t* __restrict__ tab, const uint64_t* __restrict__ rs,
       const uint64_t* __restrict__ rd, const uint64_t* __restrict__ Xcol, int K, int* __restrict__ cls,
       uint8_t* __restrict__ obuf, int* __restrict__ ran, int* __restrict__ err,
       unsigned long long* __restrict__ counters, int pass, int* __restrict__ ran_log)
 {
     extern __shared__ uint64_t dsm[];
+    constexpr int kDetTargets = det_targets(WPL);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k0 = blk_x(g) * kDetTargets, k = k0 + wave;
     const int s = blk_y(g);
